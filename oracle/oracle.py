@@ -1,0 +1,316 @@
+"""ctypes front end of the oracle (TEST INFRASTRUCTURE ONLY).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this module.  It loads oracle/libchx_oracle.so (built by
+oracle/build.py with gcc, no FMA contraction) and exposes the plain FP64
+reference: the systems of the paper's Examples section, the Yoshida-4 step
+with its tangent map, and the per-orbit chaos-indicator driver (SALI, GALI_k,
+Lyapunov spectrum by modified Gram-Schmidt QR, Lagrangian-descriptor
+M-function, energy error) with resumable state.
+"""
+import ctypes as C
+import os
+from concurrent.futures import ThreadPoolExecutor
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import build as _build
+
+SYS_HENON_HEILES = 1
+SYS_FPUT = 2
+SYS_QUARTIC = 3
+SYS_HARMONIC = 4
+
+IND_SALI = 1
+IND_GALI = 2
+IND_LYAP = 4
+IND_LD = 8
+IND_ENERGY = 16
+
+ST_OK, ST_MASKED, ST_ESCAPED, ST_NONFINITE, ST_EXITED = 0, 1, 2, 3, 4
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.LIB
+        if not os.path.exists(path):
+            _build.build()
+        L = C.CDLL(path)
+        d, i, i64, u32 = C.c_double, C.c_int, C.c_int64, C.c_uint32
+        P = C.c_void_p
+        L.ora_potential.restype = d
+        L.ora_potential.argtypes = [i, i, P, P]
+        L.ora_hamiltonian.restype = d
+        L.ora_hamiltonian.argtypes = [i, i, P, P]
+        for f in (L.ora_grad, L.ora_hess):
+            f.restype = None
+            f.argtypes = [i, i, P, P, P]
+        L.ora_yoshida_coefficients.argtypes = [P, P]
+        L.ora_step.argtypes = [i, i, P, d, P, P, i]
+        L.ora_state_len.restype = i64
+        L.ora_state_len.argtypes = [i, i, i]
+        L.ora_init.restype = i
+        L.ora_init.argtypes = [i, i, P, P, P, P, i64, i, i, u32, d, P]
+        L.ora_advance.restype = i
+        L.ora_advance.argtypes = [i, i, P, P, i64, i, i, u32, d, i64, i64, i64, i, d, d,
+                                  i, d]
+        L.ora_finalize.restype = i
+        L.ora_finalize.argtypes = [i, P, i64, i, i, u32, i, d] + [P] * 12
+        L.ora_gali.argtypes = [i, i, P, i, P]
+        L.ora_mgs.argtypes = [i, i, P, P]
+        L.ora_hh_grid.argtypes = [d, d, d, i, d, d, i, P, P]
+        L.ora_hh_points.argtypes = [d, P, P, i64, P, P]
+        L.ora_fput_ic.argtypes = [i, P, P, i64, P]
+        L.ora_quartic_ic.argtypes = [i, P, P, i64, P]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+@dataclass
+class System:
+    kind: int
+    ndof: int
+    params: tuple = ()
+
+    def parr(self):
+        return np.ascontiguousarray(np.asarray(self.params if self.params else [0.0],
+                                               dtype=np.float64))
+
+
+def henon_heiles():
+    return System(SYS_HENON_HEILES, 2, ())
+
+
+def fput(N, k=1.0, alpha=0.0, beta=1.0):
+    return System(SYS_FPUT, N, (k, alpha, beta))
+
+
+def quartic(N=3, eps=0.1):
+    return System(SYS_QUARTIC, N, (eps,))
+
+
+def harmonic(omegas):
+    return System(SYS_HARMONIC, len(omegas), tuple(float(w) for w in omegas))
+
+
+# --- systems ---------------------------------------------------------------
+
+def potential(sys, q):
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    pr = sys.parr()
+    return lib().ora_potential(sys.kind, sys.ndof, _p(pr), _p(q))
+
+
+def hamiltonian(sys, x):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    pr = sys.parr()
+    return lib().ora_hamiltonian(sys.kind, sys.ndof, _p(pr), _p(x))
+
+
+def grad(sys, q):
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    g = np.zeros(sys.ndof)
+    pr = sys.parr()
+    lib().ora_grad(sys.kind, sys.ndof, _p(pr), _p(q), _p(g))
+    return g
+
+
+def hess(sys, q):
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    h = np.zeros((sys.ndof, sys.ndof))
+    pr = sys.parr()
+    lib().ora_hess(sys.kind, sys.ndof, _p(pr), _p(q), _p(h))
+    return h
+
+
+def yoshida_coefficients():
+    c = np.zeros(3)
+    d = np.zeros(4)
+    lib().ora_yoshida_coefficients(_p(c), _p(d))
+    return c, d
+
+
+def step(sys, dt, x, w=None, nsteps=1):
+    """Apply nsteps Yoshida-4 KDK steps to a copy of x[2N] (and w[m][2N])."""
+    x = np.array(x, dtype=np.float64)
+    m = 0 if w is None else len(w)
+    w = np.zeros((0, 2 * sys.ndof)) if w is None else np.array(w, dtype=np.float64)
+    pr = sys.parr()
+    for _ in range(nsteps):
+        lib().ora_step(sys.kind, sys.ndof, _p(pr), dt, _p(x), _p(w), m)
+    return (x, w) if m else x
+
+
+def mgs(w):
+    w = np.array(w, dtype=np.float64)
+    m, dim = w.shape
+    rd = np.zeros(m)
+    lib().ora_mgs(dim, m, _p(w), _p(rd))
+    return w, rd
+
+
+def gali(w, kmax):
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    m, dim = w.shape
+    out = np.zeros(kmax - 1)
+    lib().ora_gali(dim, m, _p(w), kmax, _p(out))
+    return out
+
+
+# --- driver ----------------------------------------------------------------
+
+def n_steps_for(T, dt):
+    """Number of steps n = round(T/dt); T/dt must be integral to 1e-9 relative."""
+    r = T / dt
+    n = int(round(r))
+    if n < 1 or abs(r - n) > 1e-9 * n:
+        raise ValueError("T/dt must be a positive integer (to 1e-9 relative)")
+    return n
+
+
+@dataclass
+class Run:
+    """Everything one integration needs besides the initial conditions."""
+    dt: float
+    T: float
+    indicators: int
+    K: int = 10
+    n_lyap: int = 0
+    gali_kmax: int = 0
+    ld_p: float = 0.5
+    sali_threshold: float = 1e-8
+    early_exit: bool = False
+    escape_r2: float = 0.0
+    m_s: int = field(default=-1)
+
+    def __post_init__(self):
+        if self.m_s < 0:
+            ms = 0
+            if self.indicators & IND_SALI:
+                ms = 2
+            if self.indicators & IND_GALI:
+                ms = max(ms, self.gali_kmax)
+            self.m_s = ms
+        if not (self.indicators & IND_LYAP):
+            self.n_lyap = 0
+
+
+class State:
+    """Resumable per-orbit oracle state: [n][len] doubles."""
+
+    def __init__(self, sys, run, x0, w0=None, mask=None):
+        self.sys, self.run = sys, run
+        x0 = np.ascontiguousarray(x0, dtype=np.float64).reshape(-1, 2 * sys.ndof)
+        self.n = len(x0)
+        self.len = lib().ora_state_len(sys.ndof, run.m_s, run.n_lyap)
+        self.buf = np.zeros((self.n, self.len))
+        if run.m_s:
+            w0 = np.ascontiguousarray(w0, dtype=np.float64).reshape(
+                self.n, run.m_s, 2 * sys.ndof)
+        else:
+            w0 = None
+        mask = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+        pr = sys.parr()
+        rc = lib().ora_init(sys.kind, sys.ndof, _p(pr), _p(x0), _p(w0), _p(mask), self.n,
+                            run.m_s, run.n_lyap, run.indicators, run.ld_p, _p(self.buf))
+        if rc:
+            raise ValueError("ora_init failed")
+        self.s_done = 0
+        self.n_total = n_steps_for(run.T, run.dt)
+
+    def advance(self, s_end, threads=1):
+        run, sys = self.run, self.sys
+        s_end = min(s_end, self.n_total)
+        pr = sys.parr()
+
+        def work(lo, hi):
+            sub = self.buf[lo:hi]
+            assert sub.flags.c_contiguous
+            rc = lib().ora_advance(sys.kind, sys.ndof, _p(pr), _p(sub), hi - lo, run.m_s,
+                                   run.n_lyap, run.indicators, run.dt, self.s_done, s_end,
+                                   self.n_total, run.K, run.ld_p, run.sali_threshold,
+                                   int(run.early_exit), run.escape_r2)
+            if rc:
+                raise RuntimeError("ora_advance failed (%d)" % rc)
+
+        _parallel(work, self.n, threads)
+        self.s_done = s_end
+
+    def finalize(self):
+        run, sys, n, N2 = self.run, self.sys, self.n, 2 * self.sys.ndof
+        o = dict(
+            x_final=np.zeros((n, N2)), t_end=np.zeros(n),
+            status=np.zeros(n, np.int32), label=np.zeros(n, np.int8),
+            sali_final=np.zeros(n), sali_min=np.zeros(n), t_chaos=np.zeros(n),
+            gali=np.zeros((n, max(run.gali_kmax - 1, 0))),
+            lyap=np.zeros((n, run.n_lyap)), ld=np.zeros(n), energy_err=np.zeros(n),
+            ln_growth=np.zeros((n, run.m_s)))
+        keys = ["x_final", "t_end", "status", "label", "sali_final", "sali_min", "t_chaos",
+                "gali", "lyap", "ld", "energy_err", "ln_growth"]
+        kmax = run.gali_kmax if run.indicators & IND_GALI else 0
+        lib().ora_finalize(sys.ndof, _p(self.buf), n, run.m_s, run.n_lyap, run.indicators,
+                           kmax, run.sali_threshold, *[_p(o[k]) for k in keys])
+        if not kmax:
+            o["gali"] = np.zeros((n, 0))
+        return o
+
+
+def _parallel(fn, n, threads):
+    if threads <= 1 or n < 2:
+        fn(0, n)
+        return
+    chunks = np.linspace(0, n, min(threads, n) + 1).astype(int)
+    with ThreadPoolExecutor(max_workers=len(chunks) - 1) as ex:
+        futs = [ex.submit(fn, int(a), int(b)) for a, b in zip(chunks[:-1], chunks[1:])]
+        for f in futs:
+            f.result()
+
+
+def integrate(sys, x0, run, w0=None, mask=None, threads=1):
+    st = State(sys, run, x0, w0, mask)
+    st.advance(st.n_total, threads=threads)
+    return st.finalize()
+
+
+# --- inputs ----------------------------------------------------------------
+
+def hh_grid(E, ny, npy, y0=-0.4, y1=0.7, py0=-0.45, py1=0.45):
+    x0 = np.zeros((ny * npy, 4))
+    mask = np.zeros(ny * npy, np.uint8)
+    lib().ora_hh_grid(E, y0, y1, ny, py0, py1, npy, _p(x0), _p(mask))
+    return x0, mask
+
+
+def hh_points(E, y, py):
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    py = np.ascontiguousarray(py, dtype=np.float64)
+    n = len(y)
+    x0 = np.zeros((n, 4))
+    mask = np.zeros(n, np.uint8)
+    lib().ora_hh_points(E, _p(y), _p(py), n, _p(x0), _p(mask))
+    return x0, mask
+
+
+def fput_ic(sys, u):
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1, 5)
+    x0 = np.zeros((len(u), 2 * sys.ndof))
+    pr = sys.parr()
+    lib().ora_fput_ic(sys.ndof, _p(pr), _p(u), len(u), _p(x0))
+    return x0
+
+
+def quartic_ic(sys, draws):
+    draws = np.ascontiguousarray(draws, dtype=np.float64).reshape(-1, 2 * sys.ndof + 1)
+    x0 = np.zeros((len(draws), 2 * sys.ndof))
+    pr = sys.parr()
+    lib().ora_quartic_ic(sys.ndof, _p(pr), _p(draws), len(draws), _p(x0))
+    return x0
+
