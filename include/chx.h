@@ -1,0 +1,221 @@
+/*
+ * chx.h -- C ABI of libchx: MI355X (gfx950) ensemble integration of
+ * Hamiltonian systems with their variational equations, accumulating chaos
+ * indicators (arXiv 2507.00622, "Chaoticus").
+ *
+ * The paper's statement of the problem (Functionalities section): integrate
+ * the ODE system derived from a Hamiltonian for many initial conditions and
+ * compute indicators that classify each trajectory.  Deviation vectors obey
+ * the variational equations (Statement of need), so the library needs the
+ * potential, its gradient and its Hessian: they are built in for the
+ * systems of the Examples section (Henon-Heiles; the Fermi-Pasta-Ulam chain
+ * with fixed ends) and two test systems (coupled quartic oscillator,
+ * uncoupled harmonic oscillators).
+ *
+ * Integrator: fixed-step fourth-order symplectic composition (Yoshida, Phys.
+ * Lett. A 150 (1990) 262) of kick-drift-kick leapfrog; deviation vectors are
+ * propagated by the exact tangent map of the step.  All arithmetic on the
+ * trajectory and the deviation vectors is IEEE binary64.
+ *
+ * Conventions shared by every entry point
+ *   - Phase-space points are x = (q_1..q_N, p_1..p_N), N = ndof; arrays of
+ *     points are row-major [n][2N].
+ *   - n = 0 is a no-op returning CHX_OK.
+ *   - Every argument is validated before any device work; on a non-OK
+ *     status nothing is written to any output and chx_last_error() returns a
+ *     message (thread-local, valid until the next call on that thread).
+ *   - Ownership: the caller allocates every input and output; the library
+ *     keeps no caller pointer after returning (an ensemble handle keeps
+ *     copies of what it needs).
+ *   - Host pointers (flags without CHX_PTR_DEVICE): the call is synchronous.
+ *     Device pointers (CHX_PTR_DEVICE): every pointer argument is device
+ *     memory, work is ordered on `stream` (a hipStream_t, NULL = the null
+ *     stream) and the caller keeps the buffers alive until the stream has
+ *     synchronised.  The system's params pointer is always host memory.
+ *   - Per-orbit problems (escape, non-finite state) are not call errors:
+ *     they are reported in the per-orbit status and label.
+ */
+#ifndef CHX_H
+#define CHX_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CHX_OK = 0,
+  CHX_ERR_INVALID_ARG = 1,
+  CHX_ERR_UNSUPPORTED = 2,
+  CHX_ERR_OUT_OF_MEMORY = 3,
+  CHX_ERR_DEVICE = 4,
+  CHX_ERR_INTERNAL = 5
+} chx_status;
+
+/* Built-in systems (separable, H = |p|^2/2 + V(q)). */
+enum {
+  CHX_SYS_HENON_HEILES = 1, /* Examples section, Henon-Heiles Hamiltonian:
+                               V = (x^2+y^2)/2 + x^2 y - y^3/3; ndof = 2, no params */
+  CHX_SYS_FPUT = 2,         /* Examples section, FPU Hamiltonian with fixed ends
+                               q_0 = q_{N+1} = 0 and N+1 springs:
+                               V = sum_j k d^2/2 + alpha d^3/3 + beta d^4/4,
+                               d_j = q_j - q_{j-1}; params {k, alpha, beta};
+                               ndof 2..16 */
+  CHX_SYS_QUARTIC = 3,      /* V = sum q_i^4/4 + eps sum_{i<j} q_i^2 q_j^2;
+                               params {eps}; ndof 1..3 */
+  CHX_SYS_HARMONIC = 4      /* V = sum omega_i^2 q_i^2 / 2; params {omega_i};
+                               ndof 1..3 */
+};
+
+typedef struct {
+  int32_t kind;         /* CHX_SYS_* */
+  int32_t ndof;         /* N; phase-space dimension 2N */
+  const double *params; /* host memory, nparams values (see above) */
+  int32_t nparams;
+} chx_system;
+
+/* Indicator bits (Functionalities section). */
+enum {
+  CHX_IND_SALI = 1,   /* SALI of two unit deviation vectors */
+  CHX_IND_GALI = 2,   /* GALI_k, k = 2..gali_kmax (volume of k unit vectors) */
+  CHX_IND_LYAP = 4,   /* Lyapunov spectrum by periodic QR (modified Gram-Schmidt) */
+  CHX_IND_LD = 8,     /* Lagrangian-descriptor M-function, forward in time */
+  CHX_IND_ENERGY = 16 /* max |H(t) - H(0)| over checkpoints */
+};
+
+/* Option flags. */
+enum { CHX_PTR_DEVICE = 1 };
+
+/* Per-orbit status. */
+enum {
+  CHX_ORBIT_OK = 0,
+  CHX_ORBIT_MASKED = 1,    /* mask[i] == 0: not integrated */
+  CHX_ORBIT_ESCAPED = 2,   /* |q|^2 > escape_r2 at a checkpoint: stopped there */
+  CHX_ORBIT_NONFINITE = 3, /* non-finite state at t = 0 or at a checkpoint */
+  CHX_ORBIT_EXITED = 4     /* early exit: SALI < threshold at a checkpoint */
+};
+
+typedef struct {
+  double dt;              /* step, > 0 */
+  double T;               /* final time; T/dt integral to 1e-9 relative */
+  uint32_t indicators;    /* CHX_IND_* bits */
+  int32_t renorm_every;   /* K: checkpoint every K steps and at the last step
+                             (renormalisation, SALI, QR, checks); 0 -> 10 */
+  int32_t n_lyap;         /* Lyapunov vectors 1..2N; 0 -> 2N */
+  int32_t gali_kmax;      /* 2..2N; 0 -> 2 */
+  double ld_p;            /* LD exponent in (0, 1]; 0 -> 0.5 */
+  double sali_threshold;  /* chaotic iff min SALI < threshold; 0 -> 1e-8 */
+  int32_t early_exit;     /* non-zero: stop an orbit at its first checkpoint
+                             with SALI < threshold (needs CHX_IND_SALI) */
+  int32_t steps_per_launch; /* kernel launch granularity; 0 -> automatic */
+  uint64_t seed;          /* deviation vectors when w0 == NULL */
+  const double *w0;       /* optional [n][m_s][2N] initial SALI/GALI vectors
+                             (normalised at t = 0); m_s = max(2 if SALI,
+                             gali_kmax if GALI).  NULL -> Gaussian vectors
+                             from SplitMix64(seed) with Box-Muller, element
+                             (i, v, c) drawn at counter (i*m_s + v)*2N + c of
+                             stream 0 */
+  double escape_r2;       /* 0 = off */
+  uint32_t flags;         /* CHX_PTR_DEVICE */
+  int32_t block_size;     /* threads per block for the lane kernel; 0 -> tuned */
+  void *stream;           /* hipStream_t for CHX_PTR_DEVICE calls */
+} chx_options;
+
+/* Fills *o with dt = T = 0 (must be set) and all defaults above. */
+void chx_options_default(chx_options *o);
+
+/* Outputs; any NULL member is skipped.  Layouts are row-major per orbit. */
+typedef struct {
+  double *x_final;    /* [n][2N] state at t_end */
+  double *t_end;      /* [n] time of the last checkpoint reached */
+  int32_t *status;    /* [n] CHX_ORBIT_* */
+  int8_t *label;      /* [n] -1 masked, 0 regular, 1 chaotic (min SALI <
+                         threshold), 2 escaped, 3 non-finite; needs SALI */
+  double *sali_final; /* [n] SALI at t_end */
+  double *sali_min;   /* [n] min SALI over checkpoints */
+  double *t_chaos;    /* [n] first checkpoint time with SALI < threshold, NaN if none */
+  double *gali;       /* [n][gali_kmax - 1] GALI_2..GALI_kmax at t_end */
+  double *lyap;       /* [n][n_lyap] finite-time exponents at t_end, QR order */
+  double *ld;         /* [n] M-function over [0, t_end] */
+  double *energy_err; /* [n] max |H - H(0)| */
+  double *ln_growth;  /* [n][m_s] sum of ln |w_v| over renormalisations */
+} chx_result;
+
+/* Whole-ensemble integration (Functionalities section: the solvers with
+ * deviation-vector normalisation and QR, plus SALI, GALI and LD).
+ * x0: [n][2N] initial conditions; mask: [n] (0 = skip) or NULL. */
+chx_status chx_integrate_ensemble(const chx_system *sys, const double *x0,
+                                  const uint8_t *mask, int64_t n,
+                                  const chx_options *opt, chx_result *res);
+
+/* Host-pointer convenience calls (synchronous). */
+/* SALI (Functionalities section) with two seeded unit vectors, K = 10:
+ * min SALI over checkpoints and the label (0 regular, 1 chaotic at 1e-8). */
+chx_status chx_sali(const chx_system *sys, const double *x0, int64_t n, double dt,
+                    double T, uint64_t seed, double *sali_min_out, int8_t *label_out);
+/* GALI_k, k = 2..kmax, of kmax seeded unit vectors renormalised every 10
+ * steps (Functionalities section: GALI from the singular values). */
+chx_status chx_gali(const chx_system *sys, const double *x0, int64_t n, double dt,
+                    double T, int32_t kmax, uint64_t seed,
+                    double *gali_out /* [n][kmax-1] */);
+/* First n_exp Lyapunov exponents by QR every renorm_every steps
+ * (Functionalities section: Lyapunov spectrum via QR factorisation). */
+chx_status chx_lyap_spectrum(const chx_system *sys, const double *x0, int64_t n,
+                             double dt, double T, int32_t n_exp, int32_t renorm_every,
+                             double *lyap_out /* [n][n_exp] */);
+/* Lagrangian-descriptor M-function int_0^T sum_i |dx_i/dt|^p dt (Summary and
+ * Functionalities sections; trapezoid rule on the step endpoints). */
+chx_status chx_ld(const chx_system *sys, const double *x0, int64_t n, double dt,
+                  double T, double p, double *ld_out /* [n] */);
+
+/* Resumable ensemble: checkpoint/resume and chunked launches.  create
+ * validates and uploads (no steps); advance integrates up to step s_end,
+ * which must be a checkpoint step (a multiple of K, or the last step);
+ * results may be read at any checkpoint.  Splitting a run at checkpoints
+ * gives results bit-identical to one call. */
+typedef struct chx_ensemble chx_ensemble;
+chx_status chx_ensemble_create(const chx_system *sys, const double *x0,
+                               const uint8_t *mask, int64_t n, const chx_options *opt,
+                               chx_ensemble **out);
+chx_status chx_ensemble_advance(chx_ensemble *e, int64_t s_end);
+chx_status chx_ensemble_results(chx_ensemble *e, chx_result *res);
+/* n_total steps, steps done, orbits actually integrated (unmasked). */
+chx_status chx_ensemble_info(const chx_ensemble *e, int64_t *n_total, int64_t *s_done,
+                             int64_t *n_active);
+void chx_ensemble_destroy(chx_ensemble *e);
+
+/* Initial-condition assembly. */
+/* Henon-Heiles surface of section x = 0 at energy E (Examples section):
+ * y_i = y0 + (y1-y0) i/(ny-1), p_y,j likewise, index j*ny + i;
+ * p_x = +sqrt(2E - p_y^2 - y^2 + 2y^3/3), mask = 0 where the root's
+ * argument is negative (p_x written as 0).  x0_out [ny*npy][4], mask_out. */
+chx_status chx_grid_hh_section(double E, double y0, double y1, int32_t ny, double py0,
+                               double py1, int32_t npy, double *x0_out,
+                               uint8_t *mask_out, uint32_t flags, void *stream);
+/* Same for given (y, p_y) lists of length n. */
+chx_status chx_hh_section_points(double E, const double *y, const double *py, int64_t n,
+                                 double *x0_out, uint8_t *mask_out, uint32_t flags,
+                                 void *stream);
+/* FPU chain with its energy in the two lowest normal modes of the fixed-end
+ * linear chain: u [n][5] uniforms in [0,1): E = 0.1 + 9.9 u0, amplitudes
+ * u1, u2, phases 2 pi u3, 2 pi u4; scaled so that H = E. */
+chx_status chx_ic_fput_modes(const chx_system *sys, const double *u, int64_t n,
+                             double *x0_out, uint32_t flags, void *stream);
+/* Coupled quartic oscillator at H = 1 from draws [n][2N+1]: Gaussian
+ * position and momentum directions and a potential fraction f in (0,1). */
+chx_status chx_ic_quartic(const chx_system *sys, const double *draws, int64_t n,
+                          double *x0_out, uint32_t flags, void *stream);
+
+/* Message for the last non-OK status on this thread ("" if none). */
+const char *chx_last_error(void);
+/* Library version string. */
+const char *chx_version(void);
+/* sizeof(chx_system), sizeof(chx_options), sizeof(chx_result) for which =
+ * 0, 1, 2 (0 otherwise): lets a binding check its struct layouts. */
+size_t chx_struct_size(int32_t which);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,40 @@
+// System dispatch of the lane-per-orbit kernels.
+#include "chx_internal.h"
+
+namespace chx {
+hipError_t launch_lane_hh(int M, const StepArgs &a, int block, hipStream_t s);
+hipError_t launch_lane_quartic1(int M, const StepArgs &a, int block, hipStream_t s);
+hipError_t launch_lane_quartic2(int M, const StepArgs &a, int block, hipStream_t s);
+hipError_t launch_lane_quartic3(int M, const StepArgs &a, int block, hipStream_t s);
+hipError_t launch_lane_harmonic1(int M, const StepArgs &a, int block, hipStream_t s);
+hipError_t launch_lane_harmonic2(int M, const StepArgs &a, int block, hipStream_t s);
+hipError_t launch_lane_harmonic3(int M, const StepArgs &a, int block, hipStream_t s);
+
+bool lane_supported(int sys, int ndof, int M) {
+  if (M < 0 || M > 4 * ndof) return false;
+  switch (sys) {
+  case SYS_HH: return ndof == 2;
+  case SYS_QUARTIC:
+  case SYS_HARMONIC: return ndof >= 1 && ndof <= 3;
+  }
+  return false;
+}
+
+hipError_t launch_lane(int sys, int ndof, int M, const StepArgs &a, int block,
+                       hipStream_t s) {
+  if (!lane_supported(sys, ndof, M)) return hipErrorInvalidValue;
+  if (a.n == 0) return hipSuccess;
+  switch (sys) {
+  case SYS_HH: return launch_lane_hh(M, a, block, s);
+  case SYS_QUARTIC:
+    return ndof == 1 ? launch_lane_quartic1(M, a, block, s)
+         : ndof == 2 ? launch_lane_quartic2(M, a, block, s)
+                     : launch_lane_quartic3(M, a, block, s);
+  case SYS_HARMONIC:
+    return ndof == 1 ? launch_lane_harmonic1(M, a, block, s)
+         : ndof == 2 ? launch_lane_harmonic2(M, a, block, s)
+                     : launch_lane_harmonic3(M, a, block, s);
+  }
+  return hipErrorInvalidValue;
+}
+}  // namespace chx

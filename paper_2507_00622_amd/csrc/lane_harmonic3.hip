@@ -1,0 +1,9 @@
+// Lane-per-orbit kernels for 3 uncoupled harmonic oscillator(s): up to
+// 12 deviation vectors.
+#include "lane_kernel.h"
+
+namespace chx {
+hipError_t launch_lane_harmonic3(int M, const StepArgs &a, int block, hipStream_t s) {
+  return LaneDispatch<SysHarmonic<3>, 12>::go(M, a, block, s);
+}
+}  // namespace chx

@@ -1,0 +1,125 @@
+"""The C ABI on the CPU: the library loads, exports every function
+include/chx.h declares, and rejects invalid arguments before any device
+work (so these run without a GPU)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2507_00622_amd as P
+from paper_2507_00622_amd import chx
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "chx.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(chx_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_function():
+    L = chx.lib()
+    names = declared_functions()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(chx.EXPORTS) == names
+
+
+def test_struct_layouts_match_header():
+    L = chx.lib()
+    assert L.chx_struct_size(0) == C.sizeof(chx._System) == 24
+    assert L.chx_struct_size(1) == C.sizeof(chx._Options) == 96
+    assert L.chx_struct_size(2) == C.sizeof(chx._Result) == 12 * 8
+    assert L.chx_struct_size(3) == 0
+
+
+def test_options_default():
+    o = chx._Options()
+    chx.lib().chx_options_default(C.byref(o))
+    assert o.renorm_every == 10 and o.ld_p == 0.5 and o.sali_threshold == 1e-8
+    assert o.dt == 0 and o.flags == 0 and o.w0 is None
+
+
+def hh_x0(n=3):
+    return np.tile([0.0, 0.1, 0.45, 0.0], (n, 1))
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(dt=0.0, T=1.0), "dt"),
+    (dict(dt=0.01, T=-1.0), "T must"),
+    (dict(dt=0.03, T=1.0), "integer"),
+    (dict(dt=float("nan"), T=1.0), "dt"),
+])
+def test_bad_time_arguments(kw, msg):
+    with pytest.raises(chx.ChxError) as e:
+        chx.sali(P.henon_heiles(), hh_x0(), kw["dt"], kw["T"], 1)
+    assert e.value.status == chx.ERR_INVALID_ARG and msg in str(e.value)
+
+
+def test_bad_systems():
+    with pytest.raises(chx.ChxError, match="ndof == 2"):
+        chx.sali(chx.System(chx.SYS_HENON_HEILES, 3), np.zeros((2, 6)), 0.01, 1.0, 1)
+    with pytest.raises(chx.ChxError, match="unknown system"):
+        chx.sali(chx.System(9, 2), hh_x0(), 0.01, 1.0, 1)
+    with pytest.raises(chx.ChxError, match="params"):
+        chx.sali(chx.System(chx.SYS_FPUT, 4, (1.0,)), np.zeros((2, 8)), 0.01, 1.0, 1)
+    with pytest.raises(chx.ChxError, match="not finite"):
+        chx.sali(chx.quartic(3, float("inf")), np.zeros((2, 6)), 0.01, 1.0, 1)
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(indicators=64), "indicator"),
+    (dict(indicators=chx.IND_LYAP, n_lyap=5), "n_lyap"),
+    (dict(indicators=chx.IND_GALI, gali_kmax=5), "gali_kmax"),
+    (dict(indicators=chx.IND_LD, ld_p=1.5), "ld_p"),
+    (dict(indicators=chx.IND_LYAP, early_exit=True), "early_exit"),
+    (dict(indicators=chx.IND_SALI, renorm_every=-1), "renorm_every"),
+    (dict(indicators=chx.IND_SALI, block_size=96), "block_size"),
+    (dict(indicators=chx.IND_SALI, escape_r2=-1.0), "escape_r2"),
+    (dict(indicators=chx.IND_SALI, sali_threshold=-1.0), "sali_threshold"),
+])
+def test_bad_options(kw, msg):
+    with pytest.raises(chx.ChxError) as e:
+        chx.integrate_ensemble(P.henon_heiles(), hh_x0(), dt=0.01, T=1.0, **kw)
+    assert e.value.status == chx.ERR_INVALID_ARG and msg in str(e.value)
+
+
+def test_label_needs_sali():
+    with pytest.raises(chx.ChxError, match="label"):
+        o = chx.make_options(dt=0.01, T=1.0, indicators=chx.IND_LD)
+        res = chx._Result()
+        lab = np.zeros(3, np.int8)
+        res.label = lab.ctypes.data_as(C.c_void_p)
+        x0 = hh_x0()
+        cs = P.henon_heiles()._c()
+        chx._check(chx.lib().chx_integrate_ensemble(C.byref(cs), x0.ctypes.data_as(C.c_void_p),
+                                                    None, 3, C.byref(o), C.byref(res)))
+
+
+def test_empty_ensemble_is_a_noop():
+    out = chx.integrate_ensemble(P.henon_heiles(), np.zeros((0, 4)), dt=0.01, T=1.0,
+                                 indicators=chx.IND_SALI)
+    assert out["sali_min"].shape == (0,)
+
+
+def test_outputs_untouched_on_error():
+    smin = np.full(3, 7.0)
+    lab = np.full(3, 5, np.int8)
+    cs = P.henon_heiles()._c()
+    st = chx.lib().chx_sali(C.byref(cs), hh_x0().ctypes.data_as(C.c_void_p), 3, 0.0, 1.0, 1,
+                            smin.ctypes.data_as(C.c_void_p), lab.ctypes.data_as(C.c_void_p))
+    assert st == chx.ERR_INVALID_ARG
+    assert np.all(smin == 7.0) and np.all(lab == 5)
+    assert chx.lib().chx_last_error().decode() != ""
+
+
+def test_stream_without_device_flag_rejected():
+    with pytest.raises(chx.ChxError, match="stream"):
+        chx.lib()  # loaded
+        cs = chx._check(chx.lib().chx_grid_hh_section(0.125, -0.4, 0.7, 4, -0.45, 0.45, 4,
+                                                      None, None, 0, C.c_void_p(1)))
+        del cs
