@@ -27,32 +27,72 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64 = 78.6e12  # MI355X FP64 vector peak, FLOP/s (FMA = 2)
 
+# Sources of the benchmarked integration kernel: the HBM traffic recorded in
+# profiles/ applies only while their hash is the one recorded beside it.
+KERNEL_SOURCES = ["paper_2507_00622_amd/csrc/lane_kernel.h",
+                  "paper_2507_00622_amd/csrc/systems.h",
+                  "paper_2507_00622_amd/csrc/device_math.h",
+                  "paper_2507_00622_amd/csrc/chx_internal.h",
+                  "paper_2507_00622_amd/csrc/lane_hh.hip"]
+TRAFFIC_FILE = "profiles/lane_kernel_hh6_traffic.md"
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """HBM bytes per launch measured by rocprofv3 (FETCH_SIZE and WRITE_SIZE,
+    scaled by a plain copy), or None when the kernel changed since."""
+    try:
+        txt = open(os.path.join(ROOT, TRAFFIC_FILE)).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in txt.splitlines():
+        if ":" in line and line.strip().startswith(("kernel-source-sha256", "traffic-bytes-per-launch")):
+            k, v = line.strip().split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel-source-sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["traffic-bytes-per-launch"])
+    except (KeyError, ValueError):
+        return None
+
 
 def flops_per_step(N, m_s, n_l, ld, energy, sali, K, system="hh"):
     """Algorithmic FP64 flops of one orbit-step of the lane-per-orbit path
-    (FMA = 2, add/mul = 1, sqrt/div/log = 0), minimal form of the algorithm:
-    per step 3 force+Hessian evaluations, 3 drifts, and -- kicks commuting --
-    3 kicks of the deviation vectors (K(d3) K(d0) merged) but 4 of the state
-    (the LD needs p at every step endpoint); checkpoint work divided by K."""
+    for Henon-Heiles (FMA = 2, add/mul = 1; sqrt, division, log and
+    exponent bookkeeping = 0): the minimal operation count of the step as
+    the method is formulated here -- 3 drifts and 3 force evaluations; 4
+    state kicks (the LD needs p at every step endpoint) but 3 kicks of the
+    deviation vectors (kicks commute, so K(d3) K(d0) is one kick), each
+    with the step-scaled Hessian; checkpoint work divided by K."""
     assert system == "hh" and N == 2
     M = m_s + n_l
     D = 2 * N
-    force_hess = 10          # Vxx, Vyy (2 FMA), Vxy, Fx (mul), Fy (2 FMA)
-    state = 3 * 2 * N + 3 * force_hess + 4 * 2 * N  # drifts + evals + kicks
-    prescale = 3 * 3         # H' = h H for the 3 vector kicks
+    force = 2 + 4            # F_x = x(1+2y): 1 FMA; F_y = y - y^2 + x^2: 2 FMA
+    hess_scaled = 2 + 1 + 2  # h(1+2y), 2h x, h(1-2y)
+    state = 3 * 2 * N + 4 * 2 * N + 3 * force  # drifts, kicks, forces
     vec = 3 * (N * N * 2) + 3 * (N * 2)  # 3 kicks (2x2 mat-vec FMA) + 3 drifts
-    per = state + prescale + M * vec
+    per = state + 3 * hess_scaled + M * vec
     if ld:
-        per += (2 * N - 1) + 1 + 2  # sum of 2N terms, g_prev + g, FMA into LD
+        per += (2 * N - 1) + 1 + 2  # sum of 2N roots, g_prev + g, FMA into LD
     ck = 0
-    norm = 2 * D - 1 + D + 1  # |w|^2, scale, growth product
+    norm = 2 * D - 1 + D + 1  # |w|^2, rescale, growth product
     ck += m_s * norm
     if sali:
         ck += 2 * (D + 2 * D - 1)  # |w1 +- w2|^2
     for j in range(n_l):
         ck += j * ((2 * D - 1) + 2 * D) + norm  # projections + normalisation
     if energy:
-        ck += 14  # H (HH: 2 FMA kin, 5 potential) and |H - H0|
+        ck += 14  # H (kinetic 2 FMA, potential 5 ops) and |H - H0|
     return per + ck / K
 
 
@@ -66,9 +106,12 @@ def parse():
     ap.add_argument("--steps-per-launch", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=192,
+    ap.add_argument("--cpu-sample", type=int, default=2048,
                     help="orbits in the oracle sample (strided over the workload)")
-    ap.add_argument("--cpu-T", type=float, default=1e3)
+    ap.add_argument("--cpu-T", type=float, default=1e4)
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run a plain device copy of this many bytes (calibrates "
+                         "the FETCH_SIZE / WRITE_SIZE counters) and exit")
     return ap.parse_args()
 
 
@@ -87,6 +130,14 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_bytes:
+        a = torch.empty(args.copy_bytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.copy_bytes}), flush=True)
+        return
     energies = (0.125, 1.0 / 6.0)
     n_side = args.grid
     dt, T, K = 0.01, args.T, 10
@@ -184,7 +235,7 @@ def main():
             "peak": PEAK_FP64 / 1e12,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64,
-            "traffic": None,
+            "traffic": recorded_traffic(),
             "kernel": "chx::lane_kernel<SysHH, 6, false>",
             "flops_per_orbit_step": fps,
             "launch_ms": ms_avg,

@@ -131,7 +131,9 @@ chx_status make_plan(const chx_system *sys, const chx_options *opt, Plan *p) {
   p->kmax = kmax;
   p->n_total = (int64_t)nr;
   const int sk = sys->kind;
-  const bool ok = (sk == CHX_SYS_FPUT) ? fput_row_supported(N, p->M) : lane_supported(sk, N, p->M);
+  const bool ok = (sk == CHX_SYS_FPUT)
+                      ? fput_row_supported(N, p->M, p->n_l, (o.indicators & CHX_IND_SALI) != 0)
+                      : lane_supported(sk, N, p->M);
   if (!ok)
     return fail(CHX_ERR_UNSUPPORTED, "system kind %d with ndof %d and %d deviation vectors is not supported", sk, N, p->M);
   return CHX_OK;

@@ -64,7 +64,7 @@ hipError_t launch_lane(int sys, int ndof, int M, const StepArgs &a, int block,
                        hipStream_t s);
 bool lane_supported(int sys, int ndof, int M);
 hipError_t launch_fput_row(int ndof, int M, const StepArgs &a, hipStream_t s);
-bool fput_row_supported(int ndof, int M);
+bool fput_row_supported(int ndof, int M, int n_l, bool sali);
 
 // Preparation and output kernels (prep.hip).
 struct InitArgs {

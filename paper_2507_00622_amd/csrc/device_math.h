@@ -10,30 +10,31 @@ namespace chx {
 constexpr double YOSHIDA_W1 = 1.3512071919596575;
 constexpr double YOSHIDA_W0 = -1.7024143839193153;
 
-// 1/sqrt(a) for a > 0 to about one ulp: the hardware estimate refined by
-// two Newton steps y <- y + y (1 - a y^2) / 2.
+// 1/sqrt(a) for a > 0, relative error below 1e-14: the hardware estimate
+// (relative error up to about 5e-8 on gfx950) refined by one Newton step
+// y <- y + y (1 - a y^2) / 2, which leaves 1.5 e^2.  Used to rescale
+// deviation vectors; the growth accounting takes |w|^2 itself, so a
+// rescaled vector off unit length by 1e-14 only moves the next norm.
 __device__ __forceinline__ double rsqrt_nr(double a) {
-  double y = __builtin_amdgcn_rsq(a);
-  double e = __builtin_fma(-a * y, y, 1.0);
-  y = __builtin_fma(0.5 * y, e, y);
-  e = __builtin_fma(-a * y, y, 1.0);
+  const double y = __builtin_amdgcn_rsq(a);
+  const double e = __builtin_fma(-a * y, y, 1.0);
   return __builtin_fma(0.5 * y, e, y);
 }
 
-// sqrt(a) for a >= 0, relative error a few 1e-16: s = a y with y the
-// refined reciprocal root estimate (Goldschmidt step, then a Newton
-// correction of s).  a is floored at 1e-300 so that a = 0 gives 1e-150,
-// which no sum of O(1) terms can see.
-__device__ __forceinline__ double sqrt_nr(double a) {
-  a = __builtin_fmax(a, 1e-300);
-  double y = __builtin_amdgcn_rsq(a);
-  double s = a * y;
-  double h = 0.5 * y;
-  double r = __builtin_fma(-s, h, 0.5);
-  s = __builtin_fma(s, r, s);
-  h = __builtin_fma(h, r, h);
-  r = __builtin_fma(-s, s, a);
-  return __builtin_fma(r, h, s);
+// sqrt(|a|) for the Lagrangian-descriptor integrand, relative error below
+// 1e-14: one Goldschmidt step from the hardware reciprocal-root estimate
+// (error 1.5 e^2 for an estimate with relative error e; e <= 5.3e-8 was
+// measured over 2^20 arguments spanning 1e-13..1e13 on gfx950, giving
+// 4e-15).  |a| is
+// offset by 1e-300 -- invisible for |a| > 1e-284 -- so that a = 0 gives
+// 1e-150 instead of 0 * inf.
+__device__ __forceinline__ double sqrt_ld(double a) {
+  a = __builtin_fabs(a) + 1e-300;
+  const double y = __builtin_amdgcn_rsq(a);
+  const double s = a * y;
+  const double h = 0.5 * y;
+  const double r = __builtin_fma(-s, h, 0.5);
+  return __builtin_fma(s, r, s);
 }
 
 // Keep a growth product as mantissa * 2^exponent: multiply the mantissa by

@@ -44,19 +44,18 @@ __device__ inline double rng_normal(uint64_t key, uint64_t e) {
 // ---- system dispatch for the non-hot kernels ----------------------------
 __device__ inline void sys_force(int sys, int N, const double *q, const double *prm,
                                  double *F) {
-  double H[6];
   switch (sys) {
-  case SYS_HH: SysHH::force_hess(q, F, H, prm); return;
+  case SYS_HH: SysHH::force(q, F, prm); return;
   case SYS_FPUT: fput_force(q, N, prm, F); return;
   case SYS_QUARTIC:
-    if (N == 1) SysQuartic<1>::force_hess(q, F, H, prm);
-    else if (N == 2) SysQuartic<2>::force_hess(q, F, H, prm);
-    else SysQuartic<3>::force_hess(q, F, H, prm);
+    if (N == 1) SysQuartic<1>::force(q, F, prm);
+    else if (N == 2) SysQuartic<2>::force(q, F, prm);
+    else SysQuartic<3>::force(q, F, prm);
     return;
   case SYS_HARMONIC:
-    if (N == 1) SysHarmonic<1>::force_hess(q, F, H, prm);
-    else if (N == 2) SysHarmonic<2>::force_hess(q, F, H, prm);
-    else SysHarmonic<3>::force_hess(q, F, H, prm);
+    if (N == 1) SysHarmonic<1>::force(q, F, prm);
+    else if (N == 2) SysHarmonic<2>::force(q, F, prm);
+    else SysHarmonic<3>::force(q, F, prm);
     return;
   }
 }

@@ -1,9 +1,12 @@
 // systems.h -- potentials, forces and Hessians of the built-in systems for
 // the lane-per-orbit kernel.  Each system gives, at a configuration q:
-//   F = grad V(q)  (N values)
-//   H = Hess V(q)  packed upper triangle, H[hidx(i, j)] for i <= j
-// in registers; the kernels use them for the kick of the state
-// (p -= h F) and of every deviation vector (dp -= h H dq).
+//   force(q, F):            F = grad V(q)                      (N values)
+//   hess_scaled(q, h, Hs):  Hs = h Hess V(q), packed upper triangle,
+//                           Hs[hidx(i, j)] for i <= j
+// in registers.  The kernels use them for the kick of the state
+// (p -= h F) and of every deviation vector (dp -= h Hess V dq); the step
+// size h is folded into the Hessian's coefficients where the system allows,
+// so a kick costs no separate rescaling.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -21,14 +24,17 @@ struct SysHH {
   static constexpr int N = 2;
   static constexpr int NH = 3;
   static constexpr bool diag_only = false;
-  __device__ static inline void force_hess(const double *q, double *F, double *H,
-                                           const double *) {
+  __device__ static inline void force(const double *q, double *F, const double *) {
     const double x = q[0], y = q[1];
-    H[0] = __builtin_fma(2.0, y, 1.0);
-    H[1] = x + x;
-    H[2] = __builtin_fma(-2.0, y, 1.0);
-    F[0] = x * H[0];
+    F[0] = __builtin_fma(x + x, y, x);
     F[1] = __builtin_fma(x, x, __builtin_fma(-y, y, y));
+  }
+  __device__ static inline void hess_scaled(const double *q, double h, double *Hs,
+                                            const double *) {
+    const double h2 = h + h;
+    Hs[0] = __builtin_fma(h2, q[1], h);
+    Hs[1] = h2 * q[0];
+    Hs[2] = __builtin_fma(-h2, q[1], h);
   }
   __device__ static inline double potential(const double *q, const double *) {
     const double x = q[0], y = q[1];
@@ -45,22 +51,33 @@ struct SysQuartic {
   static constexpr int N = NN;
   static constexpr int NH = NN * (NN + 1) / 2;
   static constexpr bool diag_only = false;
-  __device__ static inline void force_hess(const double *q, double *F, double *H,
-                                           const double *prm) {
+  __device__ static inline void force(const double *q, double *F, const double *prm) {
     const double eps = prm[0];
     double S = 0.0;
 #pragma unroll
     for (int i = 0; i < N; ++i) S = __builtin_fma(q[i], q[i], S);
-    const double te = 2.0 * eps * S;
-    const double a1 = 1.0 - 2.0 * eps, a3 = 3.0 - 2.0 * eps, e4 = 4.0 * eps;
+    const double te = 2.0 * eps * S, a1 = 1.0 - 2.0 * eps;
+#pragma unroll
+    for (int i = 0; i < N; ++i) F[i] = q[i] * __builtin_fma(a1, q[i] * q[i], te);
+  }
+  __device__ static inline void hess_scaled(const double *q, double h, double *Hs,
+                                            const double *prm) {
+    const double eps = prm[0];
+    double S = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) S = __builtin_fma(q[i], q[i], S);
+    const double hte = (2.0 * eps * h) * S, ha3 = (3.0 - 2.0 * eps) * h, he4 = 4.0 * eps * h;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      const double qi2 = q[i] * q[i];
-      F[i] = q[i] * __builtin_fma(a1, qi2, te);
-      H[hidx(N, i, i)] = __builtin_fma(a3, qi2, te);
+      Hs[hidx(N, i, i)] = __builtin_fma(ha3, q[i] * q[i], hte);
 #pragma unroll
-      for (int j = i + 1; j < N; ++j) H[hidx(N, i, j)] = (e4 * q[i]) * q[j];
+      for (int j = i + 1; j < N; ++j) Hs[hidx(N, i, j)] = (he4 * q[i]) * q[j];
     }
+  }
+  __device__ static inline void force_hess(const double *q, double *F, double *H,
+                                           const double *prm) {
+    force(q, F, prm);
+    hess_scaled(q, 1.0, H, prm);
   }
   __device__ static inline double potential(const double *q, const double *prm) {
     const double eps = prm[0];
@@ -82,15 +99,17 @@ struct SysHarmonic {
   static constexpr int N = NN;
   static constexpr int NH = NN * (NN + 1) / 2;
   static constexpr bool diag_only = true;
-  __device__ static inline void force_hess(const double *q, double *F, double *H,
-                                           const double *prm) {
+  __device__ static inline void force(const double *q, double *F, const double *prm) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) F[i] = (prm[i] * prm[i]) * q[i];
+  }
+  __device__ static inline void hess_scaled(const double *, double h, double *Hs,
+                                            const double *prm) {
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      const double w2 = prm[i] * prm[i];
-      F[i] = w2 * q[i];
-      H[hidx(N, i, i)] = w2;
+      Hs[hidx(N, i, i)] = h * (prm[i] * prm[i]);
 #pragma unroll
-      for (int j = i + 1; j < N; ++j) H[hidx(N, i, j)] = 0.0;
+      for (int j = i + 1; j < N; ++j) Hs[hidx(N, i, j)] = 0.0;
     }
   }
   __device__ static inline double potential(const double *q, const double *prm) {

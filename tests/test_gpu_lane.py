@@ -5,9 +5,12 @@ Tolerances (floating point; rounding differs because the HIP path fuses
 multiply-adds and merges commuting kicks, the oracle does neither):
   - state, regular orbits (oracle label at T = 1e4), T = 200: relative 1e-9
     (max_c |x_gpu - x_cpu| / max(1, |x_cpu|_inf));
-  - every orbit at T = 100: |log10 SALI| and |log10 GALI| 1e-6 where both
-    values are >= 1e-12, Lyapunov exponents 1e-6 absolute, LD 1e-9
-    relative, energy error 1e-12 absolute;
+  - every orbit at short T -- about ten Lyapunov times of the fastest orbit
+    of the set: T = 100 at E = 0.125, T = 50 at E = 1/6 -- |log10 SALI| 1e-6
+    where both values are >= 1e-12, |log10 GALI| 1e-6 where both are >= 1e-8
+    (GALI comes from a QR of unit vectors, whose small R_kk carry an absolute
+    rounding error near 1e-16 on both sides), Lyapunov exponents
+    1e-6 absolute, LD 1e-9 relative, energy error 1e-12 absolute;
   - integers (status, mask, labels of regular orbits) exactly.
 """
 import os
@@ -89,29 +92,30 @@ def test_hh_sali_ld_state_regular_T200(env):
     assert err.max() < 1e-9
     act = mask == 1
     assert np.max(np.abs(g["energy_err"][act] - o["energy_err"][act])) < 1e-12
-    assert np.max(np.abs(g["ld"][act] / o["ld"][act] - 1)) < 1e-9
+    assert np.max(np.abs(g["ld"][reg] / o["ld"][reg] - 1)) < 1e-9
     # labels at T = 200 of regular orbits cannot flip
     assert np.array_equal(g["label"][reg], o["label"][reg])
 
 
 def test_hh_all_indicators_T100(env):
     torch, P, O = env
-    for E in (0.125, 1.0 / 6.0):
-        say(f"case: HH E={E:.6f} 24x24, all indicators, T=100")
+    for E, T in ((0.125, 100.0), (1.0 / 6.0, 50.0)):
+        say(f"case: HH E={E:.6f} 24x24, all indicators, T={T}")
         x0, mask = O.hh_grid(E, 24, 24)
         w0 = S.deviation_vectors(7, len(x0), 2, 4)
-        kw = dict(dt=0.01, T=100.0, indicators=ALL, gali_kmax=2, n_lyap=4, escape_r2=4.0)
+        kw = dict(dt=0.01, T=T, indicators=ALL, gali_kmax=2, n_lyap=4, escape_r2=4.0)
         g = run_gpu(env, P.henon_heiles(), x0, mask, w0, **kw)
         o = O.integrate(O.henon_heiles(), x0, O.Run(**kw), w0=w0, mask=mask, threads=8)
         act = mask == 1
         assert np.array_equal(g["status"], o["status"])
         ok = act & (o["status"] == 0)
-        say("  sali", log_err(g["sali_min"][ok], o["sali_min"][ok]),
-            "gali", log_err(g["gali"][ok, 0], o["gali"][ok, 0]),
+        say("  max lambda_1", np.max(o["lyap"][ok, 0]),
+            "sali", log_err(g["sali_min"][ok], o["sali_min"][ok]),
+            "gali", log_err(g["gali"][ok, 0], o["gali"][ok, 0], floor=1e-8),
             "lyap", np.max(np.abs(g["lyap"][ok] - o["lyap"][ok])))
         assert log_err(g["sali_min"][ok], o["sali_min"][ok]) < 1e-6
         assert log_err(g["sali_final"][ok], o["sali_final"][ok]) < 1e-6
-        assert log_err(g["gali"][ok, 0], o["gali"][ok, 0]) < 1e-6
+        assert log_err(g["gali"][ok, 0], o["gali"][ok, 0], floor=1e-8) < 1e-6
         assert np.max(np.abs(g["lyap"][ok] - o["lyap"][ok])) < 1e-6
         assert np.max(np.abs(g["ld"][ok] / o["ld"][ok] - 1)) < 1e-9
         assert np.max(np.abs(g["energy_err"][ok] - o["energy_err"][ok])) < 1e-12
@@ -277,7 +281,7 @@ def test_convenience_entry_points(env):
                                                   gali_kmax=4),
                      w0=S.deviation_vectors(5, len(x0), 4, 4))
     for k in range(3):
-        assert log_err(ga[:, k], og["gali"][:, k]) < 1e-8
+        assert log_err(ga[:, k], og["gali"][:, k], floor=1e-8) < 1e-8
 
 
 def test_section_grid_kernel(env):
@@ -289,8 +293,9 @@ def test_section_grid_kernel(env):
         xo, mo = O.hh_grid(E, 1024, 1024)
         assert np.array_equal(mg, mo) and int(mg.sum()) == cnt
         assert np.array_equal(xg[:, [0, 1, 3]], xo[:, [0, 1, 3]])
-        assert np.max(np.abs(xg[:, 2] - xo[:, 2])) < 1e-15
+        # p_x = sqrt(r): r agrees to rounding, sqrt amplifies that near r = 0
+        assert np.max(np.abs(xg[:, 2] ** 2 - xo[:, 2] ** 2)) < 1e-15
     y, py = S.section_points(3, 1000)
     xg, mg = P.hh_section_points(0.125, y, py)
     xo, mo = O.hh_points(0.125, y, py)
-    assert np.array_equal(mg, mo) and np.max(np.abs(xg - xo)) < 1e-15
+    assert np.array_equal(mg, mo) and np.max(np.abs(xg**2 - xo**2)) < 1e-15
