@@ -96,13 +96,319 @@ def flops_per_step(N, m_s, n_l, ld, energy, sali, K, system="hh"):
     return per + ck / K
 
 
+def flops_per_step_fput(N, m_s, n_l, ld, energy, sali, K):
+    """Algorithmic FP64 flops of one orbit-step of an FPU-beta chain of N
+    masses between fixed walls (same conventions as flops_per_step): each
+    force evaluation takes the N+1 spring elongations (1), forces
+    d (k + d (alpha + beta d)) (2 FMA + 1 mul), the net forces (1 per mass)
+    and the N+1 stiffnesses k + d (2 alpha + 3 beta d) (2 FMA) of the
+    tridiagonal Hessian; a tangent kick scales the three diagonals by the
+    kick's step (4 per mass, shared by all vectors) and applies them
+    (3 FMA per component)."""
+    M = m_s + n_l
+    D = 2 * N
+    force = 6 * (N + 1) + N + 4 * (N + 1)
+    state = 3 * force + 4 * 2 * N + 3 * 2 * N
+    prescale = 3 * 4 * N
+    vec = 3 * 3 * 2 * N + 3 * 2 * N
+    per = state + prescale + M * vec
+    if ld:
+        per += (2 * N - 1) + 1 + 2
+    norm = 2 * D - 1 + D + 1
+    ck = m_s * norm
+    if sali:
+        ck += 2 * (D + 2 * D - 1)
+    for j in range(n_l):
+        ck += j * ((2 * D - 1) + 2 * D) + norm
+    if energy:
+        ck += 8 * (N + 1) + 2 * N + 2
+    return per + ck / K
+
+
+def flops_per_step_quartic(N, m_s, ld, energy, sali, K):
+    """Algorithmic FP64 flops of one orbit-step of the coupled quartic
+    oscillators V = sum q_i^4/4 + eps sum_{i<j} q_i^2 q_j^2 (same
+    conventions): force q_i (a q_i^2 + 2 eps S) with S = |q|^2, and the
+    step-scaled symmetric Hessian, 3 times per step."""
+    D = 2 * N
+    force = 2 * N + 1 + 4 * N
+    hess = 2 * N + 3 + 3 * N + 2 * (N * (N - 1) // 2) + N
+    state = 3 * (force + hess) + 4 * 2 * N + 3 * 2 * N
+    vec = 3 * (2 * N * N) + 3 * 2 * N
+    per = state + m_s * vec
+    if ld:
+        per += (2 * N - 1) + 1 + 2
+    ck = m_s * (2 * D - 1 + D + 1)
+    if sali:
+        ck += 2 * (D + 2 * D - 1)
+    if energy:
+        ck += 6 * N + 2 * (N * (N - 1) // 2) + 4
+    return per + ck / K
+
+
+def emit(args, metric, value, unit, elapsed, dtype, config, roofline, cpu, higher=True):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": elapsed / max(args.steps, 1) * 1e3,
+            "higher_is_better": higher, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": config, "roofline": roofline, "cpu_baseline": cpu}
+
+
+def advance_timed(e, n_steps, spl, stream, torch, log):
+    """Advance an ensemble to its last step in launches of spl steps, with
+    HIP events around each launch on the stream it runs on."""
+    s = 0
+    while s < n_steps:
+        nxt = min(s + spl, n_steps)
+        if log is not None:
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            e.advance(nxt)
+            b.record(stream)
+            log.append((a, b, nxt - s))
+        else:
+            e.advance(nxt)
+        s = nxt
+
+
+def bench_fput(args, P, chx, torch, dev):
+    """FPU-beta chains, N = 8 and N = 16, 65,536 orbits each (energy 1 per
+    mass, random mode amplitudes), 3N deviation vectors per orbit: the 2N
+    Lyapunov vectors (modified Gram-Schmidt every 10 steps) and N GALI/SALI
+    vectors, dt = 0.02."""
+    import numpy as np
+
+    import seeded_inputs as S
+    T = args.T or 2000.0
+    dt, K, n = 0.02, 10, 65536
+    n_steps = int(round(T / dt))
+    spl = min(args.steps_per_launch or 10000, n_steps)
+    stream = torch.cuda.current_stream()
+    ind = chx.IND_SALI | chx.IND_GALI | chx.IND_LYAP | chx.IND_ENERGY
+    x0s = {}
+    for N in (8, 16):
+        u = torch.as_tensor(S.fput_mode_draws(1003 + N, n), device=dev)
+        x0s[N] = P.ic_fput_modes(P.fput(N), u)
+    logs = {8: [], 16: []}
+
+    def one_pass(record):
+        for N in (8, 16):
+            e = P.Ensemble(P.fput(N), x0s[N], steps_per_launch=spl, dt=dt, T=T, indicators=ind,
+                           gali_kmax=N, n_lyap=2 * N, renorm_every=K, seed=1003,
+                           outputs=("status", "lyap", "gali"))
+            advance_timed(e, n_steps, spl, stream, torch, logs[N] if record else None)
+            e.results()
+            e.close()
+
+    for _ in range(args.warmup):
+        one_pass(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_pass(True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = 2 * n * n_steps * args.steps / elapsed
+    per_n = {}
+    for N in (8, 16):
+        fps = flops_per_step_fput(N, N, 2 * N, False, True, True, K)
+        full = [a.elapsed_time(b) for a, b, k in logs[N] if k == spl]
+        ms = float(np.mean(full))
+        per_n[N] = dict(fps=fps, ms=ms, achieved=fps * n * spl / (ms * 1e-3), launches=len(full))
+    r = per_n[16]
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        threads = max(1, min(16, len(os.sched_getaffinity(0))))
+        cT = args.cpu_T if args.cpu_T != 1e4 else 100.0
+        tot, el = 0, 0.0
+        for N in (8, 16):
+            m = 32
+            xs = O.fput_ic(O.fput(N), S.fput_mode_draws(1003 + N, m))
+            w0 = S.deviation_vectors(1003, m, N, 2 * N)
+            run = O.Run(dt=dt, T=cT, indicators=ind, gali_kmax=N, n_lyap=2 * N, K=K)
+            t1 = time.perf_counter()
+            O.integrate(O.fput(N), xs, run, w0=w0, threads=threads)
+            el += time.perf_counter() - t1
+            tot += m * int(round(cT / dt))
+        cpu = {"value": tot / el, "unit": "orbit-steps/s", "cores": threads, "kind": "oracle",
+               "sample": f"32 orbits per N (8 and 16), T={cT:g} ({tot:.3g} orbit-steps, "
+                         f"{el:.1f} s)"}
+    return emit(args, "FP64 trajectory-steps/s (with tangents)", value, "orbit-steps/s", elapsed,
+                "f64", {
+                    "workload": f"FPU-beta chains N=8 and N=16 (k=1, beta=1), 65536 orbits each, "
+                                f"3N deviation vectors (2N Lyapunov by MGS/10 + N GALI), "
+                                f"dt={dt}, T={T:g}",
+                    "orbits": 2 * n, "steps_per_orbit": n_steps, "steps_per_launch": spl,
+                    "per_N": {str(N): {"flops_per_orbit_step": v["fps"], "launch_ms": v["ms"],
+                                       "tflops": v["achieved"] / 1e12,
+                                       "frac": v["achieved"] / PEAK_FP64}
+                              for N, v in per_n.items()}},
+                {"bound": "alu", "achieved": r["achieved"] / 1e12, "peak": PEAK_FP64 / 1e12,
+                 "unit": "TFLOP/s", "frac": r["achieved"] / PEAK_FP64, "traffic": None,
+                 "kernel": "chx::fput_row_kernel<16, 3>", "flops_per_orbit_step": r["fps"],
+                 "launch_ms": r["ms"], "launches_timed": r["launches"]}, cpu)
+
+
+def bench_batched(args, P, chx, torch, dev):
+    """The persistent batched form: 2^20 Henon-Heiles orbits (seeded uniform
+    accessible section points, E = 0.125), 2^18 coupled-quartic orbits
+    (N = 3, eps = 0.1, E = 1) and 2^16 FPU-beta N = 16 orbits in one
+    persistent launch sequence, two deviation vectors each, early exit at the
+    first checkpoint with SALI < 1e-8; against three plain launches."""
+    import numpy as np
+
+    import seeded_inputs as S
+    T = args.T or 1e4
+    y, py = S.section_points(1004, 1400000)
+    x, m = P.hh_section_points(0.125, torch.as_tensor(y, device=dev),
+                               torch.as_tensor(py, device=dev))
+    xh = x[m == 1][: 1 << 20].contiguous()
+    xq = P.ic_quartic(P.quartic(3, 0.1), torch.as_tensor(S.quartic_draws(1005, 1 << 18),
+                                                          device=dev))
+    xf = P.ic_fput_modes(P.fput(16), torch.as_tensor(S.fput_mode_draws(1006, 1 << 16),
+                                                      device=dev))
+    items = [dict(sys=P.henon_heiles(), x0=xh, dt=0.01, T=T),
+             dict(sys=P.quartic(3, 0.1), x0=xq, dt=0.01, T=T),
+             dict(sys=P.fput(16), x0=xf, dt=0.02, T=T)]
+    n_orbits = sum(int(it["x0"].shape[0]) for it in items)
+    ind = chx.IND_SALI | chx.IND_ENERGY
+    kw = dict(indicators=ind, seed=1004, early_exit=True, sali_threshold=1e-8,
+              steps_per_launch=args.steps_per_launch, block_size=args.block)
+    outs_keys = ("status", "label", "t_end")
+    for _ in range(args.warmup):
+        P.integrate_batched(items, outputs=outs_keys, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = None
+    for _ in range(args.steps):
+        outs, stats = P.integrate_batched(items, outputs=outs_keys, **kw)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    # three plain launches of the same work
+    t1 = time.perf_counter()
+    ref = []
+    for i, it in enumerate(items):
+        ref.append(P.integrate_ensemble(it["sys"], it["x0"], dt=it["dt"], T=it["T"],
+                                        outputs=outs_keys, indicators=ind, seed=1004 + i,
+                                        early_exit=True, sali_threshold=1e-8))
+    torch.cuda.synchronize()
+    plain = time.perf_counter() - t1
+    agree = [float((a["label"] == b["label"]).float().mean()) for a, b in zip(outs, ref)]
+    steps_exec = [int(v) for v in stats["orbit_steps"][:3]]
+    fps = [flops_per_step(2, 2, 0, False, True, True, 10),
+           flops_per_step_quartic(3, 2, False, True, True, 10),
+           flops_per_step_fput(16, 2, 0, False, True, True, 10)]
+    flops = sum(f * s for f, s in zip(fps, steps_exec))
+    kern_s = stats["integrate_ms"] * 1e-3
+    achieved = flops / kern_s
+    value = n_orbits * args.steps / elapsed
+    exited = [int((o["status"] == 4).sum()) for o in outs]
+    return emit(args, "labelled ICs/s (persistent batched form)", value, "ICs/s", elapsed, "f64", {
+        "workload": f"2^20 Henon-Heiles (E=0.125) + 2^18 quartic N=3 + 2^16 FPU-beta N=16, two "
+                    f"deviation vectors, early exit at SALI<1e-8, dt 0.01/0.01/0.02, T={T:g}",
+        "orbits": n_orbits, "exited_early": exited,
+        "executed_orbit_steps": steps_exec,
+        "executed_orbit_steps_per_s": sum(steps_exec) / kern_s,
+        "threads_per_block": stats["threads_per_block"], "blocks": stats["blocks"],
+        "launches": stats["launches"], "steps_per_launch": stats["steps_per_launch"],
+        "plain_three_launches_s": plain, "plain_ICs_per_s": n_orbits / plain,
+        "speedup_vs_plain": plain / (elapsed / args.steps),
+        "label_agreement_vs_plain": agree},
+        {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
+         "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
+         "kernel": "chx::batched_kernel", "flops_per_orbit_step": fps,
+         "launch_ms": stats["integrate_ms"] / max(stats["launches"], 1),
+         "launches_timed": stats["launches"]}, None)
+
+
+def bench_gate(args, P, chx, torch, dev):
+    """The learned gate against the plain form on the Henon-Heiles E = 0.125
+    2048x2048 section grid: training labels from 4,194,304 seeded uniform
+    accessible section points integrated to T = 1e4 (features at t = 200),
+    training on the GPU, then gate + fallback vs the plain integration of the
+    test grid (labels by SALI < 1e-8)."""
+    import numpy as np
+
+    import seeded_inputs as S
+    T = args.T or 1e4
+    dt, t_gate, conf_min = 0.01, 200.0, 0.98
+    n_train = 1 << 22
+    ind = chx.IND_SALI | chx.IND_LD
+    kw = dict(dt=dt, T=T, indicators=ind, seed=1005)
+    s_gate = int(round(t_gate / dt))
+    y, py = S.section_points(1005, int(n_train * 1.35))
+    x, m = P.hh_section_points(0.125, torch.as_tensor(y, device=dev),
+                               torch.as_tensor(py, device=dev))
+    xt = x[m == 1][:n_train].contiguous()
+    assert xt.shape[0] == n_train
+    t0 = time.perf_counter()
+    e = P.Ensemble(P.henon_heiles(), xt, **kw)
+    e.advance(s_gate)
+    r = e.results(("ld", "ln_growth"))
+    feat = P.gate_features(xt, r["ld"], r["ln_growth"], t_gate)
+    e.advance()
+    lab = e.results(("label",))["label"]
+    e.close()
+    torch.cuda.synchronize()
+    t_label = time.perf_counter() - t0
+    g = P.Gate(1005)
+    t0 = time.perf_counter()
+    epochs = int(os.environ.get("CHX_GATE_EPOCHS", "6"))
+    losses = g.train(feat, lab, epochs=epochs, batch=4096, lr=1e-3, seed=1005)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    xg, mg = P.grid_hh_section(0.125, 2048, 2048, device=dev)
+    n_test = int(mg.sum())
+    for _ in range(args.warmup):
+        g.classify(P.henon_heiles(), xg, mg, t_gate=t_gate, conf_min=conf_min, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out, st = g.classify(P.henon_heiles(), xg, mg, t_gate=t_gate, conf_min=conf_min, **kw)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ref = P.integrate_ensemble(P.henon_heiles(), xg, mask=mg, outputs=("label",), **kw)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    act = mg == 1
+    agree = float((out["label"][act] == ref["label"][act]).float().mean())
+    gated = out["source"] == 2
+    acc_gated = float((out["label"][gated] == ref["label"][gated]).float().mean()) \
+        if int(gated.sum()) else float("nan")
+    value = n_test * args.steps / elapsed
+    return emit(args, "labelled ICs/s (learned gate + fallback)", value, "ICs/s", elapsed,
+                "f64+bf16", {
+                    "workload": f"Henon-Heiles E=0.125 2048x2048 section grid, labels by SALI<1e-8 "
+                                f"at T={T:g} (dt={dt}); gate at t={t_gate:g}, confidence >= "
+                                f"{conf_min}; trained on {n_train} seeded accessible points",
+                    "orbits": n_test, "plain_s": t_plain, "plain_ICs_per_s": n_test / t_plain,
+                    "speedup_vs_plain": t_plain / (elapsed / args.steps),
+                    "agreement_vs_plain": agree, "accepted_accuracy": acc_gated,
+                    "fallback_fraction": st["n_fallback"] / max(st["n_active"], 1),
+                    "accepted": st["n_accepted"], "fallback": st["n_fallback"],
+                    "stopped_before_gate": st["n_early"],
+                    "ms_gate_integration": st["ms_gate"], "ms_features_inference": st["ms_infer"],
+                    "ms_fallback": st["ms_fallback"],
+                    "label_generation_s": t_label, "train_s": t_train, "epochs": epochs,
+                    "epoch_loss": [float(v) for v in losses],
+                    "train_chaotic_fraction": float((lab == 1).float().mean())},
+                None, None)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=("hh", "fput", "batched", "gate"), default="hh",
+                    help="hh: the headline Henon-Heiles grids (default); fput: FPU-beta "
+                         "chains with 3N deviation vectors; batched: the persistent mixed "
+                         "form with early exit; gate: the learned gate against the plain form")
     ap.add_argument("--grid", type=int, default=1024, help="grid side per energy")
-    ap.add_argument("--T", type=float, default=1e4)
+    ap.add_argument("--T", type=float, default=None,
+                    help="final time (default: 1e4 for hh, gate and batched, 2e3 for fput)")
     ap.add_argument("--steps-per-launch", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -138,6 +444,12 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": args.copy_bytes}), flush=True)
         return
+    if args.workload != "hh":
+        fn = {"fput": bench_fput, "batched": bench_batched, "gate": bench_gate}[args.workload]
+        print(json.dumps(fn(args, P, chx, torch, dev)), flush=True)
+        return
+    if args.T is None:
+        args.T = 1e4
     energies = (0.125, 1.0 / 6.0)
     n_side = args.grid
     dt, T, K = 0.01, args.T, 10

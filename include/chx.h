@@ -184,6 +184,48 @@ chx_status chx_ensemble_results(chx_ensemble *e, chx_result *res);
 chx_status chx_ensemble_info(const chx_ensemble *e, int64_t *n_total, int64_t *s_done,
                              int64_t *n_active);
 void chx_ensemble_destroy(chx_ensemble *e);
+/* Continue only part of an ensemble: *out is a new ensemble holding the
+ * active (unmasked) orbits of e with keep[i] != 0, i < n of e, in increasing
+ * i, with their current state, accumulated indicators and step count, so
+ * advancing it gives each kept orbit exactly the results it would have had
+ * in e.  Its orbits are numbered 0..n2-1 (n2 from chx_ensemble_info);
+ * results() arrays have n2 rows.  keep is host or device memory as e's
+ * pointers were at creation; e is not changed.  Used to resume a small
+ * unresolved part of a large ensemble without idle lanes. */
+chx_status chx_ensemble_subset(chx_ensemble *e, const uint8_t *keep, chx_ensemble **out);
+
+/* Batched persistent integration: several systems in one persistent
+ * launch, orbits leaving at their first checkpoint with SALI below the
+ * threshold when early_exit is set, freed slots refilled at once, repeated
+ * launches replayed from a captured hipGraph.  Each item is one system with
+ * its own initial conditions, mask, dt and T (T/dt must be a multiple of
+ * renorm_every).  Supported items: Henon-Heiles, coupled quartic with
+ * ndof 3, FPU with ndof 8 or 16; two deviation vectors per orbit (SALI
+ * required; GALI and Lyapunov not available here; LD and energy allowed);
+ * opt->w0 must be NULL (item i draws its vectors with seed opt->seed + i);
+ * at most 4 items.  opt->block_size and opt->steps_per_launch fix the
+ * threads per block and the steps per launch; 0 lets the autotuner choose
+ * (it times short probe launches on copies of the ensembles, per system and
+ * block size; timings are cached for the process and, if the environment
+ * variable CHX_AUTOTUNE_CACHE names a file, in that file).  Results per
+ * item as for chx_integrate_ensemble.  stats may be NULL. */
+typedef struct {
+  chx_system sys;
+  const double *x0;     /* [n][2N] */
+  const uint8_t *mask;  /* [n] or NULL */
+  int64_t n;
+  double dt, T;
+} chx_batch_item;
+typedef struct {
+  int32_t threads_per_block, blocks, launches, from_cache;
+  int64_t steps_per_launch;
+  double integrate_ms;        /* GPU time of the persistent launches */
+  int64_t orbit_steps[4];     /* steps integrated per item (sum over orbits) */
+  double cost_ps[4];          /* autotuned GPU time per orbit-step, picoseconds */
+} chx_batch_stats;
+chx_status chx_integrate_batched(const chx_batch_item *items, int32_t n_items,
+                                 const chx_options *opt, chx_result *per_item,
+                                 chx_batch_stats *stats);
 
 /* Initial-condition assembly. */
 /* Henon-Heiles surface of section x = 0 at energy E (Examples section):
@@ -207,12 +249,94 @@ chx_status chx_ic_fput_modes(const chx_system *sys, const double *u, int64_t n,
 chx_status chx_ic_quartic(const chx_system *sys, const double *draws, int64_t n,
                           double *x0_out, uint32_t flags, void *stream);
 
+/* Learned gate.  The paper motivates fast chaos indicators as a way to
+ * generate large labelled datasets for machine-learning models of dynamics
+ * (Introduction and Related research); the gate is such a model, used to
+ * label Henon-Heiles orbits from a short integration: a perceptron
+ * 6 -> 256 -> 256 -> 2 with erf-GELU activations on the features
+ *   f = (y, p_y, p_x, LD(t)/t, G_1(t)/t, G_2(t)/t),
+ * (x0 = (x, y, p_x, p_y); LD the M-function; G_v the ln-growth of the two
+ * SALI vectors, chx_result.ln_growth) z-scored with the training-set mean
+ * and standard deviation.  Products in BF16 with FP32 accumulation (MFMA),
+ * FP32 master parameters, softmax cross-entropy, AdamW.  All arithmetic is
+ * done by the library's kernels on the current device.
+ * Parameters, flat FP32 [CHX_GATE_NPARAM]: W1[16][256] (rows 6..15 zero),
+ * b1[256], W2[256][256], b2[256], W3[256][16] (columns 2..15 zero), b3[16]
+ * (2..15 zero); logits z = (a2 W3 + b3)[0..1], p(chaotic) = softmax(z)[1]. */
+#define CHX_GATE_NFEAT 6
+#define CHX_GATE_NPARAM 74256
+typedef struct chx_gate chx_gate;
+typedef struct {
+  int32_t epochs;       /* passes over the training set; 0 -> 1 */
+  int32_t batch;        /* rows per step: multiple of 16 in 16..65536; 0 -> 4096 */
+  float lr;             /* 0 -> 1e-3 */
+  float beta1, beta2;   /* 0 -> 0.9, 0.999 */
+  float eps;            /* 0 -> 1e-8 */
+  float weight_decay;   /* decoupled (AdamW), >= 0 */
+  uint64_t seed;        /* epoch permutations */
+} chx_gate_train_cfg;
+typedef struct {
+  int64_t n_active;     /* unmasked orbits */
+  int64_t n_early;      /* stopped before the gate time (label known) */
+  int64_t n_accepted;   /* labelled by the gate */
+  int64_t n_fallback;   /* integrated on to T */
+  double ms_gate;       /* integration to the gate time */
+  double ms_infer;      /* features + inference + selection */
+  double ms_fallback;   /* subset + integration to T + merge */
+} chx_gate_stats;
+/* New gate with weights drawn N(0, 2/fan_in) from SplitMix64(seed), zero
+ * biases, identity feature scaling. */
+chx_status chx_gate_create(uint64_t seed, chx_gate **out);
+void chx_gate_destroy(chx_gate *g);
+/* Train on features [n][6] (FP32) and labels [n] (1 chaotic, 0 regular;
+ * other values contribute nothing but still count in the batch mean).  The
+ * first call (or one with reset_stats != 0) sets the z-score statistics
+ * from these features.  epoch_loss: host [epochs] mean loss per epoch, or
+ * NULL.  Pointers per flags; synchronous. */
+chx_status chx_gate_train(chx_gate *g, const float *features, const int8_t *labels, int64_t n,
+                          const chx_gate_train_cfg *cfg, int32_t reset_stats,
+                          float *epoch_loss, uint32_t flags, void *stream);
+/* Mean loss over n <= 65536 rows and its gradient (host [CHX_GATE_NPARAM],
+ * zero on padded entries), without updating anything. */
+chx_status chx_gate_grad(chx_gate *g, const float *features, const int8_t *labels, int64_t n,
+                         float *grad_out, float *loss_out, uint32_t flags, void *stream);
+/* p(chaotic) and confidence max(p, 1 - p) per row; either output may be NULL. */
+chx_status chx_gate_infer(const chx_gate *g, const float *features, int64_t n,
+                          float *p_chaotic, float *confidence, uint32_t flags, void *stream);
+/* Read (any output may be NULL) or replace the parameters and the z-score
+ * mean / inverse standard deviation [6] (host memory).  Replacing zeroes
+ * the padded entries and the optimiser state. */
+chx_status chx_gate_get(const chx_gate *g, float *params, float *mean, float *istd);
+chx_status chx_gate_set(chx_gate *g, const float *params, const float *mean, const float *istd);
+/* Gate features from Henon-Heiles results at time t > 0: x0 [n][4],
+ * ld [n], ln_growth [n][2] -> features [n][6]. */
+chx_status chx_gate_features(const double *x0, const double *ld, const double *ln_growth,
+                             double t, int64_t n, float *features_out, uint32_t flags,
+                             void *stream);
+/* Label a Henon-Heiles ensemble with the gate: integrate all orbits to
+ * t_gate (a checkpoint time before T) with opt's indicators (SALI and LD
+ * required, GALI and Lyapunov not allowed), compute the features and the
+ * gate's confidence; orbits already stopped keep their label, confident
+ * ones (confidence >= conf_min) take the gate's label (p >= 0.5: chaotic),
+ * and the rest are resumed from their t_gate state on a compacted ensemble
+ * (chx_ensemble_subset) and integrated to T, taking the plain label.
+ * label_out [n] as chx_result.label; source_out [n] (or NULL): 0 masked,
+ * 1 stopped before t_gate, 2 gate, 3 integrated to T; confidence_out [n]
+ * (or NULL; NaN where not evaluated); stats may be NULL. */
+chx_status chx_gate_classify(const chx_gate *g, const chx_system *sys, const double *x0,
+                             const uint8_t *mask, int64_t n, const chx_options *opt,
+                             double t_gate, float conf_min, int8_t *label_out,
+                             uint8_t *source_out, float *confidence_out,
+                             chx_gate_stats *stats);
+
 /* Message for the last non-OK status on this thread ("" if none). */
 const char *chx_last_error(void);
 /* Library version string. */
 const char *chx_version(void);
-/* sizeof(chx_system), sizeof(chx_options), sizeof(chx_result) for which =
- * 0, 1, 2 (0 otherwise): lets a binding check its struct layouts. */
+/* sizeof(chx_system), sizeof(chx_options), sizeof(chx_result),
+ * sizeof(chx_batch_item), sizeof(chx_batch_stats), sizeof(chx_gate_train_cfg),
+ * sizeof(chx_gate_stats) for which = 0..6 (0 otherwise): lets a binding
+ * check its struct layouts. */
 size_t chx_struct_size(int32_t which);
 
 #ifdef __cplusplus

@@ -28,8 +28,12 @@ EXPORTS = [
     "chx_lyap_spectrum", "chx_ld", "chx_ensemble_create", "chx_ensemble_advance",
     "chx_ensemble_results", "chx_ensemble_info", "chx_ensemble_destroy",
     "chx_grid_hh_section", "chx_hh_section_points", "chx_ic_fput_modes", "chx_ic_quartic",
-    "chx_last_error", "chx_version", "chx_struct_size",
+    "chx_last_error", "chx_version", "chx_struct_size", "chx_integrate_batched",
+    "chx_ensemble_subset", "chx_gate_create", "chx_gate_destroy", "chx_gate_train",
+    "chx_gate_grad", "chx_gate_infer", "chx_gate_get", "chx_gate_set", "chx_gate_features",
+    "chx_gate_classify",
 ]
+GATE_NFEAT, GATE_NPARAM = 6, 74256
 
 
 class ChxError(RuntimeError):
@@ -58,6 +62,30 @@ RESULT_FIELDS = ["x_final", "t_end", "status", "label", "sali_final", "sali_min"
 
 class _Result(C.Structure):
     _fields_ = [(f, C.c_void_p) for f in RESULT_FIELDS]
+
+
+class _BatchItem(C.Structure):
+    _fields_ = [("sys", _System), ("x0", C.c_void_p), ("mask", C.c_void_p),
+                ("n", C.c_int64), ("dt", C.c_double), ("T", C.c_double)]
+
+
+class _BatchStats(C.Structure):
+    _fields_ = [("threads_per_block", C.c_int32), ("blocks", C.c_int32),
+                ("launches", C.c_int32), ("from_cache", C.c_int32),
+                ("steps_per_launch", C.c_int64), ("integrate_ms", C.c_double),
+                ("orbit_steps", C.c_int64 * 4), ("cost_ps", C.c_double * 4)]
+
+
+class _GateTrainCfg(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float),
+                ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("weight_decay", C.c_float), ("seed", C.c_uint64)]
+
+
+class _GateStats(C.Structure):
+    _fields_ = [("n_active", C.c_int64), ("n_early", C.c_int64), ("n_accepted", C.c_int64),
+                ("n_fallback", C.c_int64), ("ms_gate", C.c_double), ("ms_infer", C.c_double),
+                ("ms_fallback", C.c_double)]
 
 
 _lib = None
@@ -93,13 +121,28 @@ def lib():
         L.chx_ic_quartic.argtypes = [S, P, i64, P, u32, P]
         L.chx_last_error.restype = C.c_char_p
         L.chx_version.restype = C.c_char_p
+        L.chx_integrate_batched.argtypes = [C.POINTER(_BatchItem), i32, O, R,
+                                            C.POINTER(_BatchStats)]
         L.chx_struct_size.argtypes = [i32]
         L.chx_struct_size.restype = C.c_size_t
+        L.chx_ensemble_subset.argtypes = [P, P, C.POINTER(P)]
+        L.chx_gate_create.argtypes = [u64, C.POINTER(P)]
+        L.chx_gate_destroy.argtypes = [P]
+        L.chx_gate_destroy.restype = None
+        L.chx_gate_train.argtypes = [P, P, P, i64, C.POINTER(_GateTrainCfg), i32, P, u32, P]
+        L.chx_gate_grad.argtypes = [P, P, P, i64, P, P, u32, P]
+        L.chx_gate_infer.argtypes = [P, P, i64, P, P, u32, P]
+        L.chx_gate_get.argtypes = [P, P, P, P]
+        L.chx_gate_set.argtypes = [P, P, P, P]
+        L.chx_gate_features.argtypes = [P, P, P, d, i64, P, u32, P]
+        L.chx_gate_classify.argtypes = [P, S, P, P, i64, O, d, C.c_float, P, P, P,
+                                        C.POINTER(_GateStats)]
         for f in EXPORTS:
             if f not in ("chx_options_default", "chx_ensemble_destroy", "chx_last_error",
-                         "chx_version", "chx_struct_size"):
+                         "chx_version", "chx_struct_size", "chx_gate_destroy"):
                 getattr(L, f).restype = C.c_int
-        for k, st in enumerate((_System, _Options, _Result)):
+        for k, st in enumerate((_System, _Options, _Result, _BatchItem, _BatchStats,
+                                _GateTrainCfg, _GateStats)):
             if L.chx_struct_size(k) != C.sizeof(st):
                 raise ImportError(f"libchx struct {st.__name__} layout differs from the binding")
         _lib = L
@@ -172,7 +215,8 @@ class _Arrays:
             return None, None
         if self.device:
             t = self.torch.as_tensor(a, device=self.dev)
-            tdt = {np.float64: self.torch.float64, np.uint8: self.torch.uint8}[dtype]
+            tdt = {np.float64: self.torch.float64, np.uint8: self.torch.uint8,
+                   np.float32: self.torch.float32, np.int8: self.torch.int8}[dtype]
             t = t.to(tdt).contiguous()
             return t, C.c_void_p(t.data_ptr())
         arr = np.ascontiguousarray(a, dtype=dtype)
@@ -181,7 +225,8 @@ class _Arrays:
     def out(self, shape, dtype):
         if self.device:
             tdt = {np.float64: self.torch.float64, np.int32: self.torch.int32,
-                   np.int8: self.torch.int8, np.uint8: self.torch.uint8}[dtype]
+                   np.int8: self.torch.int8, np.uint8: self.torch.uint8,
+                   np.float32: self.torch.float32}[dtype]
             t = self.torch.empty(shape, dtype=tdt, device=self.dev)
             return t, C.c_void_p(t.data_ptr())
         arr = np.empty(shape, dtype=dtype)
@@ -282,6 +327,20 @@ class Ensemble:
                                   outputs if outputs is not None else self.outputs)
         _check(lib().chx_ensemble_results(self.h, C.byref(res)))
         return out
+
+    def subset(self, keep):
+        """chx_ensemble_subset: a new Ensemble continuing the active orbits
+        with keep[i] != 0 (numbered 0..n2-1 in increasing i)."""
+        k, pk = self.arr.inp(keep, np.uint8)
+        if int(k.shape[0]) != self.n:
+            raise ValueError("keep must have one entry per orbit")
+        h = C.c_void_p()
+        _check(lib().chx_ensemble_subset(self.h, pk, C.byref(h)))
+        e = Ensemble.__new__(Ensemble)
+        e.sys, e.arr, e.o, e.outputs, e.h = self.sys, self.arr, self.o, self.outputs, h
+        e._x0 = e._mask = e._w0 = None
+        e.n = e.info()[2]
+        return e
 
     def close(self):
         if self.h:
@@ -404,6 +463,145 @@ def ic_quartic(sys, draws):
     cs = sys._c()
     _check(lib().chx_ic_quartic(C.byref(cs), pd, n, px, arr.flags, arr.stream))
     return x0
+
+
+def integrate_batched(items, outputs=None, **opts):
+    """chx_integrate_batched.  items: list of dicts with keys sys, x0,
+    mask (optional), dt, T.  Returns (list of per-item output dicts, stats
+    dict).  All arrays numpy (host) or all torch CUDA tensors (device)."""
+    if not items:
+        raise ValueError("no items")
+    arr = _Arrays(items[0]["x0"])
+    o = make_options(dt=items[0]["dt"], T=items[0]["T"], **opts)
+    o.flags, o.stream = arr.flags, arr.stream
+    c_items = (_BatchItem * len(items))()
+    results = (_Result * len(items))()
+    keep, outs = [], []
+    for k, it in enumerate(items):
+        sys = it["sys"]
+        xa, px = arr.inp(it["x0"], np.float64)
+        ma, pm = arr.inp(it.get("mask"), np.uint8)
+        n = int(xa.shape[0])
+        cs = sys._c()
+        keep += [xa, ma, cs]
+        c_items[k].sys = cs
+        c_items[k].x0, c_items[k].mask, c_items[k].n = px, pm, n
+        c_items[k].dt, c_items[k].T = float(it["dt"]), float(it["T"])
+        oi = make_options(dt=it["dt"], T=it["T"], **opts)
+        res, out = _alloc_results(arr, sys, oi, n, outputs)
+        results[k] = res
+        outs.append(out)
+    st = _BatchStats()
+    _check(lib().chx_integrate_batched(c_items, len(items), C.byref(o), results, C.byref(st)))
+    stats = {f: getattr(st, f) for f, _ in _BatchStats._fields_}
+    stats["orbit_steps"] = list(st.orbit_steps)[:len(items)]
+    stats["cost_ps"] = list(st.cost_ps)[:len(items)]
+    return outs, stats
+
+
+# --- learned gate -----------------------------------------------------------------
+
+def gate_features(x0, ld, ln_growth, t):
+    """chx_gate_features: [n][6] float32 features at time t."""
+    arr = _Arrays(x0)
+    xa, px = arr.inp(x0, np.float64)
+    la, pl = arr.inp(ld, np.float64)
+    ga, pg = arr.inp(ln_growth, np.float64)
+    n = int(xa.shape[0])
+    out, po = arr.out((n, GATE_NFEAT), np.float32)
+    _check(lib().chx_gate_features(px, pl, pg, float(t), n, po, arr.flags, arr.stream))
+    return out
+
+
+class Gate:
+    """The learned gate (chx_gate_*): a 6-256-256-2 GELU perceptron trained and
+    evaluated by the library's kernels on the current GPU."""
+
+    def __init__(self, seed=0):
+        self.h = C.c_void_p()
+        _check(lib().chx_gate_create(int(seed) & (2**64 - 1), C.byref(self.h)))
+
+    def close(self):
+        if self.h:
+            lib().chx_gate_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def train(self, features, labels, epochs=1, batch=4096, lr=1e-3, beta1=0.9, beta2=0.999,
+              eps=1e-8, weight_decay=0.0, seed=0, reset_stats=False):
+        """Returns the mean loss of each epoch (numpy float32)."""
+        arr = _Arrays(features)
+        fa, pf = arr.inp(features, np.float32)
+        la, pl = arr.inp(labels, np.int8)
+        n = int(fa.shape[0])
+        c = _GateTrainCfg(int(epochs), int(batch), float(lr), float(beta1), float(beta2),
+                          float(eps), float(weight_decay), int(seed) & (2**64 - 1))
+        loss = np.zeros(max(int(epochs), 1), np.float32)
+        _check(lib().chx_gate_train(self.h, pf, pl, n, C.byref(c), int(bool(reset_stats)),
+                                    loss.ctypes.data_as(C.c_void_p), arr.flags, arr.stream))
+        return loss[:int(epochs)]
+
+    def grad(self, features, labels):
+        """(mean loss, flat gradient) over up to 65536 rows, no update."""
+        arr = _Arrays(features)
+        fa, pf = arr.inp(features, np.float32)
+        la, pl = arr.inp(labels, np.int8)
+        g = np.zeros(GATE_NPARAM, np.float32)
+        loss = C.c_float()
+        _check(lib().chx_gate_grad(self.h, pf, pl, int(fa.shape[0]), g.ctypes.data_as(C.c_void_p),
+                                   C.byref(loss), arr.flags, arr.stream))
+        return float(loss.value), g
+
+    def infer(self, features):
+        """(p_chaotic, confidence) per row."""
+        arr = _Arrays(features)
+        fa, pf = arr.inp(features, np.float32)
+        n = int(fa.shape[0])
+        p, pp = arr.out((n,), np.float32)
+        c, pc = arr.out((n,), np.float32)
+        _check(lib().chx_gate_infer(self.h, pf, n, pp, pc, arr.flags, arr.stream))
+        return p, c
+
+    def get(self):
+        p = np.zeros(GATE_NPARAM, np.float32)
+        m = np.zeros(GATE_NFEAT, np.float32)
+        s = np.zeros(GATE_NFEAT, np.float32)
+        _check(lib().chx_gate_get(self.h, p.ctypes.data_as(C.c_void_p),
+                                  m.ctypes.data_as(C.c_void_p), s.ctypes.data_as(C.c_void_p)))
+        return p, m, s
+
+    def set(self, params=None, mean=None, istd=None):
+        ptr = lambda a, n: (None, None) if a is None else (
+            lambda x: (x, x.ctypes.data_as(C.c_void_p)))(
+                np.ascontiguousarray(a, np.float32).reshape(n))
+        pa, pp = ptr(params, GATE_NPARAM)
+        ma, pm = ptr(mean, GATE_NFEAT)
+        sa, ps = ptr(istd, GATE_NFEAT)
+        _check(lib().chx_gate_set(self.h, pp, pm, ps))
+
+    def classify(self, sys, x0, mask=None, t_gate=200.0, conf_min=0.98, **opts):
+        """chx_gate_classify: returns ({label, source, confidence}, stats)."""
+        arr = _Arrays(x0)
+        o = make_options(**opts)
+        o.flags, o.stream = arr.flags, arr.stream
+        xa, px = arr.inp(x0, np.float64)
+        ma, pm = arr.inp(mask, np.uint8)
+        n = int(xa.shape[0])
+        lab, plab = arr.out((n,), np.int8)
+        src, psrc = arr.out((n,), np.uint8)
+        cf, pcf = arr.out((n,), np.float32)
+        st = _GateStats()
+        cs = sys._c()
+        _check(lib().chx_gate_classify(self.h, C.byref(cs), px, pm, n, C.byref(o),
+                                       float(t_gate), float(conf_min), plab, psrc, pcf,
+                                       C.byref(st)))
+        stats = {f: getattr(st, f) for f, _ in _GateStats._fields_}
+        return {"label": lab, "source": src, "confidence": cf}, stats
 
 
 def version():

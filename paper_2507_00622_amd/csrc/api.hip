@@ -9,10 +9,12 @@
 #include <vector>
 
 #include "chx_internal.h"
+#include "ensemble.h"
 
 using namespace chx;
 
-namespace {
+namespace chx {
+namespace host {
 
 thread_local std::string g_err;
 
@@ -71,13 +73,6 @@ chx_status check_system(const chx_system *sys) {
     if (!isfinite(sys->params[i])) return fail(CHX_ERR_INVALID_ARG, "system param %d is not finite", i);
   return CHX_OK;
 }
-
-// Options with defaults filled in, plus derived sizes.
-struct Plan {
-  chx_options o;
-  int N, D, m_s, n_l, M, K, kmax;
-  int64_t n_total;
-};
 
 chx_status make_plan(const chx_system *sys, const chx_options *opt, Plan *p) {
   if (!opt) return fail(CHX_ERR_INVALID_ARG, "options is NULL");
@@ -145,27 +140,6 @@ hipError_t dalloc(T **p, size_t count, hipStream_t s) {
   if (count == 0) return hipSuccess;
   return hipMallocAsync((void **)p, sizeof(T) * count, s);
 }
-
-}  // namespace
-
-struct chx_ensemble {
-  int kind;
-  double prm[16];
-  Plan pl;
-  int64_t n_all = 0, n_active = 0, pitch = 0, s_done = 0;
-  hipStream_t stream = nullptr;
-  bool device = false;
-  double *x0 = nullptr;      // [n_all][D] own copy
-  uint8_t *mask = nullptr;   // [n_all] own copy or null
-  int64_t *idx = nullptr;    // [n_active]
-  double *state = nullptr;   // x, w, gm, sc
-  int *istate = nullptr;     // ge, st
-  StepArgs args{};
-  int block = 256;
-  int64_t steps_per_launch = 0;
-};
-
-namespace {
 
 void release(chx_ensemble *e) {
   if (!e) return;
@@ -397,6 +371,102 @@ chx_status results(chx_ensemble *e, chx_result *res) {
   return CHX_OK;
 }
 
+// New ensemble holding the active orbits of e with keep[orbit] != 0 (keep
+// on the device, indexed by caller orbit), in increasing orbit order, with
+// their state, accumulators and step count; e is left unchanged.  The new
+// ensemble's orbits are numbered 0..n2-1; *orbit_out (device, may be
+// null) receives their caller indices in e.
+chx_status subset(chx_ensemble *e, const uint8_t *keep, chx_ensemble **out, int64_t **orbit_out) {
+  if (!out) return fail(CHX_ERR_INVALID_ARG, "output handle pointer is NULL");
+  *out = nullptr;
+  if (orbit_out) *orbit_out = nullptr;
+  if (!e) return fail(CHX_ERR_INVALID_ARG, "ensemble is NULL");
+  if (e->n_all > 0 && !keep) return fail(CHX_ERR_INVALID_ARG, "keep is NULL");
+  const hipStream_t s = e->stream;
+  const Plan &pl = e->pl;
+  const int D = pl.D, M = pl.M;
+  const int64_t na = e->n_active;
+  uint8_t *flag = nullptr;
+  int64_t *kpos = nullptr, *count = nullptr, *scratch = nullptr, *orbit = nullptr;
+  chx_ensemble *e2 = new chx_ensemble();
+  hipError_t he = hipSuccess;
+  auto cleanup = [&]() {
+    if (flag) hipFreeAsync(flag, s);
+    if (kpos) hipFreeAsync(kpos, s);
+    if (count) hipFreeAsync(count, s);
+    if (scratch) hipFreeAsync(scratch, s);
+  };
+  auto bail = [&](hipError_t err, const char *what) {
+    cleanup();
+    if (orbit) hipFreeAsync(orbit, s);
+    release(e2);
+    return dev_fail(err, what);
+  };
+  int64_t n2 = 0;
+  if (na > 0) {
+    if ((he = dalloc(&flag, (size_t)na, s))) return bail(he, "allocate flags");
+    if ((he = dalloc(&kpos, (size_t)na, s))) return bail(he, "allocate positions");
+    if ((he = dalloc(&count, 1, s))) return bail(he, "allocate count");
+    if ((he = dalloc(&scratch, (size_t)compact_scratch_len(na), s))) return bail(he, "allocate scratch");
+    if ((he = launch_keep_flags(keep, e->idx, na, flag, s))) return bail(he, "keep flags");
+    if ((he = launch_compact(flag, na, kpos, count, scratch, s))) return bail(he, "compact");
+    if ((he = hipMemcpyAsync(&n2, count, sizeof n2, hipMemcpyDeviceToHost, s))) return bail(he, "read count");
+    if ((he = hipStreamSynchronize(s))) return bail(he, "synchronise");
+  }
+  e2->kind = e->kind;
+  memcpy(e2->prm, e->prm, sizeof e2->prm);
+  e2->pl = pl;
+  e2->n_all = n2;
+  e2->n_active = n2;
+  e2->s_done = e->s_done;
+  e2->stream = s;
+  e2->device = e->device;
+  e2->block = e->block;
+  e2->pitch = n2 > 0 ? ((n2 + 63) / 64) * 64 : 64;
+  const int64_t P = e->pitch, P2 = e2->pitch;
+  const int rows_d = D + M * D + M + NSC, rows_i = M + 1;
+  if ((he = dalloc(&e2->state, (size_t)P2 * rows_d, s))) return bail(he, "allocate state");
+  if ((he = dalloc(&e2->istate, (size_t)P2 * rows_i, s))) return bail(he, "allocate state");
+  if (n2 > 0) {
+    if ((he = dalloc(&e2->x0, (size_t)n2 * D, s))) return bail(he, "allocate x0");
+    if ((he = dalloc(&e2->idx, (size_t)n2, s))) return bail(he, "allocate index");
+    if ((he = dalloc(&orbit, (size_t)n2, s))) return bail(he, "allocate orbit map");
+    if ((he = launch_gather_x0(e->x0, D, e->idx, kpos, n2, e2->x0, orbit, s))) return bail(he, "gather x0");
+    if ((he = launch_iota(e2->idx, n2, s))) return bail(he, "index");
+    if ((he = launch_gather_columns(e->state, P, e2->state, P2, rows_d, kpos, n2, s)))
+      return bail(he, "gather state");
+    if ((he = launch_gather_columns_i(e->istate, P, e2->istate, P2, rows_i, kpos, n2, s)))
+      return bail(he, "gather state");
+  }
+  StepArgs &a = e2->args;
+  a = e->args;
+  a.x = e2->state;
+  a.w = a.x + (size_t)D * P2;
+  a.gm = a.w + (size_t)M * D * P2;
+  a.sc = a.gm + (size_t)M * P2;
+  a.ge = e2->istate;
+  a.st = a.ge + (size_t)M * P2;
+  a.n = n2;
+  a.pitch = P2;
+  int64_t spl = pl.o.steps_per_launch;
+  if (spl == 0) spl = (n2 > 0) ? (int64_t)(5.0e10 / (double)n2) : pl.n_total;
+  spl = (spl / pl.K) * pl.K;
+  if (spl < pl.K) spl = pl.K;
+  e2->steps_per_launch = spl;
+  cleanup();
+  if (!e->device) {
+    if ((he = hipStreamSynchronize(s))) {
+      if (orbit) hipFreeAsync(orbit, s);
+      release(e2);
+      return dev_fail(he, "synchronise");
+    }
+  }
+  if (orbit_out) *orbit_out = orbit;
+  else if (orbit) hipFreeAsync(orbit, s);
+  *out = e2;
+  return CHX_OK;
+}
+
 chx_status run_once(const chx_system *sys, const double *x0, const uint8_t *mask, int64_t n,
                     const chx_options *opt, chx_result *res) {
   if (!res) return fail(CHX_ERR_INVALID_ARG, "result is NULL");
@@ -469,7 +539,10 @@ struct Stage {
 
 }  // namespace
 
-}  // namespace
+}  // namespace host
+}  // namespace chx
+
+using namespace chx::host;
 
 extern "C" {
 
@@ -489,6 +562,10 @@ size_t chx_struct_size(int32_t which) {
   case 0: return sizeof(chx_system);
   case 1: return sizeof(chx_options);
   case 2: return sizeof(chx_result);
+  case 3: return sizeof(chx_batch_item);
+  case 4: return sizeof(chx_batch_stats);
+  case 5: return sizeof(chx_gate_train_cfg);
+  case 6: return sizeof(chx_gate_stats);
   }
   return 0;
 }
@@ -523,6 +600,32 @@ chx_status chx_ensemble_info(const chx_ensemble *e, int64_t *n_total, int64_t *s
   if (s_done) *s_done = e->s_done;
   if (n_active) *n_active = e->n_active;
   return CHX_OK;
+}
+
+chx_status chx_ensemble_subset(chx_ensemble *e, const uint8_t *keep, chx_ensemble **out) {
+  g_err.clear();
+  if (!out) return fail(CHX_ERR_INVALID_ARG, "output handle pointer is NULL");
+  *out = nullptr;
+  if (!e) return fail(CHX_ERR_INVALID_ARG, "ensemble is NULL");
+  if (e->n_all > 0 && !keep) return fail(CHX_ERR_INVALID_ARG, "keep is NULL");
+  if (e->device || e->n_all == 0) return subset(e, keep, out, nullptr);
+  uint8_t *dk = nullptr;
+  hipError_t he = hipMallocAsync((void **)&dk, (size_t)e->n_all, e->stream);
+  if (he == hipSuccess) he = hipMemcpyAsync(dk, keep, (size_t)e->n_all, hipMemcpyHostToDevice, e->stream);
+  if (he != hipSuccess) {
+    if (dk) hipFreeAsync(dk, e->stream);
+    hipStreamSynchronize(e->stream);
+    return dev_fail(he, "stage keep");
+  }
+  chx_status st = subset(e, dk, out, nullptr);
+  hipFreeAsync(dk, e->stream);
+  he = hipStreamSynchronize(e->stream);
+  if (st == CHX_OK && he != hipSuccess) {
+    release(*out);
+    *out = nullptr;
+    return dev_fail(he, "synchronise");
+  }
+  return st;
 }
 
 void chx_ensemble_destroy(chx_ensemble *e) { release(e); }

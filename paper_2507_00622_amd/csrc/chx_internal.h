@@ -99,6 +99,19 @@ int64_t compact_scratch_len(int64_t n);
 hipError_t launch_compact(const uint8_t *mask, int64_t n, int64_t *idx,
                           int64_t *count, int64_t *scratch, hipStream_t s);
 
+// Subsets of an ensemble (prep.hip): flag[k] = keep[idx[k]]; column
+// gathers dst[r][j] = src[r][kpos[j]] for r < rows; x0 rows of the kept
+// orbits and their caller indices; p[i] = i.
+hipError_t launch_keep_flags(const uint8_t *keep, const int64_t *idx, int64_t n, uint8_t *flag,
+                             hipStream_t s);
+hipError_t launch_gather_columns(const double *src, int64_t ps, double *dst, int64_t pd, int rows,
+                                 const int64_t *kpos, int64_t n2, hipStream_t s);
+hipError_t launch_gather_columns_i(const int *src, int64_t ps, int *dst, int64_t pd, int rows,
+                                   const int64_t *kpos, int64_t n2, hipStream_t s);
+hipError_t launch_gather_x0(const double *x0, int D, const int64_t *idx, const int64_t *kpos,
+                            int64_t n2, double *x0_out, int64_t *orbit_out, hipStream_t s);
+hipError_t launch_iota(int64_t *p, int64_t n, hipStream_t s);
+
 hipError_t launch_hh_grid(double E, double y0, double y1, int ny, double py0,
                           double py1, int npy, double *x0, uint8_t *mask,
                           hipStream_t s);

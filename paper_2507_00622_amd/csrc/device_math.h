@@ -37,6 +37,15 @@ __device__ __forceinline__ double sqrt_ld(double a) {
   return __builtin_fma(s, r, s);
 }
 
+// Step coefficients of one launch.
+struct StepCoef {
+  double c0, c1, hk0, hk1, hkm, hdt;
+  __device__ explicit StepCoef(double dt)
+      : c0(YOSHIDA_W1 * dt), c1(YOSHIDA_W0 * dt), hk0((0.5 * YOSHIDA_W1) * dt),
+        hk1((0.5 * (YOSHIDA_W1 + YOSHIDA_W0)) * dt), hkm(2.0 * ((0.5 * YOSHIDA_W1) * dt)),
+        hdt(0.5 * dt) {}
+};
+
 // Keep a growth product as mantissa * 2^exponent: multiply the mantissa by
 // f and move its binary exponent into e.
 __device__ __forceinline__ void grow(double &m, int &e, double f) {

@@ -1,0 +1,53 @@
+// ensemble.h -- host-side ensemble object shared by the C ABI (api.hip) and
+// the batched launcher (batched_host.hip).
+#pragma once
+#include <string>
+
+#include "chx_internal.h"
+
+namespace chx {
+namespace host {
+
+// Options with defaults filled in, plus derived sizes.
+struct Plan {
+  chx_options o;
+  int N, D, m_s, n_l, M, K, kmax;
+  int64_t n_total;
+};
+
+chx_status fail(chx_status st, const char *fmt, ...);
+chx_status dev_fail(hipError_t e, const char *what);
+chx_status check_system(const chx_system *sys);
+chx_status make_plan(const chx_system *sys, const chx_options *opt, Plan *p);
+extern thread_local std::string g_err;
+
+}  // namespace host
+}  // namespace chx
+
+struct chx_ensemble {
+  int kind;
+  double prm[16];
+  chx::host::Plan pl;
+  int64_t n_all = 0, n_active = 0, pitch = 0, s_done = 0;
+  hipStream_t stream = nullptr;
+  bool device = false;
+  double *x0 = nullptr;      // [n_all][D] own copy
+  uint8_t *mask = nullptr;   // [n_all] own copy or null
+  int64_t *idx = nullptr;    // [n_active]
+  double *state = nullptr;   // x, w, gm, sc
+  int *istate = nullptr;     // ge, st
+  chx::StepArgs args{};
+  int block = 256;
+  int64_t steps_per_launch = 0;
+};
+
+namespace chx {
+namespace host {
+void release(chx_ensemble *e);
+chx_status create(const chx_system *sys, const double *x0, const uint8_t *mask, int64_t n,
+                  const chx_options *opt, chx_ensemble **out);
+chx_status advance(chx_ensemble *e, int64_t s_end);
+chx_status results(chx_ensemble *e, chx_result *res);
+chx_status subset(chx_ensemble *e, const uint8_t *keep, chx_ensemble **out, int64_t **orbit_out);
+}  // namespace host
+}  // namespace chx

@@ -1,4 +1,6 @@
-// fput_row.hip -- launcher of the row-per-orbit FPU kernels.
+// fput_row.hip -- launchers of the FPU kernels: component rows for up to
+// four deviation vectors, vector rows (up to 48 vectors) otherwise.
+#include "fput_crow.h"
 #include "fput_row.h"
 
 namespace chx {
@@ -6,6 +8,18 @@ namespace chx {
 namespace {
 template <int N>
 hipError_t launch_n(int M, const StepArgs &a, hipStream_t s) {
+  if (M <= 4) {
+    // 16 rows (orbits) per 256-thread block
+    const unsigned grid = (unsigned)((a.n + 15) / 16);
+    switch (M) {
+    case 0:
+    case 1: hipLaunchKernelGGL((fput_crow_kernel<N, 1>), dim3(grid), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((fput_crow_kernel<N, 2>), dim3(grid), dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((fput_crow_kernel<N, 3>), dim3(grid), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((fput_crow_kernel<N, 4>), dim3(grid), dim3(256), 0, s, a); break;
+    }
+    return hipGetLastError();
+  }
   const unsigned grid = (unsigned)((a.n + 3) / 4);
   const int V = (M + 15) / 16;
   if (V <= 1)
@@ -21,7 +35,8 @@ hipError_t launch_n(int M, const StepArgs &a, hipStream_t s) {
 bool fput_row_supported(int ndof, int M, int n_l, bool sali) {
   if (!(ndof == 2 || ndof == 4 || ndof == 8 || ndof == 16)) return false;
   if (M < 0 || M > 48) return false;
-  if (sali && n_l % 16 != 0) return false;
+  // vector rows keep the SALI pair in lanes 0 and 1 of one slot
+  if (M > 4 && sali && n_l % 16 != 0) return false;
   return true;
 }
 

@@ -4,6 +4,6 @@
 
 namespace chx {
 hipError_t launch_lane_harmonic2(int M, const StepArgs &a, int block, hipStream_t s) {
-  return LaneDispatch<SysHarmonic<2>, 8, 1>::go(M, a, block, s);
+  return LaneDispatch<SysHarmonic<2>, 8>::go(M, a, block, s);
 }
 }  // namespace chx

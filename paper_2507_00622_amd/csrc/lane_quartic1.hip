@@ -4,6 +4,6 @@
 
 namespace chx {
 hipError_t launch_lane_quartic1(int M, const StepArgs &a, int block, hipStream_t s) {
-  return LaneDispatch<SysQuartic<1>, 4, 1>::go(M, a, block, s);
+  return LaneDispatch<SysQuartic<1>, 4>::go(M, a, block, s);
 }
 }  // namespace chx

@@ -4,6 +4,6 @@
 
 namespace chx {
 hipError_t launch_lane_quartic3(int M, const StepArgs &a, int block, hipStream_t s) {
-  return LaneDispatch<SysQuartic<3>, 12, 1>::go(M, a, block, s);
+  return LaneDispatch<SysQuartic<3>, 12>::go(M, a, block, s);
 }
 }  // namespace chx

@@ -1,0 +1,57 @@
+// mlp.h -- kernels of the learned gate (mlp.hip) and its host object.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "chx_internal.h"
+
+namespace chx {
+
+constexpr int MLP_IN = 6;         // features
+constexpr int MLP_INP = 16;       // padded input width
+constexpr int MLP_H = 256;        // hidden width
+constexpr int MLP_OUTP = 16;      // padded logits (2 used)
+constexpr int MLP_STAT_BLOCKS = 256;
+// flat parameter layout
+constexpr int64_t MLP_W1 = 0;
+constexpr int64_t MLP_B1 = MLP_W1 + (int64_t)MLP_INP * MLP_H;
+constexpr int64_t MLP_W2 = MLP_B1 + MLP_H;
+constexpr int64_t MLP_B2 = MLP_W2 + (int64_t)MLP_H * MLP_H;
+constexpr int64_t MLP_W3 = MLP_B2 + MLP_H;
+constexpr int64_t MLP_B3 = MLP_W3 + (int64_t)MLP_H * MLP_OUTP;
+constexpr int64_t MLP_NPARAM = MLP_B3 + MLP_OUTP;
+
+hipError_t mlp_gemm(const uint16_t *A, int64_t a_r, int64_t a_c, const uint16_t *B, int64_t b_r,
+                    int64_t b_c, float *C, int64_t ldc, int M, int N, int K, const float *bias,
+                    int accumulate, hipStream_t s);
+hipError_t mlp_gelu(const float *Z, uint16_t *Ab, int64_t n, hipStream_t s);
+hipError_t mlp_gelu_back(const float *dA, const float *Z, float *dZ, uint16_t *dZb, int64_t n,
+                         hipStream_t s);
+hipError_t mlp_softmax_ce(const float *Z3, const int8_t *labels, const int64_t *rows, int B,
+                          int64_t n_valid, float inv, float *dZ3, uint16_t *dZ3b, float *loss_sum,
+                          hipStream_t s);
+hipError_t mlp_apply_mask(float *p, const uint8_t *mask, int64_t n, hipStream_t s);
+hipError_t mlp_colsum(const float *dZ, int B, int ncol, int64_t ld, float *db, hipStream_t s);
+hipError_t mlp_fill(float *p, int64_t n, float v, hipStream_t s);
+hipError_t gate_select(int64_t n, const int *status, const int8_t *label1, const float *pc,
+                       const float *conf, float conf_min, int8_t *label, uint8_t *source,
+                       uint8_t *keep, float *conf_out, unsigned long long *counts,
+                       hipStream_t s);
+hipError_t gate_scatter(int64_t n2, const int64_t *orbit, const int8_t *label2, int8_t *label,
+                        hipStream_t s);
+hipError_t mlp_adamw(float *p, const float *g, float *m, float *v, const uint8_t *mask, int64_t n,
+                     float lr, float b1, float b2, float eps, float wd, float bc1, float bc2,
+                     hipStream_t s);
+hipError_t mlp_to_bf16(const float *x, uint16_t *y, int64_t n, hipStream_t s);
+hipError_t mlp_batch_input(const float *feat, const int64_t *rows, int B, int64_t n_valid,
+                           const float *mean, const float *istd, uint16_t *X, hipStream_t s);
+hipError_t mlp_init_params(float *p, uint8_t *mask, uint64_t seed, hipStream_t s);
+hipError_t mlp_feature_stats(const float *feat, int64_t n, float *mean, float *istd,
+                             double *partials, hipStream_t s);
+hipError_t mlp_infer_out(const float *Z3, int B, float *pc, float *conf, hipStream_t s);
+hipError_t mlp_features(const double *x0, const double *ld, const double *lg, double t, int64_t n,
+                        float *out, hipStream_t s);
+hipError_t mlp_batch_rows(int64_t n, int64_t start, int B, uint64_t a, uint64_t c,
+                          int64_t *rows, hipStream_t s);
+
+}  // namespace chx

@@ -1,0 +1,482 @@
+// mlp.hip -- the learned gate: a 6 -> 256 -> 256 -> 2 perceptron with erf
+// GELU activations, trained and evaluated on the GPU by these kernels.
+//
+// Layout.  Inputs are padded to 16 features and the two logits to 16
+// columns so that every product is a whole number of 16x16x16 MFMA tiles;
+// the padded weights start at zero and receive zero gradients, so they stay
+// zero.  Master parameters are FP32 (flat: W1[16][256], b1[256],
+// W2[256][256], b2[256], W3[256][16], b3[16]); the products read BF16 copies
+// of weights and activations and accumulate in FP32
+// (v_mfma_f32_16x16x16_bf16).  Training: softmax cross-entropy on the two
+// logits, AdamW on the FP32 masters.
+#include <math.h>
+
+#include "mlp.h"
+
+namespace chx {
+
+namespace {
+
+typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+// float -> bf16 bits, round to nearest even (finite inputs; NaN stays NaN)
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// C[M][N] (fp32, row stride ldc) = A B (+ bias[col]) (+ C if accumulate),
+// A(i,k) = A[i*a_r + k*a_c], B(k,j) = B[k*b_r + j*b_c], both BF16.
+// One wavefront per 16x16 tile of C; M, N, K multiples of 16.
+__global__ void __launch_bounds__(256) gemm_bf16_kernel(const uint16_t *A, int64_t a_r,
+                                                        int64_t a_c, const uint16_t *B,
+                                                        int64_t b_r, int64_t b_c, float *C,
+                                                        int64_t ldc, int M, int N, int K,
+                                                        const float *bias, int accumulate) {
+  const int wave = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  const int tiles_n = N / 16;
+  const int tm = wave / tiles_n, tn = wave % tiles_n;
+  if (tm * 16 >= M) return;
+  const int row0 = tm * 16, col0 = tn * 16;
+  const int li = lane & 15, lk = 4 * (lane >> 4);
+  float4_t acc = {0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    short4_t a, b;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      a[e] = (short)A[(int64_t)(row0 + li) * a_r + (int64_t)(k0 + lk + e) * a_c];
+      b[e] = (short)B[(int64_t)(k0 + lk + e) * b_r + (int64_t)(col0 + li) * b_c];
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+  }
+  // lane holds D[4*(lane/16) + r][lane % 16]
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = row0 + lk + r, j = col0 + li;
+    float v = acc[r];
+    if (bias) v += bias[j];
+    float *dst = C + (int64_t)i * ldc + j;
+    *dst = accumulate ? *dst + v : v;
+  }
+}
+
+__device__ __forceinline__ float gelu(float z) {
+  return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+}
+__device__ __forceinline__ float gelu_grad(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
+         z * 0.39894228040143268f * expf(-0.5f * z * z);
+}
+
+// A = GELU(Z) as BF16 (and FP32 Z kept for the backward pass)
+__global__ void gelu_kernel(const float *Z, uint16_t *Ab, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) Ab[i] = f2bf(gelu(Z[i]));
+}
+
+// dZ = dA * GELU'(Z), as FP32 and BF16
+__global__ void gelu_back_kernel(const float *dA, const float *Z, float *dZ, uint16_t *dZb,
+                                 int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const float g = dA[i] * gelu_grad(Z[i]);
+    dZ[i] = g;
+    dZb[i] = f2bf(g);
+  }
+}
+
+// Softmax cross-entropy over logits Z3[r][0..1] (row stride 16).  Row r
+// reads label labels[src], src = rows ? rows[r] : r; rows with src outside
+// [0, n_valid) are padding.  Labels other than 0 and 1, and padding rows,
+// contribute neither loss nor gradient.  Writes the loss sum (atomic) and
+// dZ3 = (softmax - onehot) * inv in columns 0..1 (zero elsewhere), FP32 and
+// BF16.
+__global__ void softmax_ce_kernel(const float *Z3, const int8_t *labels, const int64_t *rows,
+                                  int B, int64_t n_valid, float inv, float *dZ3,
+                                  uint16_t *dZ3b, float *loss_sum) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  float l = 0.f;
+  if (r < B) {
+    const int64_t src = rows ? rows[r] : r;
+    const int y = (src >= 0 && src < n_valid) ? (int)labels[src] : -1;
+    float g0 = 0.f, g1 = 0.f;
+    if (y == 0 || y == 1) {
+      const float a = Z3[r * 16 + 0], b = Z3[r * 16 + 1];
+      const float m = fmaxf(a, b);
+      const float ea = expf(a - m), eb = expf(b - m), s = ea + eb;
+      const float pa = ea / s, pb = eb / s;
+      // -log softmax_y = log(s) - (z_y - m)
+      l = logf(s) - ((y ? b : a) - m);
+      g0 = (pa - (y == 0 ? 1.f : 0.f)) * inv;
+      g1 = (pb - (y == 1 ? 1.f : 0.f)) * inv;
+    }
+    for (int c = 0; c < 16; ++c) {
+      const float g = c == 0 ? g0 : (c == 1 ? g1 : 0.f);
+      dZ3[r * 16 + c] = g;
+      dZ3b[r * 16 + c] = f2bf(g);
+    }
+  }
+  // block reduction of the loss
+  __shared__ float part[4];
+  for (int off = 32; off > 0; off >>= 1) l += __shfl_down(l, off, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = l;
+  __syncthreads();
+  if (threadIdx.x == 0 && loss_sum) {
+    float t = 0.f;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += part[w];
+    atomicAdd(loss_sum, t);
+  }
+}
+
+// db[j] = sum_r dZ[r][j] (B rows, row stride ld): one block of 16 waves per
+// 64 columns, wave w summing rows w, w+16, ..., then the 16 partial sums
+// added in wave order (deterministic).
+__global__ void __launch_bounds__(1024) colsum_kernel(const float *dZ, int B, int ncol,
+                                                      int64_t ld, float *db) {
+  __shared__ float part[16][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + lane;
+  float acc = 0.f;
+  if (j < ncol)
+    for (int r = w; r < B; r += 16) acc += dZ[(int64_t)r * ld + j];
+  part[w][lane] = acc;
+  __syncthreads();
+  if (w == 0 && j < ncol) {
+    float t = 0.f;
+    for (int q = 0; q < 16; ++q) t += part[q][lane];
+    db[j] = t;
+  }
+}
+
+__global__ void fill_f32_kernel(float *p, int64_t n, float v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Gate selection per orbit from its status and label at the gate time and
+// the gate's output: masked -> label -1, source 0; stopped -> its label,
+// source 1; confident -> gate label, source 2; else keep for integration
+// to T, source 3.  counts[0..3] += orbits per source.
+__global__ void gate_select_kernel(int64_t n, const int *status, const int8_t *label1,
+                                   const float *pc, const float *conf, float conf_min,
+                                   int8_t *label, uint8_t *source, uint8_t *keep, float *conf_out,
+                                   unsigned long long *counts) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int src = -1;
+  if (i < n) {
+    const int st = status[i];
+    int8_t lb;
+    float cf = __builtin_nanf("");
+    uint8_t kp = 0;
+    if (st == CHX_ORBIT_MASKED) {
+      src = 0;
+      lb = -1;
+    } else if (st != CHX_ORBIT_OK) {
+      src = 1;
+      lb = label1[i];
+    } else {
+      cf = conf[i];
+      if (cf >= conf_min) {
+        src = 2;
+        lb = pc[i] >= 0.5f ? 1 : 0;
+      } else {
+        src = 3;
+        lb = -1;
+        kp = 1;
+      }
+    }
+    label[i] = lb;
+    if (source) source[i] = (uint8_t)src;
+    keep[i] = kp;
+    if (conf_out) conf_out[i] = cf;
+  }
+  for (int c = 0; c < 4; ++c) {
+    const uint64_t m = __ballot(src == c);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(&counts[c], (unsigned long long)__popcll(m));
+  }
+}
+
+// label[orbit[j]] = label2[j]
+__global__ void gate_scatter_kernel(int64_t n2, const int64_t *orbit, const int8_t *label2,
+                                    int8_t *label) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n2) label[orbit[j]] = label2[j];
+}
+
+__global__ void zero_u64_kernel(unsigned long long *p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+}
+
+// AdamW on the FP32 masters; mask[i] = 0 keeps padded entries at zero.
+__global__ void adamw_kernel(float *p, const float *g, float *m, float *v, const uint8_t *mask,
+                             int64_t n, float lr, float b1, float b2, float eps, float wd,
+                             float bc1, float bc2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !mask[i]) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float mh = mi / bc1, vh = vi / bc2;
+  p[i] = p[i] - lr * (mh / (sqrtf(vh) + eps) + wd * p[i]);
+}
+
+__global__ void to_bf16_kernel(const float *x, uint16_t *y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = f2bf(x[i]);
+}
+
+// X[r][0..15] = BF16 of the z-scored features of row rows[r] (zero pad;
+// rows at or past n_valid are all zero)
+__global__ void batch_input_kernel(const float *feat, const int64_t *rows, int B,
+                                   int64_t n_valid, const float *mean, const float *istd,
+                                   uint16_t *X) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= B) return;
+  const int64_t src = rows ? rows[r] : r;
+  const bool ok = src >= 0 && src < n_valid;
+  for (int c = 0; c < 16; ++c) {
+    const float v = (ok && c < MLP_IN) ? (feat[src * MLP_IN + c] - mean[c]) * istd[c] : 0.f;
+    X[r * 16 + c] = f2bf(v);
+  }
+}
+
+// Initial weights: N(0, 2/fan_in) on the real entries (SplitMix64 counters
+// and the Box-Muller cosine branch), zero biases and padding; mask marks
+// the real entries.
+__device__ inline uint64_t mlp_mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__global__ void init_params_kernel(float *p, uint8_t *mask, uint64_t seed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= MLP_NPARAM) return;
+  bool real;
+  double fan = 1.0;
+  bool bias = false;
+  if (i < MLP_B1) {
+    real = (i / MLP_H) < MLP_IN;
+    fan = MLP_IN;
+  } else if (i < MLP_W2) {
+    real = true;
+    bias = true;
+  } else if (i < MLP_B2) {
+    real = true;
+    fan = MLP_H;
+  } else if (i < MLP_W3) {
+    real = true;
+    bias = true;
+  } else if (i < MLP_B3) {
+    real = ((i - MLP_W3) % MLP_OUTP) < 2;
+    fan = MLP_H;
+  } else {
+    real = (i - MLP_B3) < 2;
+    bias = true;
+  }
+  mask[i] = real ? 1 : 0;
+  float v = 0.f;
+  if (real && !bias) {
+    const uint64_t key = mlp_mix64(seed ^ mlp_mix64(3));
+    const double u1 = (double)(mlp_mix64(key + (2 * i + 1) * 0x9E3779B97F4A7C15ull) >> 11) * 0x1.0p-53;
+    const double u2 = (double)(mlp_mix64(key + (2 * i + 2) * 0x9E3779B97F4A7C15ull) >> 11) * 0x1.0p-53;
+    const double z = sqrt(-2.0 * log(1.0 - u1)) * cos(2.0 * M_PI * u2);
+    v = (float)(z * sqrt(2.0 / fan));
+  }
+  p[i] = v;
+}
+
+// Z-score statistics of the features, in two passes: per-block partial
+// sums of v and v^2 (FP64), then mean and 1/std (population) per feature.
+__global__ void feature_partials_kernel(const float *feat, int64_t n, double *part) {
+  double a[MLP_IN], b[MLP_IN];
+  for (int c = 0; c < MLP_IN; ++c) a[c] = b[c] = 0.0;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    for (int c = 0; c < MLP_IN; ++c) {
+      const double v = feat[r * MLP_IN + c];
+      a[c] += v;
+      b[c] += v * v;
+    }
+  }
+  __shared__ double sa[256][2 * MLP_IN];
+  for (int c = 0; c < MLP_IN; ++c) {
+    sa[threadIdx.x][c] = a[c];
+    sa[threadIdx.x][MLP_IN + c] = b[c];
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * MLP_IN) {
+    double t = 0.0;
+    for (int k = 0; k < (int)blockDim.x; ++k) t += sa[k][threadIdx.x];
+    part[blockIdx.x * 2 * MLP_IN + threadIdx.x] = t;
+  }
+}
+__global__ void feature_stats_kernel(const double *part, int nblocks, int64_t n, float *mean,
+                                     float *istd) {
+  const int c = threadIdx.x;
+  if (c >= MLP_IN) return;
+  double a = 0.0, b = 0.0;
+  for (int k = 0; k < nblocks; ++k) {
+    a += part[k * 2 * MLP_IN + c];
+    b += part[k * 2 * MLP_IN + MLP_IN + c];
+  }
+  const double mu = a / (double)n;
+  const double var = b / (double)n - mu * mu;
+  mean[c] = (float)mu;
+  istd[c] = var > 0.0 ? (float)(1.0 / sqrt(var)) : 1.0f;
+}
+
+// Inference output: p(chaotic) and the confidence max(p, 1 - p).
+__global__ void infer_out_kernel(const float *Z3, int B, float *pc, float *conf) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= B) return;
+  const float a = Z3[r * 16 + 0], b = Z3[r * 16 + 1];
+  const float m = fmaxf(a, b);
+  const float ea = expf(a - m), eb = expf(b - m);
+  const float p1 = eb / (ea + eb);
+  if (pc) pc[r] = p1;
+  if (conf) conf[r] = fmaxf(p1, 1.f - p1);
+}
+
+// Gate features at time t: (y, p_y, p_x, LD/t, G1/t, G2/t) from the
+// initial conditions [n][4], the LD [n] and the ln-growths [n][2].
+__global__ void features_kernel(const double *x0, const double *ld, const double *lg, double t,
+                                int64_t n, float *out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[i * 6 + 0] = (float)x0[i * 4 + 1];
+  out[i * 6 + 1] = (float)x0[i * 4 + 3];
+  out[i * 6 + 2] = (float)x0[i * 4 + 2];
+  out[i * 6 + 3] = (float)(ld[i] / t);
+  out[i * 6 + 4] = (float)(lg[i * 2 + 0] / t);
+  out[i * 6 + 5] = (float)(lg[i * 2 + 1] / t);
+}
+
+// Rows of one batch: positions start .. start+B-1 of the epoch's
+// permutation i -> (a i + c) mod n (a coprime with n, so it is one);
+// positions at or past n are padding (-1).
+__global__ void batch_rows_kernel(int64_t n, int64_t start, int B, uint64_t a, uint64_t c,
+                                  int64_t *rows) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= B) return;
+  const int64_t i = start + r;
+  rows[r] = i < n ? (int64_t)((a * (uint64_t)i + c) % (uint64_t)n) : -1;
+}
+
+// p[i] *= mask[i] (keeps padded entries at zero after a load)
+__global__ void apply_mask_kernel(float *p, const uint8_t *mask, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !mask[i]) p[i] = 0.f;
+}
+
+inline unsigned nb(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t mlp_gemm(const uint16_t *A, int64_t a_r, int64_t a_c, const uint16_t *B, int64_t b_r,
+                    int64_t b_c, float *C, int64_t ldc, int M, int N, int K, const float *bias,
+                    int accumulate, hipStream_t s) {
+  if (M % 16 || N % 16 || K % 16) return hipErrorInvalidValue;
+  const int64_t waves = (int64_t)(M / 16) * (N / 16);
+  hipLaunchKernelGGL(gemm_bf16_kernel, dim3(nb(waves * 64)), dim3(256), 0, s, A, a_r, a_c, B,
+                     b_r, b_c, C, ldc, M, N, K, bias, accumulate);
+  return hipGetLastError();
+}
+
+hipError_t mlp_gelu(const float *Z, uint16_t *Ab, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(gelu_kernel, dim3(nb(n)), dim3(256), 0, s, Z, Ab, n);
+  return hipGetLastError();
+}
+hipError_t mlp_gelu_back(const float *dA, const float *Z, float *dZ, uint16_t *dZb, int64_t n,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(gelu_back_kernel, dim3(nb(n)), dim3(256), 0, s, dA, Z, dZ, dZb, n);
+  return hipGetLastError();
+}
+hipError_t mlp_softmax_ce(const float *Z3, const int8_t *labels, const int64_t *rows, int B,
+                          int64_t n_valid, float inv, float *dZ3, uint16_t *dZ3b, float *loss_sum,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(softmax_ce_kernel, dim3(nb(B)), dim3(256), 0, s, Z3, labels, rows, B, n_valid,
+                     inv, dZ3, dZ3b, loss_sum);
+  return hipGetLastError();
+}
+hipError_t mlp_colsum(const float *dZ, int B, int ncol, int64_t ld, float *db, hipStream_t s) {
+  hipLaunchKernelGGL(colsum_kernel, dim3(nb(ncol, 64)), dim3(1024), 0, s, dZ, B, ncol, ld, db);
+  return hipGetLastError();
+}
+hipError_t mlp_fill(float *p, int64_t n, float v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_f32_kernel, dim3(nb(n)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+hipError_t gate_select(int64_t n, const int *status, const int8_t *label1, const float *pc,
+                       const float *conf, float conf_min, int8_t *label, uint8_t *source,
+                       uint8_t *keep, float *conf_out, unsigned long long *counts,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, s, counts, 4);
+  if (n > 0)
+    hipLaunchKernelGGL(gate_select_kernel, dim3(nb(n)), dim3(256), 0, s, n, status, label1, pc,
+                       conf, conf_min, label, source, keep, conf_out, counts);
+  return hipGetLastError();
+}
+hipError_t gate_scatter(int64_t n2, const int64_t *orbit, const int8_t *label2, int8_t *label,
+                        hipStream_t s) {
+  if (n2 == 0) return hipSuccess;
+  hipLaunchKernelGGL(gate_scatter_kernel, dim3(nb(n2)), dim3(256), 0, s, n2, orbit, label2, label);
+  return hipGetLastError();
+}
+hipError_t mlp_adamw(float *p, const float *g, float *m, float *v, const uint8_t *mask, int64_t n,
+                     float lr, float b1, float b2, float eps, float wd, float bc1, float bc2,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(adamw_kernel, dim3(nb(n)), dim3(256), 0, s, p, g, m, v, mask, n, lr, b1, b2,
+                     eps, wd, bc1, bc2);
+  return hipGetLastError();
+}
+hipError_t mlp_to_bf16(const float *x, uint16_t *y, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(to_bf16_kernel, dim3(nb(n)), dim3(256), 0, s, x, y, n);
+  return hipGetLastError();
+}
+hipError_t mlp_batch_input(const float *feat, const int64_t *rows, int B, int64_t n_valid,
+                           const float *mean, const float *istd, uint16_t *X, hipStream_t s) {
+  hipLaunchKernelGGL(batch_input_kernel, dim3(nb(B)), dim3(256), 0, s, feat, rows, B, n_valid,
+                     mean, istd, X);
+  return hipGetLastError();
+}
+hipError_t mlp_init_params(float *p, uint8_t *mask, uint64_t seed, hipStream_t s) {
+  hipLaunchKernelGGL(init_params_kernel, dim3(nb(MLP_NPARAM)), dim3(256), 0, s, p, mask, seed);
+  return hipGetLastError();
+}
+hipError_t mlp_feature_stats(const float *feat, int64_t n, float *mean, float *istd,
+                             double *partials, hipStream_t s) {
+  hipLaunchKernelGGL(feature_partials_kernel, dim3(MLP_STAT_BLOCKS), dim3(256), 0, s, feat, n,
+                     partials);
+  hipLaunchKernelGGL(feature_stats_kernel, dim3(1), dim3(64), 0, s, partials, MLP_STAT_BLOCKS, n,
+                     mean, istd);
+  return hipGetLastError();
+}
+hipError_t mlp_infer_out(const float *Z3, int B, float *pc, float *conf, hipStream_t s) {
+  hipLaunchKernelGGL(infer_out_kernel, dim3(nb(B)), dim3(256), 0, s, Z3, B, pc, conf);
+  return hipGetLastError();
+}
+hipError_t mlp_features(const double *x0, const double *ld, const double *lg, double t, int64_t n,
+                        float *out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(features_kernel, dim3(nb(n)), dim3(256), 0, s, x0, ld, lg, t, n, out);
+  return hipGetLastError();
+}
+hipError_t mlp_apply_mask(float *p, const uint8_t *mask, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(apply_mask_kernel, dim3(nb(n)), dim3(256), 0, s, p, mask, n);
+  return hipGetLastError();
+}
+hipError_t mlp_batch_rows(int64_t n, int64_t start, int B, uint64_t a, uint64_t c,
+                          int64_t *rows, hipStream_t s) {
+  hipLaunchKernelGGL(batch_rows_kernel, dim3(nb(B)), dim3(256), 0, s, n, start, B, a, c, rows);
+  return hipGetLastError();
+}
+
+}  // namespace chx

@@ -305,6 +305,39 @@ __global__ void compact_scatter_kernel(const uint8_t *mask, int64_t n, const int
   }
 }
 
+// ---- subsets of an ensemble ------------------------------------------------
+// flag[k] = keep[idx[k]] (k over the active columns)
+__global__ void keep_flags_kernel(const uint8_t *keep, const int64_t *idx, int64_t n,
+                                  uint8_t *flag) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) flag[k] = keep[idx[k]] ? 1 : 0;
+}
+
+// dst[r][j] = src[r][kpos[j]] for rows r (blockIdx.y) and new columns j
+template <class T>
+__global__ void gather_columns_kernel(const T *src, int64_t ps, T *dst, int64_t pd,
+                                      const int64_t *kpos, int64_t n2) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t r = blockIdx.y;
+  if (j < n2) dst[r * pd + j] = src[r * ps + kpos[j]];
+}
+
+// x0_out[j] = x0[idx[kpos[j]]] (rows of D values), orbit_out[j] = idx[kpos[j]]
+__global__ void gather_x0_kernel(const double *x0, int D, const int64_t *idx,
+                                 const int64_t *kpos, int64_t n2, double *x0_out,
+                                 int64_t *orbit_out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n2) return;
+  const int64_t o = idx[kpos[j]];
+  for (int c = 0; c < D; ++c) x0_out[j * D + c] = x0[o * D + c];
+  if (orbit_out) orbit_out[j] = o;
+}
+
+__global__ void iota_kernel(int64_t *p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = i;
+}
+
 // ---- initial conditions ----------------------------------------------------
 // Henon-Heiles section x = 0: H = (px^2 + py^2)/2 + y^2/2 - y^3/3 there, so
 // px^2 = 2E - py^2 - y^2 + 2 y^3/3; px >= 0; negative: inaccessible.
@@ -459,6 +492,43 @@ hipError_t launch_masked_fill(const double *x0, const uint8_t *mask, int64_t n_a
   if (!mask || n_all == 0) return hipSuccess;
   hipLaunchKernelGGL(masked_fill_kernel, dim3(blocks_for(n_all)), dim3(TPB), 0, s, x0, mask,
                      n_all, ndof, oa, m_s, n_l);
+  return hipGetLastError();
+}
+
+hipError_t launch_keep_flags(const uint8_t *keep, const int64_t *idx, int64_t n, uint8_t *flag,
+                             hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(keep_flags_kernel, dim3(blocks_for(n)), dim3(TPB), 0, s, keep, idx, n, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_columns(const double *src, int64_t ps, double *dst, int64_t pd, int rows,
+                                 const int64_t *kpos, int64_t n2, hipStream_t s) {
+  if (n2 == 0 || rows == 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_columns_kernel<double>, dim3(blocks_for(n2), (unsigned)rows),
+                     dim3(TPB), 0, s, src, ps, dst, pd, kpos, n2);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_columns_i(const int *src, int64_t ps, int *dst, int64_t pd, int rows,
+                                   const int64_t *kpos, int64_t n2, hipStream_t s) {
+  if (n2 == 0 || rows == 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_columns_kernel<int>, dim3(blocks_for(n2), (unsigned)rows), dim3(TPB),
+                     0, s, src, ps, dst, pd, kpos, n2);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_x0(const double *x0, int D, const int64_t *idx, const int64_t *kpos,
+                            int64_t n2, double *x0_out, int64_t *orbit_out, hipStream_t s) {
+  if (n2 == 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_x0_kernel, dim3(blocks_for(n2)), dim3(TPB), 0, s, x0, D, idx, kpos,
+                     n2, x0_out, orbit_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_iota(int64_t *p, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(iota_kernel, dim3(blocks_for(n)), dim3(TPB), 0, s, p, n);
   return hipGetLastError();
 }
 

@@ -34,7 +34,11 @@ def test_struct_layouts_match_header():
     assert L.chx_struct_size(0) == C.sizeof(chx._System) == 24
     assert L.chx_struct_size(1) == C.sizeof(chx._Options) == 96
     assert L.chx_struct_size(2) == C.sizeof(chx._Result) == 12 * 8
-    assert L.chx_struct_size(3) == 0
+    assert L.chx_struct_size(3) == C.sizeof(chx._BatchItem) == 64
+    assert L.chx_struct_size(4) == C.sizeof(chx._BatchStats)
+    assert L.chx_struct_size(5) == C.sizeof(chx._GateTrainCfg) == 40
+    assert L.chx_struct_size(6) == C.sizeof(chx._GateStats) == 56
+    assert L.chx_struct_size(7) == 0
 
 
 def test_options_default():
@@ -117,9 +121,44 @@ def test_outputs_untouched_on_error():
     assert chx.lib().chx_last_error().decode() != ""
 
 
+def test_batched_validation():
+    x0 = hh_x0(4)
+    item = dict(sys=P.henon_heiles(), x0=x0, dt=0.01, T=1.0)
+    with pytest.raises(chx.ChxError, match="SALI"):
+        chx.integrate_batched([item], indicators=chx.IND_LD)
+    with pytest.raises(chx.ChxError, match="GALI or Lyapunov"):
+        chx.integrate_batched([item], indicators=chx.IND_SALI | chx.IND_LYAP)
+    with pytest.raises(chx.ChxError, match="multiple of renorm_every"):
+        chx.integrate_batched([dict(item, T=1.05)], indicators=chx.IND_SALI)
+    with pytest.raises(chx.ChxError, match="not supported"):
+        chx.integrate_batched([dict(item, sys=P.harmonic([1.0]), x0=np.zeros((2, 2)))],
+                              indicators=chx.IND_SALI)
+    with pytest.raises(chx.ChxError, match="n_items"):
+        chx.integrate_batched([item] * 5, indicators=chx.IND_SALI)
+
+
 def test_stream_without_device_flag_rejected():
     with pytest.raises(chx.ChxError, match="stream"):
         chx.lib()  # loaded
         cs = chx._check(chx.lib().chx_grid_hh_section(0.125, -0.4, 0.7, 4, -0.45, 0.45, 4,
                                                       None, None, 0, C.c_void_p(1)))
         del cs
+
+
+def test_gate_and_subset_validation():
+    L = chx.lib()
+    with pytest.raises(chx.ChxError, match="t must be"):
+        chx.gate_features(np.zeros((2, 4)), np.zeros(2), np.zeros((2, 2)), 0.0)
+    out = C.c_void_p()
+    assert L.chx_ensemble_subset(None, None, C.byref(out)) == chx.ERR_INVALID_ARG
+    assert "NULL" in L.chx_last_error().decode()
+    cs = P.henon_heiles()._c()
+    o = chx.make_options(dt=0.01, T=1.0, indicators=chx.IND_SALI | chx.IND_LD)
+    lab = np.zeros(2, np.int8)
+    st = L.chx_gate_classify(None, C.byref(cs), hh_x0(2).ctypes.data_as(C.c_void_p), None, 2,
+                             C.byref(o), 0.5, C.c_float(0.98), lab.ctypes.data_as(C.c_void_p),
+                             None, None, None)
+    assert st == chx.ERR_INVALID_ARG and "gate is NULL" in L.chx_last_error().decode()
+    cfg = chx._GateTrainCfg()
+    st = L.chx_gate_train(None, None, None, 0, C.byref(cfg), 0, None, 0, None)
+    assert st == chx.ERR_INVALID_ARG
