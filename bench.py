@@ -146,6 +146,10 @@ def flops_per_step_quartic(N, m_s, ld, energy, sali, K):
     return per + ck / K
 
 
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def emit(args, metric, value, unit, elapsed, dtype, config, roofline, cpu, higher=True):
     return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": elapsed / max(args.steps, 1) * 1e3,
@@ -193,6 +197,7 @@ def bench_fput(args, P, chx, torch, dev):
 
     def one_pass(record):
         for N in (8, 16):
+            progress(f"fput: N={N}, {n} orbits, T={T:g}")
             e = P.Ensemble(P.fput(N), x0s[N], steps_per_launch=spl, dt=dt, T=T, indicators=ind,
                            gali_kmax=N, n_lyap=2 * N, renorm_every=K, seed=1003,
                            outputs=("status", "lyap", "gali"))
@@ -276,6 +281,7 @@ def bench_batched(args, P, chx, torch, dev):
     kw = dict(indicators=ind, seed=1004, early_exit=True, sali_threshold=1e-8,
               steps_per_launch=args.steps_per_launch, block_size=args.block)
     outs_keys = ("status", "label", "t_end")
+    progress(f"batched: {n_orbits} orbits, T={T:g}")
     for _ in range(args.warmup):
         P.integrate_batched(items, outputs=outs_keys, **kw)
     torch.cuda.synchronize()
@@ -285,6 +291,7 @@ def bench_batched(args, P, chx, torch, dev):
         outs, stats = P.integrate_batched(items, outputs=outs_keys, **kw)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    progress(f"batched: {elapsed / args.steps:.2f} s per pass; plain launches")
     # three plain launches of the same work
     t1 = time.perf_counter()
     ref = []
@@ -342,6 +349,7 @@ def bench_gate(args, P, chx, torch, dev):
                                torch.as_tensor(py, device=dev))
     xt = x[m == 1][:n_train].contiguous()
     assert xt.shape[0] == n_train
+    progress(f"gate: labelling {n_train} training orbits to T={T:g}")
     t0 = time.perf_counter()
     e = P.Ensemble(P.henon_heiles(), xt, **kw)
     e.advance(s_gate)
@@ -352,12 +360,14 @@ def bench_gate(args, P, chx, torch, dev):
     e.close()
     torch.cuda.synchronize()
     t_label = time.perf_counter() - t0
+    progress(f"gate: labels done in {t_label:.1f} s; training")
     g = P.Gate(1005)
     t0 = time.perf_counter()
-    epochs = int(os.environ.get("CHX_GATE_EPOCHS", "6"))
+    epochs = args.gate_epochs
     losses = g.train(feat, lab, epochs=epochs, batch=4096, lr=1e-3, seed=1005)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    progress(f"gate: trained in {t_train:.1f} s, epoch losses {[round(float(v), 4) for v in losses]}")
     xg, mg = P.grid_hh_section(0.125, 2048, 2048, device=dev)
     n_test = int(mg.sum())
     for _ in range(args.warmup):
@@ -368,6 +378,7 @@ def bench_gate(args, P, chx, torch, dev):
         out, st = g.classify(P.henon_heiles(), xg, mg, t_gate=t_gate, conf_min=conf_min, **kw)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    progress(f"gate: classify {elapsed / args.steps:.2f} s per pass, {st}; plain run")
     t0 = time.perf_counter()
     ref = P.integrate_ensemble(P.henon_heiles(), xg, mask=mg, outputs=("label",), **kw)
     torch.cuda.synchronize()
@@ -378,6 +389,17 @@ def bench_gate(args, P, chx, torch, dev):
     acc_gated = float((out["label"][gated] == ref["label"][gated]).float().mean()) \
         if int(gated.sum()) else float("nan")
     value = n_test * args.steps / elapsed
+    # integration kernel of the gated run: every orbit to t_gate, the
+    # unconfident ones on to T (no early exit, no escapes at this energy)
+    n_total = int(round(T / dt))
+    steps_exec = st["n_active"] * s_gate + st["n_fallback"] * (n_total - s_gate)
+    fps = flops_per_step(2, 2, 0, True, False, True, 10)
+    kern_s = (st["ms_gate"] + st["ms_fallback"]) * 1e-3
+    achieved = fps * steps_exec / kern_s
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
+            "kernel": "chx::lane_kernel<SysHH, 2, false>", "flops_per_orbit_step": fps,
+            "launch_ms": None, "launches_timed": None}
     return emit(args, "labelled ICs/s (learned gate + fallback)", value, "ICs/s", elapsed,
                 "f64+bf16", {
                     "workload": f"Henon-Heiles E=0.125 2048x2048 section grid, labels by SALI<1e-8 "
@@ -394,7 +416,7 @@ def bench_gate(args, P, chx, torch, dev):
                     "label_generation_s": t_label, "train_s": t_train, "epochs": epochs,
                     "epoch_loss": [float(v) for v in losses],
                     "train_chaotic_fraction": float((lab == 1).float().mean())},
-                None, None)
+                roof, None)
 
 
 def parse():
@@ -415,6 +437,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=2048,
                     help="orbits in the oracle sample (strided over the workload)")
     ap.add_argument("--cpu-T", type=float, default=1e4)
+    ap.add_argument("--gate-epochs", type=int, default=6,
+                    help="training epochs of the gate workload")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes (calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")

@@ -266,7 +266,11 @@ __global__ void __launch_bounds__(256) lane_kernel(const StepArgs a) {
     // a stopped orbit leaves the loop; the write-back happens once, after it
     if (!o.checkpoint(a, (double)s * a.dt)) break;
   }
-  o.store(a, i);
+  // Hide the index from the optimiser so that the store addresses are formed
+  // here rather than kept in registers from the loads across the whole loop.
+  int64_t j = i;
+  asm volatile("" : "+v"(j));
+  o.store(a, j);
 }
 
 // Dispatch over the vector count for one system; the LD exponent 1/2 takes

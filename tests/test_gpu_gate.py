@@ -159,8 +159,13 @@ def test_adamw_step_matches_oracle(env):
     pr, _, _ = M.adamw(p.astype(np.float64), gg.astype(np.float64), np.zeros(M.NPARAM),
                        np.zeros(M.NPARAM), 1, lr=lr, wd=wd, keep=M.mask())
     d = np.abs(p1 - pr)
-    say(f"  max |dp| {d.max():.3e}")
-    assert d.max() <= 2e-6
+    # Where |g| is near eps the step g / (|g| + eps) is sensitive to the
+    # float32 rounding of g, which differs between the two passes (rows are
+    # summed in another order); elsewhere the step is fixed to float32 rounding.
+    firm = np.abs(gg) >= 1e-6
+    say(f"  max |dp| {d[firm].max():.3e} where |g| >= 1e-6, {d.max():.3e} overall")
+    assert d[firm].max() <= 2e-6
+    assert d.max() <= 2 * lr * (1.0 + wd * np.abs(p).max())
     assert np.all(p1[M.mask() == 0] == 0.0)
     g.close()
 
