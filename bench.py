@@ -398,7 +398,7 @@ def bench_gate(args, P, chx, torch, dev):
     achieved = fps * steps_exec / kern_s
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
-            "kernel": "chx::lane_kernel<SysHH, 2, false>", "flops_per_orbit_step": fps,
+            "kernel": "chx::lane_kernel<SysHH, 2, false, 2>", "flops_per_orbit_step": fps,
             "launch_ms": None, "launches_timed": None}
     return emit(args, "labelled ICs/s (learned gate + fallback)", value, "ICs/s", elapsed,
                 "f64+bf16", {
@@ -419,15 +419,69 @@ def bench_gate(args, P, chx, torch, dev):
                 roof, None)
 
 
+def bench_sweep(args, P, chx, torch, dev):
+    """Time per orbit against the number of orbits integrated together (the
+    shape of the paper's timing figures): Henon-Heiles at E = 0.125, seeded
+    accessible section points, SALI (two vectors) + LD, dt = 0.01, T = 200,
+    ensembles of 2^8 .. 2^22 orbits; the value is the largest ensemble's
+    orbit-steps/s."""
+    import numpy as np
+
+    import seeded_inputs as S
+    T = args.T or 200.0
+    dt = 0.01
+    n_steps = int(round(T / dt))
+    y, py = S.section_points(1001, int((1 << 22) * 1.35))
+    x, m = P.hh_section_points(0.125, torch.as_tensor(y, device=dev),
+                               torch.as_tensor(py, device=dev))
+    xa = x[m == 1][: 1 << 22].contiguous()
+    ind = chx.IND_SALI | chx.IND_LD
+    stream = torch.cuda.current_stream()
+    rows = []
+    for k in range(8, 23, 2):
+        n = 1 << k
+        xs = xa[:n].contiguous()
+        reps = max(1, min(20, (1 << 18) // n))
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        P.integrate_ensemble(P.henon_heiles(), xs, dt=dt, T=T, indicators=ind, seed=1001,
+                             outputs=("label",))
+        e0.record(stream)
+        for _ in range(reps):
+            P.integrate_ensemble(P.henon_heiles(), xs, dt=dt, T=T, indicators=ind, seed=1001,
+                                 outputs=("label",))
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        rows.append({"orbits": n, "ms": ms, "us_per_orbit": ms * 1e3 / n,
+                     "orbit_steps_per_s": n * n_steps / (ms * 1e-3)})
+        progress(f"sweep: {n} orbits, {ms:.2f} ms, {ms * 1e3 / n:.4f} us per orbit")
+    fps = flops_per_step(2, 2, 0, True, False, True, 10)
+    best = rows[-1]
+    achieved = fps * best["orbit_steps_per_s"]
+    return emit(args, "FP64 trajectory-steps/s (with tangents)", best["orbit_steps_per_s"],
+                "orbit-steps/s", best["ms"] * 1e-3 * args.steps, "f64", {
+                    "workload": f"henon-heiles E=0.125 seeded accessible section points, "
+                                f"SALI (2 vectors) + LD, dt={dt}, T={T:g}, ensembles of "
+                                f"2^8..2^22 orbits (each call includes set-up and results)",
+                    "sweep": rows},
+                {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
+                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
+                 "kernel": "chx::lane_kernel<SysHH, 2, false, 2>", "flops_per_orbit_step": fps,
+                 "launch_ms": None, "launches_timed": None}, None)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=("hh", "fput", "batched", "gate"), default="hh",
+    ap.add_argument("--workload", choices=("hh", "fput", "batched", "gate", "sweep"),
+                    default="hh",
                     help="hh: the headline Henon-Heiles grids (default); fput: FPU-beta "
                          "chains with 3N deviation vectors; batched: the persistent mixed "
-                         "form with early exit; gate: the learned gate against the plain form")
+                         "form with early exit; gate: the learned gate against the plain "
+                         "form; sweep: time per orbit against the ensemble size")
     ap.add_argument("--grid", type=int, default=1024, help="grid side per energy")
     ap.add_argument("--T", type=float, default=None,
                     help="final time (default: 1e4 for hh, gate and batched, 2e3 for fput)")
@@ -469,7 +523,8 @@ def main():
         print(json.dumps({"copy_bytes": args.copy_bytes}), flush=True)
         return
     if args.workload != "hh":
-        fn = {"fput": bench_fput, "batched": bench_batched, "gate": bench_gate}[args.workload]
+        fn = {"fput": bench_fput, "batched": bench_batched, "gate": bench_gate,
+              "sweep": bench_sweep}[args.workload]
         print(json.dumps(fn(args, P, chx, torch, dev)), flush=True)
         return
     if args.T is None:
@@ -572,7 +627,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64,
             "traffic": recorded_traffic(),
-            "kernel": "chx::lane_kernel<SysHH, 6, false>",
+            "kernel": "chx::lane_kernel<SysHH, 6, false, 2>",
             "flops_per_orbit_step": fps,
             "launch_ms": ms_avg,
             "launches_timed": len(full),

@@ -72,7 +72,7 @@ __device__ int64_t run_lane_pool(const Pool &pl, int64_t left) {
   const unsigned long long t0 = tail0_of(pl);
   const StepCoef k(a.dt);
   const int K = a.K;
-  LaneOrbit<S, 2, false> o;
+  LaneOrbit<S, 2, false, 2> o;
   int64_t idx = -1, s = 0;
   bool have = false;
   auto refill = [&]() {
@@ -166,7 +166,10 @@ __device__ int64_t run_crow_pool(const Pool &pl, int64_t left) {
   return left;
 }
 
-__global__ void __launch_bounds__(256) batched_kernel(const BatchArgs b) {
+// Three wavefronts per SIMD: the union of the four pool paths would take 180
+// VGPRs (two wavefronts); held to 168 the compiler spills 6 dwords, all
+// outside the step loops.
+__global__ void __launch_bounds__(256, 3) batched_kernel(const BatchArgs b) {
   const int wave = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   int p = 0;
   while (p + 1 < b.npool && wave >= b.split[p + 1]) ++p;

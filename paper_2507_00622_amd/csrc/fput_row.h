@@ -63,13 +63,21 @@ __device__ __forceinline__ double row_sum(double s) {
 
 }  // namespace fputrow
 
-template <int N, int V>
+// R rows per orbit (R = 1: four orbits per wavefront; R = 2: two).  Every
+// row of an orbit holds the whole state (the rows execute the same
+// instructions, so the copy costs nothing) and V vector slots per lane:
+// slot s of lane l in row r of the orbit is vector position
+// pos = (r V + s) 16 + l.
+template <int N, int V, int R>
 __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
   using namespace fputrow;
   constexpr int D = 2 * N;
-  __shared__ double piv[4][D];
+  constexpr int OPW = 4 / R;  // orbits per wavefront
+  __shared__ double piv[OPW][D];
+  __shared__ double piv2[OPW];
   const int lane = threadIdx.x & 15, row = threadIdx.x >> 4;
-  const int64_t o = (int64_t)blockIdx.x * 4 + row;
+  const int ow = row / R, ro = row % R;
+  const int64_t o = (int64_t)blockIdx.x * OPW + ow;
   const int64_t P = a.pitch;
   bool act = (o < a.n) && (a.st[o] == CHX_ORBIT_OK);
   const int64_t oo = act ? o : 0;  // inactive rows compute on a copy
@@ -84,7 +92,7 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
   int vk[V];  // vector index in the ensemble layout, -1 = unused slot
 #pragma unroll
   for (int s = 0; s < V; ++s) {
-    const int pos = s * 16 + lane;
+    const int pos = (ro * V + s) * 16 + lane;
     vk[s] = pos < n_l ? m_s + pos : (pos < M ? pos - n_l : -1);
     const int64_t k = vk[s] < 0 ? 0 : vk[s];
 #pragma unroll
@@ -136,21 +144,36 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
   auto kick_vectors = [&](double h) {
     const double hdiag = h * (kl + kr), hleft = h * kl;
     // component by component: the diagonal coefficient of component i and
-    // the coupling to component i+1 come from lanes i and i+1
+    // the coupling to component i+1 come from lanes i and i+1.  The
+    // broadcasts for component i+1 are issued before the updates of
+    // component i; empty volatile asm statements pin that order, because
+    // left free the compiler issues all 2N broadcasts first and holds them
+    // in registers at once.
     double Kcur = 0.0;
+    double Acur = bcast<0>(hdiag);
+    double Knext = N > 1 ? bcast<(N > 1 ? 1 : 0)>(hleft) : 0.0;
     static_for<0, N>([&](auto ic) {
       constexpr int i = decltype(ic)::value;
-      const double Ai = bcast<i>(hdiag);
-      double Knext = 0.0;
-      if constexpr (i + 1 < N) Knext = bcast<i + 1>(hleft);
+      double An = 0.0, Knn = 0.0;
+      if constexpr (i + 1 < N) {
+        An = bcast<i + 1>(hdiag);
+        asm volatile("" : "+v"(An));
+      }
+      if constexpr (i + 2 < N) {
+        Knn = bcast<i + 2>(hleft);
+        asm volatile("" : "+v"(Knn));
+      }
 #pragma unroll
       for (int s = 0; s < V; ++s) {
-        double acc = __builtin_fma(-Ai, w[s][i], w[s][N + i]);
+        double acc = __builtin_fma(-Acur, w[s][i], w[s][N + i]);
         if constexpr (i > 0) acc = __builtin_fma(Kcur, w[s][i - 1], acc);
         if constexpr (i + 1 < N) acc = __builtin_fma(Knext, w[s][i + 1], acc);
+        asm volatile("" : "+v"(acc));
         w[s][N + i] = acc;
       }
       Kcur = Knext;
+      Acur = An;
+      Knext = Knn;
     });
   };
   auto ld_integrand = [&]() {
@@ -175,9 +198,14 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
       gprev = g;
     }
   };
+  auto wave_sync = []() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
 
   // Checkpoint at t; returns false when the orbit stops.  Every decision is
-  // taken on row-uniform values.
+  // taken on values that are identical in all lanes of the orbit's rows.
   auto checkpoint = [&](double t) {
     tend = t;
     const bool bad = !(__builtin_isfinite(q) && __builtin_isfinite(p));
@@ -191,7 +219,7 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
     // SALI/GALI set: each vector back to unit length (lane-local)
 #pragma unroll
     for (int s = 0; s < V; ++s) {
-      const int pos = s * 16 + lane;
+      const int pos = (ro * V + s) * 16 + lane;
       if (pos >= n_l && pos < M) {
         double r2 = 0.0;
 #pragma unroll
@@ -204,9 +232,10 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
     }
     double s2 = 0.0;
     if (do_sali) {
-      // the SALI pair sits at positions n_l and n_l + 1 (lanes 0 and 1 of
-      // slot n_l / 16; the launcher requires n_l % 16 == 0)
-      const int s0 = n_l / 16;
+      // the SALI pair sits at positions n_l and n_l + 1: lanes 0 and 1 of
+      // slot n_l / 16 (the launcher requires n_l % 16 == 0), which is slot
+      // (n_l / 16) % V of the orbit's row (n_l / 16) / V
+      const int g0 = n_l / 16, r0 = g0 / V, s0 = g0 % V;
       double sp = 0.0, sm = 0.0;
 #pragma unroll
       for (int s = 0; s < V; ++s) {
@@ -220,54 +249,82 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
           }
         }
       }
-      s2 = bcast<0>(__builtin_fmin(sp, sm));
+      s2 = __builtin_fmin(sp, sm);
+      if constexpr (R == 1) {
+        s2 = bcast<0>(s2);
+      } else {
+        // lane 0 of the pair's row to every lane of the orbit
+        s2 = __shfl(s2, (ow * R + r0) * 16, 64);
+      }
       slast2 = s2;
       smin2 = __builtin_fmin(smin2, s2);
       if (s2 < a.thr2 && __builtin_isnan(tch)) tch = t;
     }
-    // Lyapunov set: modified Gram-Schmidt in vector order; the pivot's owner
-    // normalises it and stages it in LDS, every lane projects it out of its
-    // own later vectors.
+    // Lyapunov set: modified Gram-Schmidt in vector order.  The pivot's
+    // owner stages the vector (as it stands, not yet normalised) and its
+    // 1/|w|^2 in LDS; every lane of the orbit projects it out of its own
+    // later vectors: w_k -= (w_j . w_k / |w_j|^2) w_j, which is the
+    // projection on the normalised pivot.  Each lane remembers 1/|w| of
+    // its own slots and normalises them after the last pivot, so no lane
+    // rewrites its registers inside the owner-only branch.  A loop over
+    // the pivots (not unrolled) keeps the code small.
+    double invs[V];
 #pragma unroll
-    for (int j = 0; j < 16 * V; ++j) {
-      if (j < n_l) {
-        const int sj = j / 16, lj = j % 16;
-        if (lane == lj) {
+    for (int s = 0; s < V; ++s) invs[s] = 1.0;
+    for (int j = 0; j < n_l; ++j) {
+      const int gj = j >> 4, lj = j & 15, rj = gj / V, sj = gj % V;
+      const bool owner = ro == rj && lane == lj;
 #pragma unroll
-          for (int s = 0; s < V; ++s) {
-            if (s == sj) {
-              double r2 = 0.0;
+      for (int s = 0; s < V; ++s) {
+        if (s == sj && owner) {
+          double r2 = 0.0;
 #pragma unroll
-              for (int c = 0; c < D; ++c) r2 = __builtin_fma(w[s][c], w[s][c], r2);
-              const double inv = rsqrt_nr(r2);
+          for (int c = 0; c < D; ++c) r2 = __builtin_fma(w[s][c], w[s][c], r2);
+          const double inv = rsqrt_nr(r2);
+          invs[s] = inv;
+          grow(gm[s], ge[s], r2);
 #pragma unroll
-              for (int c = 0; c < D; ++c) {
-                w[s][c] *= inv;
-                piv[row][c] = w[s][c];
-              }
-              grow(gm[s], ge[s], r2);
-            }
-          }
+          for (int c = 0; c < D; ++c) piv[ow][c] = w[s][c];
+          piv2[ow] = inv * inv;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+      wave_sync();
+      const double i2 = piv2[ow];
+      double d[V];
+      bool later[V];
 #pragma unroll
-        for (int s = 0; s < V; ++s) {
-          if (s >= sj && s * 16 < n_l) {
-            const int pos = s * 16 + lane;
-            if (pos > j && pos < n_l) {
-              double d = 0.0;
+      for (int s = 0; s < V; ++s) {
+        const int pos = (ro * V + s) * 16 + lane;
+        later[s] = pos > j && pos < n_l;
+        d[s] = 0.0;
+      }
+      // The pivot is read from LDS in chunks of 8 components, once for the
+      // dot products and again for the update; the memory clobbers keep the
+      // compiler from loading all of it into registers at once.
 #pragma unroll
-              for (int c = 0; c < D; ++c) d = __builtin_fma(piv[row][c], w[s][c], d);
+      for (int c = 0; c < D; ++c) {
+        const double pc = piv[ow][c];
 #pragma unroll
-              for (int c = 0; c < D; ++c) w[s][c] = __builtin_fma(-d, piv[row][c], w[s][c]);
-            }
-          }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int s = 0; s < V; ++s) d[s] = __builtin_fma(pc, w[s][c], d[s]);
+        if (c % 8 == 7) asm volatile("" ::: "memory");
+      }
+#pragma unroll
+      for (int s = 0; s < V; ++s) d[s] *= i2;
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const double pc = piv[ow][c];
+#pragma unroll
+        for (int s = 0; s < V; ++s)
+          if (later[s]) w[s][c] = __builtin_fma(-d[s], pc, w[s][c]);
+        if (c % 8 == 7) asm volatile("" ::: "memory");
+      }
+      wave_sync();
+    }
+#pragma unroll
+    for (int s = 0; s < V; ++s) {
+      if ((ro * V + s) * 16 + lane < n_l) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) w[s][c] *= invs[s];
       }
     }
     if (do_energy) {
@@ -298,37 +355,37 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
     return true;
   };
 
-  auto store = [&]() {
-    if (mass) {
-      a.x[lane * P + o] = q;
-      a.x[(N + lane) * P + o] = p;
+  auto store = [&](int64_t ob) {
+    if (mass && ro == 0) {
+      a.x[lane * P + ob] = q;
+      a.x[(N + lane) * P + ob] = p;
     }
 #pragma unroll
     for (int s = 0; s < V; ++s) {
       if (vk[s] >= 0) {
         const int64_t k = vk[s];
 #pragma unroll
-        for (int c = 0; c < D; ++c) a.w[(k * D + c) * P + o] = w[s][c];
-        a.gm[k * P + o] = gm[s];
-        a.ge[k * P + o] = ge[s];
+        for (int c = 0; c < D; ++c) a.w[(k * D + c) * P + ob] = w[s][c];
+        a.gm[k * P + ob] = gm[s];
+        a.ge[k * P + ob] = ge[s];
       }
     }
-    if (lane == 0) {
-      a.sc[SC_LD * P + o] = ld;
-      a.sc[SC_GPREV * P + o] = gprev;
-      a.sc[SC_SALI_MIN2 * P + o] = smin2;
-      a.sc[SC_SALI_LAST2 * P + o] = slast2;
-      a.sc[SC_T_CHAOS * P + o] = tch;
-      a.sc[SC_EERR * P + o] = eerr;
-      a.sc[SC_T_END * P + o] = tend;
-      a.st[o] = st;
+    if (lane == 0 && ro == 0) {
+      a.sc[SC_LD * P + ob] = ld;
+      a.sc[SC_GPREV * P + ob] = gprev;
+      a.sc[SC_SALI_MIN2 * P + ob] = smin2;
+      a.sc[SC_SALI_LAST2 * P + ob] = slast2;
+      a.sc[SC_T_CHAOS * P + ob] = tch;
+      a.sc[SC_EERR * P + ob] = eerr;
+      a.sc[SC_T_END * P + ob] = tend;
+      a.st[ob] = st;
     }
   };
 
   springs();
   int64_t s = a.s_begin;
   const int64_t K = a.K;
-  // a row that stops leaves the loop; all rows write back once, after it
+  // an orbit that stops leaves the loop; all orbits write back once, after it
   while (act && s < a.s_end) {
     int64_t next = (s / K + 1) * K;
     if (next > a.n_total) next = a.n_total;
@@ -345,7 +402,10 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
     s = next;
     if (!checkpoint((double)s * dt)) break;
   }
-  if (o < a.n && a.st[o] == CHX_ORBIT_OK) store();
+  // the store addresses are formed here, not kept from the loads
+  int64_t ob = o;
+  asm volatile("" : "+v"(ob));
+  if (act) store(ob);
 }
 
 }  // namespace chx

@@ -20,14 +20,27 @@ hipError_t launch_n(int M, const StepArgs &a, hipStream_t s) {
     }
     return hipGetLastError();
   }
-  const unsigned grid = (unsigned)((a.n + 3) / 4);
+  // vector rows: V slots per lane while V * N <= 32 (at most 64 doubles of
+  // vectors per lane), one row per orbit; beyond that two rows per orbit
   const int V = (M + 15) / 16;
-  if (V <= 1)
-    hipLaunchKernelGGL((fput_row_kernel<N, 1>), dim3(grid), dim3(64), 0, s, a);
-  else if (V == 2)
-    hipLaunchKernelGGL((fput_row_kernel<N, 2>), dim3(grid), dim3(64), 0, s, a);
-  else
-    hipLaunchKernelGGL((fput_row_kernel<N, 3>), dim3(grid), dim3(64), 0, s, a);
+  if (V * N <= 32) {
+    const unsigned grid = (unsigned)((a.n + 3) / 4);
+    if (V <= 1)
+      hipLaunchKernelGGL((fput_row_kernel<N, 1, 1>), dim3(grid), dim3(64), 0, s, a);
+    else if (V == 2)
+      hipLaunchKernelGGL((fput_row_kernel<N, 2, 1>), dim3(grid), dim3(64), 0, s, a);
+    else if constexpr (N <= 8)
+      hipLaunchKernelGGL((fput_row_kernel<N, 3, 1>), dim3(grid), dim3(64), 0, s, a);
+    else
+      return hipErrorInvalidValue;
+  } else {
+    if constexpr (N == 16) {
+      const unsigned grid = (unsigned)((a.n + 1) / 2);
+      hipLaunchKernelGGL((fput_row_kernel<N, 2, 2>), dim3(grid), dim3(64), 0, s, a);
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
   return hipGetLastError();
 }
 }  // namespace

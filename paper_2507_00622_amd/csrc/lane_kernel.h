@@ -31,9 +31,13 @@
 
 namespace chx {
 
-template <class S, int M, bool GP>
+// MS >= 0 fixes the size of the SALI/GALI set at compile time (the rest of
+// the M vectors are the Lyapunov set), so the checkpoint has no branches on
+// it; MS = -1 reads it from the launch arguments.
+template <class S, int M, bool GP, int MS = -1>
 struct LaneOrbit {
   static constexpr int N = S::N, D = 2 * N, MM = (M > 0 ? M : 1);
+  static constexpr int UNROLL = (N == 2 && M >= 4) ? 2 : 1;
   double x[D], w[MM][D], gm[MM];
   int ge[MM];
   double ld, gprev, smin2, slast2, tch, eerr, H0, tend;
@@ -150,6 +154,10 @@ struct LaneOrbit {
     const bool do_ld = (a.ind & CHX_IND_LD) != 0;
     kick_state(k.hk0);
     kick_vectors(a, k.hk0);
+    // two steps per iteration saves register moves of the loop-carried
+    // values for 2-dof systems with several vectors; elsewhere it costs
+    // occupancy
+#pragma unroll(UNROLL)
     for (int s = 0; s + 1 < blk; ++s) {
       step_body(a, k, do_ld);
       kick_state(k.hk0);  // first kick of the next step
@@ -161,8 +169,8 @@ struct LaneOrbit {
 
   // Checkpoint at time t; returns false when the orbit stops (status set).
   __device__ bool checkpoint(const StepArgs &a, double t) {
-    const bool do_sali = (a.ind & CHX_IND_SALI) && a.m_s >= 2;
-    const int m_s = a.m_s;
+    const int m_s = MS >= 0 ? MS : a.m_s;
+    const bool do_sali = (a.ind & CHX_IND_SALI) && m_s >= 2;
     tend = t;
     bool finite = true;
 #pragma unroll
@@ -248,12 +256,12 @@ struct LaneOrbit {
   }
 };
 
-template <class S, int M, bool GP>
+template <class S, int M, bool GP, int MS>
 __global__ void __launch_bounds__(256) lane_kernel(const StepArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   if (a.st[i] != CHX_ORBIT_OK) return;
-  LaneOrbit<S, M, GP> o;
+  LaneOrbit<S, M, GP, MS> o;
   o.load(a, i);
   const StepCoef k(a.dt);
   int64_t s = a.s_begin;
@@ -282,9 +290,14 @@ struct LaneDispatch {
       const bool gp = (a.ind & CHX_IND_LD) && a.ld_p != 0.5;
       const int64_t grid = (a.n + block - 1) / block;
       if (gp)
-        hipLaunchKernelGGL((lane_kernel<S, M, true>), dim3((unsigned)grid), dim3(block), 0, s, a);
+        hipLaunchKernelGGL((lane_kernel<S, M, true, -1>), dim3((unsigned)grid), dim3(block), 0, s,
+                           a);
+      else if (M >= 2 && a.m_s == 2)  // the SALI pair (+ Lyapunov vectors)
+        hipLaunchKernelGGL((lane_kernel<S, M, false, (M >= 2 ? 2 : -1)>), dim3((unsigned)grid),
+                           dim3(block), 0, s, a);
       else
-        hipLaunchKernelGGL((lane_kernel<S, M, false>), dim3((unsigned)grid), dim3(block), 0, s, a);
+        hipLaunchKernelGGL((lane_kernel<S, M, false, -1>), dim3((unsigned)grid), dim3(block), 0,
+                           s, a);
       return hipGetLastError();
     }
     return LaneDispatch<S, M - 1>::go(m, a, block, s);

@@ -1,0 +1,50 @@
+"""The benchmark's command-line contract and its flop models (CPU only)."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_henon_heiles_flop_model():
+    # per step: 3 drifts (12) + 4 state kicks (16) + 3 forces (18) + 3 scaled
+    # Hessians (15) + 6 vectors x (3 kicks x 8 + 3 drifts x 4) + LD (6) = 283;
+    # checkpoint / 10: 2 renormalisations (26), SALI (22), 4-vector MGS
+    # (4 x 13 + 6 x 15 = 142), energy (14) -> 19.8
+    assert bench.flops_per_step(2, 2, 4, True, True, True, 10) == pytest.approx(302.8)
+    # the gate's and the batched form's two-vector kernels
+    assert bench.flops_per_step(2, 2, 0, True, False, True, 10) == pytest.approx(143.6)
+    assert bench.flops_per_step(2, 2, 0, False, True, True, 10) == pytest.approx(139.0)
+
+
+def test_fput_and_quartic_flop_models():
+    assert bench.flops_per_step_fput(16, 16, 32, False, True, True, 10) == pytest.approx(26202.0)
+    assert bench.flops_per_step_fput(8, 8, 16, False, True, True, 10) == pytest.approx(5999.6)
+    assert bench.flops_per_step_fput(16, 2, 0, False, True, True, 10) == pytest.approx(1797.2)
+    assert bench.flops_per_step_quartic(3, 2, False, True, True, 10) == pytest.approx(333.8)
+    # the vector work grows like M N and the Gram-Schmidt like n_l^2 N
+    a = bench.flops_per_step_fput(16, 0, 8, False, False, False, 10)
+    b = bench.flops_per_step_fput(16, 0, 16, False, False, False, 10)
+    assert b - a > 8 * 24 * 16
+
+
+def test_traffic_record_needs_matching_sources(tmp_path, monkeypatch):
+    f = tmp_path / "t.md"
+    f.write_text("kernel-source-sha256: `deadbeef`\ntraffic-bytes-per-launch: `123`\n")
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.recorded_traffic() is None
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "deadbeef")
+    assert bench.recorded_traffic() == 123.0
