@@ -251,7 +251,7 @@ def bench_fput(args, P, chx, torch, dev):
                               for N, v in per_n.items()}},
                 {"bound": "alu", "achieved": r["achieved"] / 1e12, "peak": PEAK_FP64 / 1e12,
                  "unit": "TFLOP/s", "frac": r["achieved"] / PEAK_FP64, "traffic": None,
-                 "kernel": "chx::fput_row_kernel<16, 3>", "flops_per_orbit_step": r["fps"],
+                 "kernel": "chx::fput_row_kernel<16, 2, 2>", "flops_per_orbit_step": r["fps"],
                  "launch_ms": r["ms"], "launches_timed": r["launches"]}, cpu)
 
 

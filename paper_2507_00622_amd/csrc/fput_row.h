@@ -67,7 +67,8 @@ __device__ __forceinline__ double row_sum(double s) {
 // row of an orbit holds the whole state (the rows execute the same
 // instructions, so the copy costs nothing) and V vector slots per lane:
 // slot s of lane l in row r of the orbit is vector position
-// pos = (r V + s) 16 + l.
+// pos = (s R + r) 16 + l -- the rows interleave, so the Lyapunov set (the
+// first positions) is spread over all rows of the orbit.
 template <int N, int V, int R>
 __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
   using namespace fputrow;
@@ -92,7 +93,7 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
   int vk[V];  // vector index in the ensemble layout, -1 = unused slot
 #pragma unroll
   for (int s = 0; s < V; ++s) {
-    const int pos = (ro * V + s) * 16 + lane;
+    const int pos = (s * R + ro) * 16 + lane;
     vk[s] = pos < n_l ? m_s + pos : (pos < M ? pos - n_l : -1);
     const int64_t k = vk[s] < 0 ? 0 : vk[s];
 #pragma unroll
@@ -219,7 +220,7 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
     // SALI/GALI set: each vector back to unit length (lane-local)
 #pragma unroll
     for (int s = 0; s < V; ++s) {
-      const int pos = (ro * V + s) * 16 + lane;
+      const int pos = (s * R + ro) * 16 + lane;
       if (pos >= n_l && pos < M) {
         double r2 = 0.0;
 #pragma unroll
@@ -233,9 +234,9 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
     double s2 = 0.0;
     if (do_sali) {
       // the SALI pair sits at positions n_l and n_l + 1: lanes 0 and 1 of
-      // slot n_l / 16 (the launcher requires n_l % 16 == 0), which is slot
-      // (n_l / 16) % V of the orbit's row (n_l / 16) / V
-      const int g0 = n_l / 16, r0 = g0 / V, s0 = g0 % V;
+      // group n_l / 16 (the launcher requires n_l % 16 == 0), which is slot
+      // (n_l / 16) / R of the orbit's row (n_l / 16) % R
+      const int g0 = n_l / 16, r0 = g0 % R, s0 = g0 / R;
       double sp = 0.0, sm = 0.0;
 #pragma unroll
       for (int s = 0; s < V; ++s) {
@@ -266,63 +267,78 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
     // later vectors: w_k -= (w_j . w_k / |w_j|^2) w_j, which is the
     // projection on the normalised pivot.  Each lane remembers 1/|w| of
     // its own slots and normalises them after the last pivot, so no lane
-    // rewrites its registers inside the owner-only branch.  A loop over
-    // the pivots (not unrolled) keeps the code small.
+    // rewrites its registers inside the owner-only branch.  Pivots come in
+    // groups of 16 (group G = slot G / R of row G % R); the group is a
+    // compile-time index and the 16 pivots of a group are a runtime loop,
+    // which keeps the code small.
     double invs[V];
 #pragma unroll
     for (int s = 0; s < V; ++s) invs[s] = 1.0;
-    for (int j = 0; j < n_l; ++j) {
-      const int gj = j >> 4, lj = j & 15, rj = gj / V, sj = gj % V;
-      const bool owner = ro == rj && lane == lj;
-#pragma unroll
-      for (int s = 0; s < V; ++s) {
-        if (s == sj && owner) {
+    const int nls = (n_l + 16 * R - 1) / (16 * R);  // slots holding Lyapunov vectors
+    static_for<0, V * R>([&](auto gc) {
+      constexpr int G = decltype(gc)::value;
+      constexpr int rj = G % R, sj = G / R;
+      int jend = n_l - G * 16;
+      if (jend > 16) jend = 16;
+      for (int lj = 0; lj < jend; ++lj) {
+        if (ro == rj && lane == lj) {
           double r2 = 0.0;
 #pragma unroll
-          for (int c = 0; c < D; ++c) r2 = __builtin_fma(w[s][c], w[s][c], r2);
+          for (int c = 0; c < D; ++c) r2 = __builtin_fma(w[sj][c], w[sj][c], r2);
           const double inv = rsqrt_nr(r2);
-          invs[s] = inv;
-          grow(gm[s], ge[s], r2);
+          invs[sj] = inv;
+          grow(gm[sj], ge[sj], r2);
 #pragma unroll
-          for (int c = 0; c < D; ++c) piv[ow][c] = w[s][c];
+          for (int c = 0; c < D; ++c) piv[ow][c] = w[sj][c];
           piv2[ow] = inv * inv;
         }
+        wave_sync();
+        const double i2 = piv2[ow];
+        // Slot s of this row is after the pivot if its group s R + ro is
+        // later, or is the pivot's group and the lane is later.  Slots
+        // before sj never are (no code for them), and slots from nls on
+        // hold no Lyapunov vector: the projection is instantiated for each
+        // possible nls and one is chosen by a uniform branch.
+        auto project = [&](auto lc) {
+          constexpr int L = decltype(lc)::value;
+          double d[V];
+          bool later[V];
+#pragma unroll
+          for (int s = 0; s < V; ++s) {
+            const int gs = s * R + ro;
+            later[s] = (gs > G || (gs == G && lane > lj)) && (gs * 16 + lane < n_l);
+            d[s] = 0.0;
+          }
+          // The pivot is read from LDS in chunks of 8 components, once for
+          // the dot products and again for the update; the memory clobbers
+          // keep the compiler from loading all of it into registers at once.
+#pragma unroll
+          for (int c = 0; c < D; ++c) {
+            const double pc = piv[ow][c];
+#pragma unroll
+            for (int s = sj; s < L; ++s) d[s] = __builtin_fma(pc, w[s][c], d[s]);
+            if (c % 8 == 7) asm volatile("" ::: "memory");
+          }
+#pragma unroll
+          for (int s = sj; s < L; ++s) d[s] *= i2;
+#pragma unroll
+          for (int c = 0; c < D; ++c) {
+            const double pc = piv[ow][c];
+#pragma unroll
+            for (int s = sj; s < L; ++s)
+              if (later[s]) w[s][c] = __builtin_fma(-d[s], pc, w[s][c]);
+            if (c % 8 == 7) asm volatile("" ::: "memory");
+          }
+        };
+        static_for<sj + 1, V + 1>([&](auto lc) {
+          if (nls == decltype(lc)::value) project(lc);
+        });
+        wave_sync();
       }
-      wave_sync();
-      const double i2 = piv2[ow];
-      double d[V];
-      bool later[V];
-#pragma unroll
-      for (int s = 0; s < V; ++s) {
-        const int pos = (ro * V + s) * 16 + lane;
-        later[s] = pos > j && pos < n_l;
-        d[s] = 0.0;
-      }
-      // The pivot is read from LDS in chunks of 8 components, once for the
-      // dot products and again for the update; the memory clobbers keep the
-      // compiler from loading all of it into registers at once.
-#pragma unroll
-      for (int c = 0; c < D; ++c) {
-        const double pc = piv[ow][c];
-#pragma unroll
-        for (int s = 0; s < V; ++s) d[s] = __builtin_fma(pc, w[s][c], d[s]);
-        if (c % 8 == 7) asm volatile("" ::: "memory");
-      }
-#pragma unroll
-      for (int s = 0; s < V; ++s) d[s] *= i2;
-#pragma unroll
-      for (int c = 0; c < D; ++c) {
-        const double pc = piv[ow][c];
-#pragma unroll
-        for (int s = 0; s < V; ++s)
-          if (later[s]) w[s][c] = __builtin_fma(-d[s], pc, w[s][c]);
-        if (c % 8 == 7) asm volatile("" ::: "memory");
-      }
-      wave_sync();
-    }
+    });
 #pragma unroll
     for (int s = 0; s < V; ++s) {
-      if ((ro * V + s) * 16 + lane < n_l) {
+      if ((s * R + ro) * 16 + lane < n_l) {
 #pragma unroll
         for (int c = 0; c < D; ++c) w[s][c] *= invs[s];
       }
