@@ -250,3 +250,49 @@ def test_classify_mixed_gate(env):
     assert np.array_equal(out["confidence"][gated], cf[gated])
     assert np.all(cf[gated] >= 0.75) and np.all(cf[src == 3] < 0.75)
     g.close()
+
+
+def test_trained_gate_gains_over_plain(env):
+    """The workflow end to end at reduced size: labels from the plain
+    integrator on 2^18 seeded accessible section points (T = 2000, features
+    at t = 200), a gate trained on them by the library's kernels, then a
+    fresh 256 x 256 grid classified with the gate and with the plain
+    integrator.  The gate must agree with the plain labels on >= 99 % of the
+    orbits while integrating to T only the orbits it is unsure of (the
+    gain: fewer orbit-steps than the plain run)."""
+    torch, P, M, O = env
+    say("case: trained gate vs plain (2^18 training orbits, 256^2 test grid, T=2000)")
+    dev = torch.device("cuda:0")
+    T, dt, tg = 2000.0, 0.01, 200.0
+    kw = dict(dt=dt, T=T, indicators=1 | 8, seed=21)
+    y, py = S.section_points(2101, 360000)
+    x, m = P.hh_section_points(0.125, torch.as_tensor(y, device=dev),
+                               torch.as_tensor(py, device=dev))
+    xt = x[m == 1][: 1 << 18].contiguous()
+    with P.Ensemble(P.henon_heiles(), xt, **kw) as e:
+        e.advance(int(round(tg / dt)))
+        r = e.results(("ld", "ln_growth"))
+        feat = P.gate_features(xt, r["ld"], r["ln_growth"], tg)
+        e.advance()
+        lab = e.results(("label",))["label"]
+    g = P.Gate(22)
+    losses = g.train(feat, lab, epochs=6, batch=4096, lr=1e-3, seed=23)
+    say("  epoch losses", np.round(losses, 4))
+    assert losses[-1] < losses[0]
+    xg, mg = P.grid_hh_section(0.125, 256, 256, device=dev)
+    out, st = g.classify(P.henon_heiles(), xg, mg, t_gate=tg, conf_min=0.98, **kw)
+    ref = P.integrate_ensemble(P.henon_heiles(), xg, mask=mg, outputs=("label",), **kw)
+    torch.cuda.synchronize()
+    act = (mg == 1).cpu().numpy()
+    gl, rl = out["label"].cpu().numpy()[act], ref["label"].cpu().numpy()[act]
+    src = out["source"].cpu().numpy()[act]
+    agree = np.mean(gl == rl)
+    n_total, n_gate = int(round(T / dt)), int(round(tg / dt))
+    steps_gate = st["n_active"] * n_gate + st["n_fallback"] * (n_total - n_gate)
+    steps_plain = st["n_active"] * n_total
+    say(f"  agreement {agree:.4f}, accepted {st['n_accepted']}, fallback {st['n_fallback']}, "
+        f"orbit-steps {steps_gate / steps_plain:.3f} of plain")
+    assert agree >= 0.99
+    assert np.all(gl[src == 3] == rl[src == 3])
+    assert steps_gate < 0.6 * steps_plain
+    g.close()
