@@ -144,12 +144,12 @@ hipError_t dalloc(T **p, size_t count, hipStream_t s) {
 void release(chx_ensemble *e) {
   if (!e) return;
   hipStream_t s = e->stream;
-  if (e->x0) hipFreeAsync(e->x0, s);
-  if (e->mask) hipFreeAsync(e->mask, s);
-  if (e->idx) hipFreeAsync(e->idx, s);
-  if (e->state) hipFreeAsync(e->state, s);
-  if (e->istate) hipFreeAsync(e->istate, s);
-  hipStreamSynchronize(s);
+  if (e->x0) (void)hipFreeAsync(e->x0, s);
+  if (e->mask) (void)hipFreeAsync(e->mask, s);
+  if (e->idx) (void)hipFreeAsync(e->idx, s);
+  if (e->state) (void)hipFreeAsync(e->state, s);
+  if (e->istate) (void)hipFreeAsync(e->istate, s);
+  (void)hipStreamSynchronize(s);
   delete e;
 }
 
@@ -184,9 +184,9 @@ chx_status create(const chx_system *sys, const double *x0, const uint8_t *mask, 
   int64_t *scratch = nullptr, *count = nullptr;
   hipError_t he = hipSuccess;
   auto bail = [&](hipError_t err, const char *what) {
-    if (w0) hipFreeAsync(w0, s);
-    if (scratch) hipFreeAsync(scratch, s);
-    if (count) hipFreeAsync(count, s);
+    if (w0) (void)hipFreeAsync(w0, s);
+    if (scratch) (void)hipFreeAsync(scratch, s);
+    if (count) (void)hipFreeAsync(count, s);
     release(e);
     return dev_fail(err, what);
   };
@@ -260,9 +260,9 @@ chx_status create(const chx_system *sys, const double *x0, const uint8_t *mask, 
   spl = (spl / pl.K) * pl.K;
   if (spl < pl.K) spl = pl.K;
   e->steps_per_launch = spl;
-  if (w0) hipFreeAsync(w0, s);
-  if (scratch) hipFreeAsync(scratch, s);
-  if (count) hipFreeAsync(count, s);
+  if (w0) (void)hipFreeAsync(w0, s);
+  if (scratch) (void)hipFreeAsync(scratch, s);
+  if (count) (void)hipFreeAsync(count, s);
   if (!device) {
     if ((he = hipStreamSynchronize(s))) {
       release(e);
@@ -349,8 +349,8 @@ chx_status results(chx_ensemble *e, chx_result *res) {
         hipError_t he = hipMallocAsync(o.dev, o.bytes, s);
         if (he != hipSuccess) {
           for (auto &q : outs)
-            if (*q.dev) hipFreeAsync(*q.dev, s);
-          hipStreamSynchronize(s);
+            if (*q.dev) (void)hipFreeAsync(*q.dev, s);
+          (void)hipStreamSynchronize(s);
           return dev_fail(he, "allocate outputs");
         }
       }
@@ -363,7 +363,7 @@ chx_status results(chx_ensemble *e, chx_result *res) {
     for (auto &o : outs)
       if (*o.dev && he == hipSuccess) he = hipMemcpyAsync(o.host, *o.dev, o.bytes, hipMemcpyDeviceToHost, s);
     for (auto &o : outs)
-      if (*o.dev) hipFreeAsync(*o.dev, s);
+      if (*o.dev) (void)hipFreeAsync(*o.dev, s);
     hipError_t h2 = hipStreamSynchronize(s);
     if (he == hipSuccess) he = h2;
   }
@@ -391,14 +391,14 @@ chx_status subset(chx_ensemble *e, const uint8_t *keep, chx_ensemble **out, int6
   chx_ensemble *e2 = new chx_ensemble();
   hipError_t he = hipSuccess;
   auto cleanup = [&]() {
-    if (flag) hipFreeAsync(flag, s);
-    if (kpos) hipFreeAsync(kpos, s);
-    if (count) hipFreeAsync(count, s);
-    if (scratch) hipFreeAsync(scratch, s);
+    if (flag) (void)hipFreeAsync(flag, s);
+    if (kpos) (void)hipFreeAsync(kpos, s);
+    if (count) (void)hipFreeAsync(count, s);
+    if (scratch) (void)hipFreeAsync(scratch, s);
   };
   auto bail = [&](hipError_t err, const char *what) {
     cleanup();
-    if (orbit) hipFreeAsync(orbit, s);
+    if (orbit) (void)hipFreeAsync(orbit, s);
     release(e2);
     return dev_fail(err, what);
   };
@@ -456,13 +456,13 @@ chx_status subset(chx_ensemble *e, const uint8_t *keep, chx_ensemble **out, int6
   cleanup();
   if (!e->device) {
     if ((he = hipStreamSynchronize(s))) {
-      if (orbit) hipFreeAsync(orbit, s);
+      if (orbit) (void)hipFreeAsync(orbit, s);
       release(e2);
       return dev_fail(he, "synchronise");
     }
   }
   if (orbit_out) *orbit_out = orbit;
-  else if (orbit) hipFreeAsync(orbit, s);
+  else if (orbit) (void)hipFreeAsync(orbit, s);
   *out = e2;
   return CHX_OK;
 }
@@ -527,7 +527,7 @@ struct Stage {
       err = hipMemcpyAsync(host, d, sizeof(T) * count, hipMemcpyDeviceToHost, s);
   }
   chx_status finish(const char *what) {
-    for (void *p : allocs) hipFreeAsync(p, s);
+    for (void *p : allocs) (void)hipFreeAsync(p, s);
     if (!device) {
       hipError_t e = hipStreamSynchronize(s);
       if (err == hipSuccess) err = e;
@@ -613,12 +613,12 @@ chx_status chx_ensemble_subset(chx_ensemble *e, const uint8_t *keep, chx_ensembl
   hipError_t he = hipMallocAsync((void **)&dk, (size_t)e->n_all, e->stream);
   if (he == hipSuccess) he = hipMemcpyAsync(dk, keep, (size_t)e->n_all, hipMemcpyHostToDevice, e->stream);
   if (he != hipSuccess) {
-    if (dk) hipFreeAsync(dk, e->stream);
-    hipStreamSynchronize(e->stream);
+    if (dk) (void)hipFreeAsync(dk, e->stream);
+    (void)hipStreamSynchronize(e->stream);
     return dev_fail(he, "stage keep");
   }
   chx_status st = subset(e, dk, out, nullptr);
-  hipFreeAsync(dk, e->stream);
+  (void)hipFreeAsync(dk, e->stream);
   he = hipStreamSynchronize(e->stream);
   if (st == CHX_OK && he != hipSuccess) {
     release(*out);

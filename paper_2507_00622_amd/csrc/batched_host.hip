@@ -128,14 +128,14 @@ chx_status probe_cost(const Pool &src, const Plan &pl, int threads, int blocks, 
     ok(hipEventSynchronize(e1));
     ok(hipEventElapsedTime(&ms, e0, e1));
   }
-  if (st) hipFreeAsync(st, s);
-  if (it) hipFreeAsync(it, s);
-  if (sdone) hipFreeAsync(sdone, s);
-  if (queue) hipFreeAsync(queue, s);
-  if (ctr) hipFreeAsync(ctr, s);
-  hipStreamSynchronize(s);
-  if (e0) hipEventDestroy(e0);
-  if (e1) hipEventDestroy(e1);
+  if (st) (void)hipFreeAsync(st, s);
+  if (it) (void)hipFreeAsync(it, s);
+  if (sdone) (void)hipFreeAsync(sdone, s);
+  if (queue) (void)hipFreeAsync(queue, s);
+  if (ctr) (void)hipFreeAsync(ctr, s);
+  (void)hipStreamSynchronize(s);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
   if (he != hipSuccess) return dev_fail(he, "autotune probe");
   *cost = (double)ms * 1e-3 / ((double)m * (double)b.budget);
   return CHX_OK;
@@ -190,20 +190,20 @@ extern "C" chx_status chx_integrate_batched(const chx_batch_item *items, int32_t
     return he == hipSuccess;
   };
   auto cleanup = [&]() {
-    if (exec) hipGraphExecDestroy(exec);
-    if (graph) hipGraphDestroy(graph);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
     if (bs) {
       for (auto &b : bufs) {
-        if (b.sdone) hipFreeAsync(b.sdone, bs);
-        if (b.queue) hipFreeAsync(b.queue, bs);
+        if (b.sdone) (void)hipFreeAsync(b.sdone, bs);
+        if (b.queue) (void)hipFreeAsync(b.queue, bs);
       }
-      if (ctr) hipFreeAsync(ctr, bs);
-      hipStreamSynchronize(bs);
-      hipStreamDestroy(bs);
+      if (ctr) (void)hipFreeAsync(ctr, bs);
+      (void)hipStreamSynchronize(bs);
+      (void)hipStreamDestroy(bs);
     }
-    if (ev) hipEventDestroy(ev);
-    if (t0) hipEventDestroy(t0);
-    if (t1) hipEventDestroy(t1);
+    if (ev) (void)hipEventDestroy(ev);
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
     for (auto *e : ens) release(e);
   };
 
@@ -250,8 +250,8 @@ extern "C" chx_status chx_integrate_batched(const chx_batch_item *items, int32_t
 
   // ---- autotune: block size, per-system cost, wave split, launch budget
   int dev = 0, ncu = 256;
-  hipGetDevice(&dev);
-  hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   std::vector<int> cands;
   if (opt->block_size) cands.push_back(opt->block_size);
   else cands = {64, 128, 256};
@@ -339,7 +339,7 @@ extern "C" chx_status chx_integrate_batched(const chx_batch_item *items, int32_t
   // ---- capture R launches in a graph, replay until every queue is empty
   const int R = 4;
   ok(hipStreamBeginCapture(bs, hipStreamCaptureModeThreadLocal));
-  for (int r = 0; r < R; ++r) launch_batched(b, blocks, best_threads, bs);
+  for (int r = 0; r < R; ++r) ok(launch_batched(b, blocks, best_threads, bs));
   ok(hipStreamEndCapture(bs, &graph));
   if (he == hipSuccess) ok(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
   unsigned long long hc[4 * MAX_POOLS];

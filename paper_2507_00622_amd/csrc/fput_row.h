@@ -17,9 +17,9 @@
 // lane's V vectors) -- no LDS, no readlane, no scalar memory.
 //
 // At checkpoints the Lyapunov set is orthonormalised by modified
-// Gram-Schmidt: the pivot's owner lane normalises it and stages it in LDS
-// (one 2N-double buffer per row), then every lane projects it out of its
-// own later vectors.  Row sums (energy, LD, escape radius) use a
+// Gram-Schmidt: the pivot's owner lane stages it in LDS, each lane of the
+// orbit reads one or two of its components, and every lane projects it out
+// of its own later vectors, taking the components by row_newbcast.  Row sums (energy, LD, escape radius) use a
 // quad_perm / half-mirror / mirror butterfly, so all 16 lanes hold the
 // same bits.
 #pragma once
@@ -52,6 +52,36 @@ __device__ __forceinline__ void static_for(Fn &&f) {
   }
 }
 
+// acc += coef(lane I of the row) * x in one instruction: v_fmac_f64 with
+// its first source read through row_newbcast:I (DPP on 64-bit operands
+// exists for this broadcast only)
+template <int I>
+__device__ __forceinline__ void fmac_bcast(double &acc, double coef, double x) {
+  asm("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+      : "+v"(acc)
+      : "v"(coef), "v"(x), "n"(I));
+}
+
+// the same, kept in program order with the other ordered ones (the
+// Gram-Schmidt sweeps: left free, the scheduler interleaves them into far
+// more live registers than the sweep needs)
+template <int I>
+__device__ __forceinline__ void fmac_bcast_ordered(double &acc, double coef, double x) {
+  asm volatile("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+               : "+v"(acc)
+               : "v"(coef), "v"(x), "n"(I));
+}
+
+// |v|^2 over D components with four partial sums, so that the FMAs are not
+// one dependent chain
+template <int D>
+__device__ __forceinline__ double norm2_4(const double *v) {
+  double p[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int c = 0; c < D; ++c) p[c & 3] = __builtin_fma(v[c], v[c], p[c & 3]);
+  return (p[0] + p[1]) + (p[2] + p[3]);
+}
+
 // sum over the 16 lanes of a row, identical in every lane
 __device__ __forceinline__ double row_sum(double s) {
   s += dpp<0xB1>(s);   // quad_perm [1,0,3,2]
@@ -74,8 +104,8 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
   using namespace fputrow;
   constexpr int D = 2 * N;
   constexpr int OPW = 4 / R;  // orbits per wavefront
-  __shared__ double piv[OPW][D];
-  __shared__ double piv2[OPW];
+  constexpr int CPL = (D + 15) / 16;  // pivot components per lane
+  __shared__ __align__(16) double piv[OPW][16][CPL];
   const int lane = threadIdx.x & 15, row = threadIdx.x >> 4;
   const int ow = row / R, ro = row % R;
   const int64_t o = (int64_t)blockIdx.x * OPW + ow;
@@ -143,38 +173,50 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
   };
   // dp_i -= h [(kappa_i + kappa_{i+1}) dq_i - kappa_i dq_{i-1} - kappa_{i+1} dq_{i+1}]
   auto kick_vectors = [&](double h) {
-    const double hdiag = h * (kl + kr), hleft = h * kl;
-    // component by component: the diagonal coefficient of component i and
-    // the coupling to component i+1 come from lanes i and i+1.  The
-    // broadcasts for component i+1 are issued before the updates of
-    // component i; empty volatile asm statements pin that order, because
-    // left free the compiler issues all 2N broadcasts first and holds them
-    // in registers at once.
-    double Kcur = 0.0;
-    double Acur = bcast<0>(hdiag);
-    double Knext = N > 1 ? bcast<(N > 1 ? 1 : 0)>(hleft) : 0.0;
-    static_for<0, N>([&](auto ic) {
-      constexpr int i = decltype(ic)::value;
-      double An = 0.0, Knn = 0.0;
-      if constexpr (i + 1 < N) {
-        An = bcast<i + 1>(hdiag);
-        asm volatile("" : "+v"(An));
-      }
-      if constexpr (i + 2 < N) {
-        Knn = bcast<i + 2>(hleft);
-        asm volatile("" : "+v"(Knn));
-      }
+    // Per lane: -h (kappa_l + kappa_{l+1}) and h kappa_l.  Every coupling of
+    // component i is taken from lane i or i+1 by the FMA itself
+    // (v_fmac_f64 with a row_newbcast source), so no broadcast moves.  The
+    // s_nop covers the two wait states a DPP read needs after the VALU
+    // write of its source.
+    double nhd = -(h * (kl + kr)), hl = h * kl;
+    asm volatile("s_nop 1" : "+v"(nhd), "+v"(hl));
+    // components in groups, the three FMAs of each component in stages,
+    // so that consecutive FMAs do not feed each other
+    constexpr int GS = V >= 2 ? 2 : 3;
+    static_for<0, (N + GS - 1) / GS>([&](auto gc) {
+      constexpr int i0 = decltype(gc)::value * GS;
+      double acc[GS][V];
+      static_for<0, GS>([&](auto jc) {
+        constexpr int j = decltype(jc)::value, i = i0 + j;
+        if constexpr (i < N) {
 #pragma unroll
-      for (int s = 0; s < V; ++s) {
-        double acc = __builtin_fma(-Acur, w[s][i], w[s][N + i]);
-        if constexpr (i > 0) acc = __builtin_fma(Kcur, w[s][i - 1], acc);
-        if constexpr (i + 1 < N) acc = __builtin_fma(Knext, w[s][i + 1], acc);
-        asm volatile("" : "+v"(acc));
-        w[s][N + i] = acc;
-      }
-      Kcur = Knext;
-      Acur = An;
-      Knext = Knn;
+          for (int s = 0; s < V; ++s) {
+            acc[j][s] = w[s][N + i];
+            fmac_bcast<i>(acc[j][s], nhd, w[s][i]);
+          }
+        }
+      });
+      static_for<0, GS>([&](auto jc) {
+        constexpr int j = decltype(jc)::value, i = i0 + j;
+        if constexpr (i < N && i > 0) {
+#pragma unroll
+          for (int s = 0; s < V; ++s) fmac_bcast<i>(acc[j][s], hl, w[s][i - 1]);
+        }
+      });
+      static_for<0, GS>([&](auto jc) {
+        constexpr int j = decltype(jc)::value, i = i0 + j;
+        if constexpr (i + 1 < N) {
+#pragma unroll
+          for (int s = 0; s < V; ++s) fmac_bcast<(i + 1 < N ? i + 1 : 0)>(acc[j][s], hl, w[s][i + 1]);
+        }
+      });
+      static_for<0, GS>([&](auto jc) {
+        constexpr int j = decltype(jc)::value, i = i0 + j;
+        if constexpr (i < N) {
+#pragma unroll
+          for (int s = 0; s < V; ++s) w[s][N + i] = acc[j][s];
+        }
+      });
     });
   };
   auto ld_integrand = [&]() {
@@ -222,9 +264,7 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
     for (int s = 0; s < V; ++s) {
       const int pos = (s * R + ro) * 16 + lane;
       if (pos >= n_l && pos < M) {
-        double r2 = 0.0;
-#pragma unroll
-        for (int c = 0; c < D; ++c) r2 = __builtin_fma(w[s][c], w[s][c], r2);
+        const double r2 = norm2_4<D>(w[s]);
         const double inv = rsqrt_nr(r2);
 #pragma unroll
         for (int c = 0; c < D; ++c) w[s][c] *= inv;
@@ -237,7 +277,7 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
       // group n_l / 16 (the launcher requires n_l % 16 == 0), which is slot
       // (n_l / 16) / R of the orbit's row (n_l / 16) % R
       const int g0 = n_l / 16, r0 = g0 % R, s0 = g0 / R;
-      double sp = 0.0, sm = 0.0;
+      double sp[2] = {0.0, 0.0}, sm[2] = {0.0, 0.0};
 #pragma unroll
       for (int s = 0; s < V; ++s) {
         if (s == s0) {
@@ -245,12 +285,12 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
           for (int c = 0; c < D; ++c) {
             const double other = bcast<1>(w[s][c]);
             const double ap = w[s][c] + other, am = w[s][c] - other;
-            sp = __builtin_fma(ap, ap, sp);
-            sm = __builtin_fma(am, am, sm);
+            sp[c & 1] = __builtin_fma(ap, ap, sp[c & 1]);
+            sm[c & 1] = __builtin_fma(am, am, sm[c & 1]);
           }
         }
       }
-      s2 = __builtin_fmin(sp, sm);
+      s2 = __builtin_fmin(sp[0] + sp[1], sm[0] + sm[1]);
       if constexpr (R == 1) {
         s2 = bcast<0>(s2);
       } else {
@@ -262,15 +302,17 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
       if (s2 < a.thr2 && __builtin_isnan(tch)) tch = t;
     }
     // Lyapunov set: modified Gram-Schmidt in vector order.  The pivot's
-    // owner stages the vector (as it stands, not yet normalised) and its
-    // 1/|w|^2 in LDS; every lane of the orbit projects it out of its own
-    // later vectors: w_k -= (w_j . w_k / |w_j|^2) w_j, which is the
-    // projection on the normalised pivot.  Each lane remembers 1/|w| of
-    // its own slots and normalises them after the last pivot, so no lane
-    // rewrites its registers inside the owner-only branch.  Pivots come in
-    // groups of 16 (group G = slot G / R of row G % R); the group is a
-    // compile-time index and the 16 pivots of a group are a runtime loop,
-    // which keeps the code small.
+    // owner stages the vector as it stands (orthogonal to the earlier
+    // pivots, not yet normalised) in LDS, spread over the lanes: lane i of
+    // every row of the orbit reads components i and i + 16.  Its squared
+    // norm is a row sum (the same bits in every lane of the orbit), and the
+    // dot products and updates take component c through the FMA's
+    // row_newbcast operand from lane c % 16, so the pivot costs one LDS
+    // read per lane.  w_k -= (w_j . w_k / |w_j|^2) w_j is the projection on
+    // the normalised pivot; each lane remembers 1/|w| of its own slots and
+    // normalises them after the last pivot.  Pivots come in groups of 16
+    // (group G = slot G / R of row G % R); the group is a compile-time
+    // index and the 16 pivots of a group are a runtime loop.
     double invs[V];
 #pragma unroll
     for (int s = 0; s < V; ++s) invs[s] = 1.0;
@@ -281,54 +323,68 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
       int jend = n_l - G * 16;
       if (jend > 16) jend = 16;
       for (int lj = 0; lj < jend; ++lj) {
-        if (ro == rj && lane == lj) {
-          double r2 = 0.0;
+        const bool owner = ro == rj && lane == lj;
+        if (owner) {
 #pragma unroll
-          for (int c = 0; c < D; ++c) r2 = __builtin_fma(w[sj][c], w[sj][c], r2);
-          const double inv = rsqrt_nr(r2);
-          invs[sj] = inv;
-          grow(gm[sj], ge[sj], r2);
+          for (int i = 0; i < 16; ++i)
 #pragma unroll
-          for (int c = 0; c < D; ++c) piv[ow][c] = w[sj][c];
-          piv2[ow] = inv * inv;
+            for (int k = 0; k < CPL; ++k)
+              piv[ow][i][k] = k * 16 + i < D ? w[sj][k * 16 + i] : 0.0;
         }
         wave_sync();
-        const double i2 = piv2[ow];
+        double pc[CPL];
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) pc[k] = piv[ow][lane][k];
+        // DPP reads of pc follow; keep two wait states after its load
+        if constexpr (CPL == 2)
+          asm volatile("s_nop 1" : "+v"(pc[0]), "+v"(pc[1]));
+        else
+          asm volatile("s_nop 1" : "+v"(pc[0]));
+        double r2 = pc[0] * pc[0];
+        if constexpr (CPL == 2) r2 = __builtin_fma(pc[1], pc[1], r2);
+        r2 = row_sum(r2);
+        const double inv = rsqrt_nr(r2);
+        const double i2 = inv * inv;
+        {
+          double g = gm[sj];
+          int e = ge[sj];
+          grow(g, e, r2);
+          gm[sj] = owner ? g : gm[sj];
+          ge[sj] = owner ? e : ge[sj];
+          invs[sj] = owner ? inv : invs[sj];
+        }
         // Slot s of this row is after the pivot if its group s R + ro is
         // later, or is the pivot's group and the lane is later.  Slots
         // before sj never are (no code for them), and slots from nls on
         // hold no Lyapunov vector: the projection is instantiated for each
-        // possible nls and one is chosen by a uniform branch.
+        // possible nls and one is chosen by a uniform branch.  Slots that
+        // are not later take a zero coefficient.
         auto project = [&](auto lc) {
           constexpr int L = decltype(lc)::value;
-          double d[V];
-          bool later[V];
+          constexpr int PS = 4;  // partial sums per dot product
+          double d[V][PS];
 #pragma unroll
-          for (int s = 0; s < V; ++s) {
+          for (int s = 0; s < V; ++s)
+#pragma unroll
+            for (int k = 0; k < PS; ++k) d[s][k] = 0.0;
+          static_for<0, D>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+#pragma unroll
+            for (int s = sj; s < L; ++s) fmac_bcast_ordered<c % 16>(d[s][c % PS], pc[c / 16], w[s][c]);
+          });
+          double nd[V];
+#pragma unroll
+          for (int s = sj; s < L; ++s) {
             const int gs = s * R + ro;
-            later[s] = (gs > G || (gs == G && lane > lj)) && (gs * 16 + lane < n_l);
-            d[s] = 0.0;
+            const bool later = (gs > G || (gs == G && lane > lj)) && (gs * 16 + lane < n_l);
+            const double t = (d[s][0] + d[s][1]) + (d[s][2] + d[s][3]);
+            nd[s] = later ? -(t * i2) : 0.0;
           }
-          // The pivot is read from LDS in chunks of 8 components, once for
-          // the dot products and again for the update; the memory clobbers
-          // keep the compiler from loading all of it into registers at once.
+          static_for<0, D>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
 #pragma unroll
-          for (int c = 0; c < D; ++c) {
-            const double pc = piv[ow][c];
-#pragma unroll
-            for (int s = sj; s < L; ++s) d[s] = __builtin_fma(pc, w[s][c], d[s]);
-            if (c % 8 == 7) asm volatile("" ::: "memory");
-          }
-#pragma unroll
-          for (int s = sj; s < L; ++s) d[s] *= i2;
-#pragma unroll
-          for (int c = 0; c < D; ++c) {
-            const double pc = piv[ow][c];
-#pragma unroll
-            for (int s = sj; s < L; ++s)
-              if (later[s]) w[s][c] = __builtin_fma(-d[s], pc, w[s][c]);
-            if (c % 8 == 7) asm volatile("" ::: "memory");
-          }
+            for (int s = sj; s < L; ++s) fmac_bcast_ordered<c % 16>(w[s][c], pc[c / 16], nd[s]);
+          });
         };
         static_for<sj + 1, V + 1>([&](auto lc) {
           if (nls == decltype(lc)::value) project(lc);

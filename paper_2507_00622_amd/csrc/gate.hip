@@ -78,7 +78,7 @@ struct Scratch {
     return p;
   }
   ~Scratch() {
-    for (void *p : ptrs) hipFreeAsync(p, s);
+    for (void *p : ptrs) (void)hipFreeAsync(p, s);
   }
 };
 
@@ -86,6 +86,7 @@ struct Scratch {
 struct Acts {
   uint16_t *X, *A1b, *A2b, *dZ3b, *dZ2b, *dZ1b;
   float *Z1, *Z2, *Z3, *dZ3, *dA2, *dZ2, *dA1, *dZ1;
+  float *part;  // column-sum partials
   int64_t *rows;
 };
 
@@ -107,6 +108,7 @@ bool alloc_acts(Scratch &S, int64_t B, bool backward, Acts *a) {
     a->dZ1 = S.get<float>(B * MLP_H);
     a->dZ1b = S.get<uint16_t>(B * MLP_H);
     a->rows = S.get<int64_t>(B);
+    a->part = S.get<float>((size_t)mlp_colsum_blocks((int)B) * MLP_H);
   }
   return S.err == hipSuccess;
 }
@@ -142,7 +144,7 @@ hipError_t backward(chx_gate *g, const Acts &a, int B, const int8_t *labels, con
   if ((e = mlp_gemm(a.A2b, 1, MLP_H, a.dZ3b, MLP_OUTP, 1, gr + MLP_W3, MLP_OUTP, MLP_H, MLP_OUTP,
                     B, nullptr, 0, s)))
     return e;
-  if ((e = mlp_colsum(a.dZ3, B, MLP_OUTP, MLP_OUTP, gr + MLP_B3, s))) return e;
+  if ((e = mlp_colsum(a.dZ3, B, MLP_OUTP, MLP_OUTP, gr + MLP_B3, a.part, s))) return e;
   if ((e = mlp_gemm(a.dZ3b, MLP_OUTP, 1, pb + MLP_W3, 1, MLP_OUTP, a.dA2, MLP_H, B, MLP_H,
                     MLP_OUTP, nullptr, 0, s)))
     return e;
@@ -151,7 +153,7 @@ hipError_t backward(chx_gate *g, const Acts &a, int B, const int8_t *labels, con
   if ((e = mlp_gemm(a.A1b, 1, MLP_H, a.dZ2b, MLP_H, 1, gr + MLP_W2, MLP_H, MLP_H, MLP_H, B,
                     nullptr, 0, s)))
     return e;
-  if ((e = mlp_colsum(a.dZ2, B, MLP_H, MLP_H, gr + MLP_B2, s))) return e;
+  if ((e = mlp_colsum(a.dZ2, B, MLP_H, MLP_H, gr + MLP_B2, a.part, s))) return e;
   if ((e = mlp_gemm(a.dZ2b, MLP_H, 1, pb + MLP_W2, 1, MLP_H, a.dA1, MLP_H, B, MLP_H, MLP_H,
                     nullptr, 0, s)))
     return e;
@@ -160,7 +162,7 @@ hipError_t backward(chx_gate *g, const Acts &a, int B, const int8_t *labels, con
   if ((e = mlp_gemm(a.X, 1, MLP_INP, a.dZ1b, MLP_H, 1, gr + MLP_W1, MLP_H, MLP_INP, MLP_H, B,
                     nullptr, 0, s)))
     return e;
-  return mlp_colsum(a.dZ1, B, MLP_H, MLP_H, gr + MLP_B1, s);
+  return mlp_colsum(a.dZ1, B, MLP_H, MLP_H, gr + MLP_B1, a.part, s);
 }
 
 // p(chaotic) and confidence of n rows of device features.
@@ -238,10 +240,10 @@ chx_status chx_gate_create(uint64_t seed, chx_gate **out) {
 
 void chx_gate_destroy(chx_gate *g) {
   if (!g) return;
-  hipDeviceSynchronize();
+  (void)hipDeviceSynchronize();
   for (void *p : {(void *)g->p, (void *)g->m, (void *)g->v, (void *)g->g, (void *)g->mask,
                   (void *)g->pb, (void *)g->mean, (void *)g->istd, (void *)g->partials})
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
   delete g;
 }
 
@@ -495,7 +497,7 @@ chx_status chx_gate_classify(const chx_gate *g, const chx_system *sys, const dou
     hipEvent_t *ev;
     ~EvGuard() {
       for (int i = 0; i < 4; ++i)
-        if (ev[i]) hipEventDestroy(ev[i]);
+        if (ev[i]) (void)hipEventDestroy(ev[i]);
     }
   } evg{ev};
 
@@ -511,7 +513,7 @@ chx_status chx_gate_classify(const chx_gate *g, const chx_system *sys, const dou
     int64_t **orbit;
     hipStream_t s;
     ~EnsGuard() {
-      if (*orbit) hipFreeAsync(*orbit, s);
+      if (*orbit) (void)hipFreeAsync(*orbit, s);
       release(*a);
       release(*b);
     }
@@ -563,9 +565,9 @@ chx_status chx_gate_classify(const chx_gate *g, const chx_system *sys, const dou
     stats->n_accepted = (int64_t)hc[2];
     stats->n_fallback = (int64_t)hc[3];
     float a = 0.f, b = 0.f, c = 0.f;
-    hipEventElapsedTime(&a, ev[0], ev[1]);
-    hipEventElapsedTime(&b, ev[1], ev[2]);
-    hipEventElapsedTime(&c, ev[2], ev[3]);
+    (void)hipEventElapsedTime(&a, ev[0], ev[1]);
+    (void)hipEventElapsedTime(&b, ev[1], ev[2]);
+    (void)hipEventElapsedTime(&c, ev[2], ev[3]);
     stats->ms_gate = a;
     stats->ms_infer = b;
     stats->ms_fallback = c;

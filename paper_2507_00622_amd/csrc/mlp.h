@@ -31,7 +31,10 @@ hipError_t mlp_softmax_ce(const float *Z3, const int8_t *labels, const int64_t *
                           int64_t n_valid, float inv, float *dZ3, uint16_t *dZ3b, float *loss_sum,
                           hipStream_t s);
 hipError_t mlp_apply_mask(float *p, const uint8_t *mask, int64_t n, hipStream_t s);
-hipError_t mlp_colsum(const float *dZ, int B, int ncol, int64_t ld, float *db, hipStream_t s);
+// column sums of a B x ncol matrix; part holds mlp_colsum_blocks(B) * ncol floats
+int mlp_colsum_blocks(int B);
+hipError_t mlp_colsum(const float *dZ, int B, int ncol, int64_t ld, float *db, float *part,
+                      hipStream_t s);
 hipError_t mlp_fill(float *p, int64_t n, float v, hipStream_t s);
 hipError_t gate_select(int64_t n, const int *status, const int8_t *label1, const float *pc,
                        const float *conf, float conf_min, int8_t *label, uint8_t *source,

@@ -133,24 +133,34 @@ __global__ void softmax_ce_kernel(const float *Z3, const int8_t *labels, const i
   }
 }
 
-// db[j] = sum_r dZ[r][j] (B rows, row stride ld): one block of 16 waves per
-// 64 columns, wave w summing rows w, w+16, ..., then the 16 partial sums
-// added in wave order (deterministic).
-__global__ void __launch_bounds__(1024) colsum_kernel(const float *dZ, int B, int ncol,
-                                                      int64_t ld, float *db) {
-  __shared__ float part[16][64];
+// db[j] = sum_r dZ[r][j] (B rows, row stride ld) in two deterministic
+// passes: block (cb, rb) of 4 waves sums rows rb*CS_ROWS .. +CS_ROWS of
+// columns cb*64 .. +64 into part[rb][j] (wave w takes rows w, w+4, ...,
+// then the 4 wave sums are added in order); a second kernel adds the
+// row-block partials in order.
+constexpr int CS_ROWS = 128;
+__global__ void __launch_bounds__(256) colsum_part_kernel(const float *dZ, int B, int ncol,
+                                                          int64_t ld, float *part) {
+  __shared__ float ws[4][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int j = blockIdx.x * 64 + lane;
+  const int r0 = blockIdx.y * CS_ROWS;
+  int r1 = r0 + CS_ROWS;
+  if (r1 > B) r1 = B;
   float acc = 0.f;
   if (j < ncol)
-    for (int r = w; r < B; r += 16) acc += dZ[(int64_t)r * ld + j];
-  part[w][lane] = acc;
+    for (int r = r0 + w; r < r1; r += 4) acc += dZ[(int64_t)r * ld + j];
+  ws[w][lane] = acc;
   __syncthreads();
-  if (w == 0 && j < ncol) {
-    float t = 0.f;
-    for (int q = 0; q < 16; ++q) t += part[q][lane];
-    db[j] = t;
-  }
+  if (w == 0 && j < ncol)
+    part[(int64_t)blockIdx.y * ncol + j] = ((ws[0][lane] + ws[1][lane]) + ws[2][lane]) + ws[3][lane];
+}
+__global__ void colsum_final_kernel(const float *part, int nrb, int ncol, float *db) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ncol) return;
+  float t = 0.f;
+  for (int k = 0; k < nrb; ++k) t += part[(int64_t)k * ncol + j];
+  db[j] = t;
 }
 
 __global__ void fill_f32_kernel(float *p, int64_t n, float v) {
@@ -405,8 +415,14 @@ hipError_t mlp_softmax_ce(const float *Z3, const int8_t *labels, const int64_t *
                      inv, dZ3, dZ3b, loss_sum);
   return hipGetLastError();
 }
-hipError_t mlp_colsum(const float *dZ, int B, int ncol, int64_t ld, float *db, hipStream_t s) {
-  hipLaunchKernelGGL(colsum_kernel, dim3(nb(ncol, 64)), dim3(1024), 0, s, dZ, B, ncol, ld, db);
+int mlp_colsum_blocks(int B) { return (B + CS_ROWS - 1) / CS_ROWS; }
+hipError_t mlp_colsum(const float *dZ, int B, int ncol, int64_t ld, float *db, float *part,
+                      hipStream_t s) {
+  const int nrb = mlp_colsum_blocks(B);
+  if (nrb == 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(colsum_part_kernel, dim3(nb(ncol, 64), nrb), dim3(256), 0, s, dZ, B, ncol,
+                     ld, part);
+  hipLaunchKernelGGL(colsum_final_kernel, dim3(nb(ncol)), dim3(256), 0, s, part, nrb, ncol, db);
   return hipGetLastError();
 }
 hipError_t mlp_fill(float *p, int64_t n, float v, hipStream_t s) {
