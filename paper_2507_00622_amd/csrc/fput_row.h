@@ -309,13 +309,14 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
     // dot products and updates take component c through the FMA's
     // row_newbcast operand from lane c % 16, so the pivot costs one LDS
     // read per lane.  w_k -= (w_j . w_k / |w_j|^2) w_j is the projection on
-    // the normalised pivot; each lane remembers 1/|w| of its own slots and
-    // normalises them after the last pivot.  Pivots come in groups of 16
-    // (group G = slot G / R of row G % R); the group is a compile-time
-    // index and the 16 pivots of a group are a runtime loop.
-    double invs[V];
+    // the normalised pivot.  The owner keeps |w_j|^2 of its own slot; the
+    // growth and the normalisation of every Lyapunov slot follow the last
+    // pivot.  Pivots come in groups of 16 (group G = slot G / R of row
+    // G % R); the group is a compile-time index and the 16 pivots of a
+    // group are a runtime loop.
+    double own2[V];  // |w|^2 of this lane's slot when it was the pivot
 #pragma unroll
-    for (int s = 0; s < V; ++s) invs[s] = 1.0;
+    for (int s = 0; s < V; ++s) own2[s] = 1.0;
     const int nls = (n_l + 16 * R - 1) / (16 * R);  // slots holding Lyapunov vectors
     static_for<0, V * R>([&](auto gc) {
       constexpr int G = decltype(gc)::value;
@@ -342,23 +343,13 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
           asm volatile("s_nop 1" : "+v"(pc[0]));
         double r2 = pc[0] * pc[0];
         if constexpr (CPL == 2) r2 = __builtin_fma(pc[1], pc[1], r2);
-        r2 = row_sum(r2);
-        const double inv = rsqrt_nr(r2);
-        const double i2 = inv * inv;
-        {
-          double g = gm[sj];
-          int e = ge[sj];
-          grow(g, e, r2);
-          gm[sj] = owner ? g : gm[sj];
-          ge[sj] = owner ? e : ge[sj];
-          invs[sj] = owner ? inv : invs[sj];
-        }
-        // Slot s of this row is after the pivot if its group s R + ro is
-        // later, or is the pivot's group and the lane is later.  Slots
+        // Slot s of this lane is after the pivot if its position is, and
+        // holds a Lyapunov vector if its position is below n_l.  Slots
         // before sj never are (no code for them), and slots from nls on
         // hold no Lyapunov vector: the projection is instantiated for each
         // possible nls and one is chosen by a uniform branch.  Slots that
-        // are not later take a zero coefficient.
+        // are not after the pivot take a zero coefficient.
+        const int pj = G * 16 + lj;
         auto project = [&](auto lc) {
           constexpr int L = decltype(lc)::value;
           constexpr int PS = 4;  // partial sums per dot product
@@ -372,13 +363,16 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
 #pragma unroll
             for (int s = sj; s < L; ++s) fmac_bcast_ordered<c % 16>(d[s][c % PS], pc[c / 16], w[s][c]);
           });
+          r2 = row_sum(r2);
+          own2[sj] = owner ? r2 : own2[sj];
+          const double inv = rsqrt_nr(r2);
+          const double ni2 = -(inv * inv);
           double nd[V];
 #pragma unroll
           for (int s = sj; s < L; ++s) {
-            const int gs = s * R + ro;
-            const bool later = (gs > G || (gs == G && lane > lj)) && (gs * 16 + lane < n_l);
+            const int pos = (s * R + ro) * 16 + lane;
             const double t = (d[s][0] + d[s][1]) + (d[s][2] + d[s][3]);
-            nd[s] = later ? -(t * i2) : 0.0;
+            nd[s] = (pos > pj && pos < n_l) ? t * ni2 : 0.0;
           }
           static_for<0, D>([&](auto cc) {
             constexpr int c = decltype(cc)::value;
@@ -395,8 +389,10 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
 #pragma unroll
     for (int s = 0; s < V; ++s) {
       if ((s * R + ro) * 16 + lane < n_l) {
+        const double inv = rsqrt_nr(own2[s]);
+        grow(gm[s], ge[s], own2[s]);
 #pragma unroll
-        for (int c = 0; c < D; ++c) w[s][c] *= invs[s];
+        for (int c = 0; c < D; ++c) w[s][c] *= inv;
       }
     }
     if (do_energy) {
