@@ -222,6 +222,183 @@ void ora_step(int kind, int N, const double *pr, double dt, double *x, double *w
 }
 
 /* ---------------------------------------------------------------------- */
+/* Integrator: the explicit Runge-Kutta method of order 8 of Dormand and    */
+/* Prince (DOP853), with a fixed step                                      */
+/* ---------------------------------------------------------------------- */
+
+/* The paper's solvers are built on DOP853 (Functionalities section).  Its
+ * coefficients are those published with the method (Prince and Dormand,
+ * J. Comput. Appl. Math. 7 (1981) 67; in the 12-stage form of Hairer, Norsett
+ * and Wanner, Solving Ordinary Differential Equations I, 2nd ed., Sect.
+ * II.10), written to 30 significant digits; the compiler stores the nearest
+ * binary64 values.  Only the eighth-order solution is used: no error
+ * estimate, no step-size control, no dense output.  Stage i (0-based) is
+ * evaluated at t + c_i dt; a[i][j] = 0 where not listed. */
+static const double DOP_C[12] = {
+    0.0,
+    0.526001519587677318785587544488e-01,
+    0.789002279381515978178381316732e-01,
+    0.118350341907227396726757197510,
+    0.281649658092772603273242802490,
+    0.333333333333333333333333333333,
+    0.25,
+    0.307692307692307692307692307692,
+    0.651282051282051282051282051282,
+    0.6,
+    0.857142857142857142857142857142,
+    1.0};
+static const double DOP_B[12] = {
+    5.42937341165687622380535766363e-2, 0.0, 0.0, 0.0, 0.0,
+    4.45031289275240888144113950566,
+    1.89151789931450038304281599044,
+    -5.8012039600105847814672114227,
+    3.1116436695781989440891606237e-1,
+    -1.52160949662516078556178806805e-1,
+    2.01365400804030348374776537501e-1,
+    4.47106157277725905176885569043e-2};
+static double dop_a(int i, int j) {
+  /* rows 2..12 of the published lower-triangular matrix, 1-based */
+  switch (i * 100 + j) {
+  case 201: return 5.26001519587677318785587544488e-2;
+  case 301: return 1.97250569845378994544595329183e-2;
+  case 302: return 5.91751709536136983633785987549e-2;
+  case 401: return 2.95875854768068491816892993775e-2;
+  case 403: return 8.87627564304205475450678981324e-2;
+  case 501: return 2.41365134159266685502369798665e-1;
+  case 503: return -8.84549479328286085344864962717e-1;
+  case 504: return 9.24834003261792003115737966543e-1;
+  case 601: return 3.7037037037037037037037037037e-2;
+  case 604: return 1.70828608729473871279604482173e-1;
+  case 605: return 1.25467687566822425016691814123e-1;
+  case 701: return 3.7109375e-2;
+  case 704: return 1.70252211019544039314978060272e-1;
+  case 705: return 6.02165389804559606850219397283e-2;
+  case 706: return -1.7578125e-2;
+  case 801: return 3.70920001185047927108779319836e-2;
+  case 804: return 1.70383925712239993810214054705e-1;
+  case 805: return 1.07262030446373284651809199168e-1;
+  case 806: return -1.53194377486244017527936158236e-2;
+  case 807: return 8.27378916381402288758473766002e-3;
+  case 901: return 6.24110958716075717114429577812e-1;
+  case 904: return -3.36089262944694129406857109825;
+  case 905: return -8.68219346841726006818189891453e-1;
+  case 906: return 2.75920996994467083049415600797e1;
+  case 907: return 2.01540675504778934086186788979e1;
+  case 908: return -4.34898841810699588477366255144e1;
+  case 1001: return 4.77662536438264365890433908527e-1;
+  case 1004: return -2.48811461997166764192642586468;
+  case 1005: return -5.90290826836842996371446475743e-1;
+  case 1006: return 2.12300514481811942347288949897e1;
+  case 1007: return 1.52792336328824235832596922938e1;
+  case 1008: return -3.32882109689848629194453265587e1;
+  case 1009: return -2.03312017085086261358222928593e-2;
+  case 1101: return -9.3714243008598732571704021658e-1;
+  case 1104: return 5.18637242884406370830023853209;
+  case 1105: return 1.09143734899672957818500254654;
+  case 1106: return -8.14978701074692612513997267357;
+  case 1107: return -1.85200656599969598641566180701e1;
+  case 1108: return 2.27394870993505042818970056734e1;
+  case 1109: return 2.49360555267965238987089396762;
+  case 1110: return -3.0467644718982195003823669022;
+  case 1201: return 2.27331014751653820792359768449;
+  case 1204: return -1.05344954667372501984066689879e1;
+  case 1205: return -2.00087205822486249909675718444;
+  case 1206: return -1.79589318631187989172765950534e1;
+  case 1207: return 2.79488845294199600508499808837e1;
+  case 1208: return -2.85899827713502369474065508674;
+  case 1209: return -8.87285693353062954433549289258;
+  case 1210: return 1.23605671757943030647266201528e1;
+  case 1211: return 6.43392746015763530355970484046e-1;
+  }
+  return 0.0;
+}
+
+void ora_dop853_tableau(double c[12], double a[144], double b[12]) {
+  for (int i = 0; i < 12; ++i) {
+    c[i] = DOP_C[i];
+    b[i] = DOP_B[i];
+    for (int j = 0; j < 12; ++j) a[i * 12 + j] = dop_a(i + 1, j + 1);
+  }
+}
+
+/* Right-hand side of the extended system y = (x, w_1..w_m, M):
+ *   dq/dt = p, dp/dt = -grad V(q)               (Hamilton's equations)
+ *   d(dq)/dt = dp, d(dp)/dt = -Hess V(q) dq    (variational equations)
+ *   dM/dt = sum over the 2N components of |dx_i/dt|^p  (LD M-function)
+ * M is present (the last component) when do_ld is set. */
+static void ext_rhs(int kind, int N, const double *pr, int m, int do_ld, double ldp,
+                    const double *y, double *f, double *g, double *h) {
+  const double *q = y, *p = y + N;
+  ora_grad(kind, N, pr, q, g);
+  ora_hess(kind, N, pr, q, h);
+  for (int i = 0; i < N; ++i) {
+    f[i] = p[i];
+    f[N + i] = -g[i];
+  }
+  for (int v = 0; v < m; ++v) {
+    const double *dq = y + 2 * N + (int64_t)v * 2 * N, *dp = dq + N;
+    double *fq = f + 2 * N + (int64_t)v * 2 * N, *fp = fq + N;
+    for (int i = 0; i < N; ++i) {
+      double s = 0.0;
+      for (int j = 0; j < N; ++j) s += h[i * N + j] * dq[j];
+      fq[i] = dp[i];
+      fp[i] = -s;
+    }
+  }
+  if (do_ld) {
+    double s = 0.0;
+    for (int i = 0; i < 2 * N; ++i) {
+      double a = fabs(f[i]);
+      s += (ldp == 0.5) ? sqrt(a) : pow(a, ldp);
+    }
+    f[2 * N + (int64_t)m * 2 * N] = s;
+  }
+}
+
+/* One step of size dt: k_i = f(y + dt sum_{j<i} a_ij k_j), i = 1..12, then
+ * y <- y + dt sum_i b_i k_i.  ws holds 13 ny + N + N^2 doubles with
+ * ny = 2N (1 + m) + (do_ld ? 1 : 0). */
+static void dop853_step_ws(int kind, int N, const double *pr, double dt, double *y, int m,
+                           int do_ld, double ldp, double *ws) {
+  const int64_t ny = (int64_t)2 * N * (1 + m) + (do_ld ? 1 : 0);
+  double *k = ws, *Y = ws + 12 * ny, *g = Y + ny, *h = g + N;
+  for (int i = 0; i < 12; ++i) {
+    for (int64_t c = 0; c < ny; ++c) {
+      double s = 0.0;
+      for (int j = 0; j < i; ++j) s += dop_a(i + 1, j + 1) * k[j * ny + c];
+      Y[c] = y[c] + dt * s;
+    }
+    ext_rhs(kind, N, pr, m, do_ld, ldp, Y, k + i * ny, g, h);
+  }
+  for (int64_t c = 0; c < ny; ++c) {
+    double s = 0.0;
+    for (int i = 0; i < 12; ++i) s += DOP_B[i] * k[i * ny + c];
+    y[c] = y[c] + dt * s;
+  }
+}
+
+static double *dop853_workspace(int N, int m) {
+  const int64_t ny = (int64_t)2 * N * (1 + m) + 1;
+  return (double *)malloc(sizeof(double) * (size_t)(13 * ny + N + (int64_t)N * N));
+}
+
+void ora_dop853_step(int kind, int N, const double *pr, double dt, double *x, double *w,
+                     int m, int do_ld, double ldp, double *ld) {
+  const int64_t ny = (int64_t)2 * N * (1 + m) + (do_ld ? 1 : 0);
+  double *ws = dop853_workspace(N, m);
+  double *y = (double *)malloc(sizeof(double) * (size_t)ny);
+  for (int i = 0; i < 2 * N; ++i) y[i] = x[i];
+  for (int64_t c = 0; c < (int64_t)m * 2 * N; ++c) y[2 * N + c] = w[c];
+  if (do_ld) y[ny - 1] = *ld;
+  dop853_step_ws(kind, N, pr, dt, y, m, do_ld, ldp, ws);
+  for (int i = 0; i < 2 * N; ++i) x[i] = y[i];
+  for (int64_t c = 0; c < (int64_t)m * 2 * N; ++c) w[c] = y[2 * N + c];
+  if (do_ld) *ld = y[ny - 1];
+  free(y);
+  free(ws);
+}
+
+/* ---------------------------------------------------------------------- */
 /* Linear algebra                                                          */
 /* ---------------------------------------------------------------------- */
 
@@ -424,25 +601,49 @@ static int checkpoint(int kind, int N, const double *pr, ora_view v, int m_s, in
   return ORA_ST_OK;
 }
 
-int ora_advance(int kind, int N, const double *pr, double *state, int64_t n, int m_s,
-                int n_l, uint32_t ind, double dt, int64_t s_begin, int64_t s_end,
-                int64_t n_total, int K, double ldp, double thr, int early_exit,
-                double escape_r2) {
+int ora_advance_with(int kind, int N, const double *pr, double *state, int64_t n,
+                     int m_s, int n_l, uint32_t ind, double dt, int64_t s_begin,
+                     int64_t s_end, int64_t n_total, int K, double ldp, double thr,
+                     int early_exit, double escape_r2, int integrator) {
   int64_t L = ora_state_len(N, m_s, n_l);
   if (K < 1 || s_begin < 0 || s_end > n_total || s_begin > s_end) return 1;
-  for (int64_t o = 0; o < n; ++o) {
+  if (integrator != ORA_INT_YOSHIDA4 && integrator != ORA_INT_DOP853) return 3;
+  const int m = m_s + n_l, do_ld = (ind & ORA_IND_LD) != 0;
+  double *ws = NULL, *y = NULL;
+  const int64_t ny = (int64_t)2 * N * (1 + m) + (do_ld ? 1 : 0);
+  if (integrator == ORA_INT_DOP853) {
+    ws = dop853_workspace(N, m);
+    y = (double *)malloc(sizeof(double) * (size_t)ny);
+  }
+  int rc = 0;
+  for (int64_t o = 0; o < n && !rc; ++o) {
     double *st = state + o * L;
     ora_view v = view(st, N, m_s, n_l);
     if ((int)v.sc[ST_STATUS] != ORA_ST_OK) continue;
-    if ((int64_t)v.sc[ST_S_DONE] != s_begin) return 2;
+    if ((int64_t)v.sc[ST_S_DONE] != s_begin) {
+      rc = 2;
+      break;
+    }
     for (int64_t s = s_begin + 1; s <= s_end; ++s) {
-      /* both vector sets are evolved by the same tangent map */
-      ora_step(kind, N, pr, dt, v.x, v.ws, m_s + n_l);
-      if (ind & ORA_IND_LD) {
-        /* trapezoid rule over the step's endpoints */
-        double g = ld_integrand(kind, N, pr, v.x, ldp);
-        v.sc[ST_LD] += dt / 2.0 * (v.sc[ST_GPREV] + g);
-        v.sc[ST_GPREV] = g;
+      if (integrator == ORA_INT_YOSHIDA4) {
+        /* both vector sets are evolved by the same tangent map */
+        ora_step(kind, N, pr, dt, v.x, v.ws, m);
+        if (do_ld) {
+          /* trapezoid rule over the step's endpoints */
+          double g = ld_integrand(kind, N, pr, v.x, ldp);
+          v.sc[ST_LD] += dt / 2.0 * (v.sc[ST_GPREV] + g);
+          v.sc[ST_GPREV] = g;
+        }
+      } else {
+        /* the state, both vector sets (contiguous after x) and the LD as
+         * one extended system */
+        for (int i = 0; i < 2 * N; ++i) y[i] = v.x[i];
+        for (int64_t c = 0; c < (int64_t)m * 2 * N; ++c) y[2 * N + c] = v.ws[c];
+        if (do_ld) y[ny - 1] = v.sc[ST_LD];
+        dop853_step_ws(kind, N, pr, dt, y, m, do_ld, ldp, ws);
+        for (int i = 0; i < 2 * N; ++i) v.x[i] = y[i];
+        for (int64_t c = 0; c < (int64_t)m * 2 * N; ++c) v.ws[c] = y[2 * N + c];
+        if (do_ld) v.sc[ST_LD] = y[ny - 1];
       }
       v.sc[ST_S_DONE] = (double)s;
       if (s % K == 0 || s == n_total) {
@@ -457,7 +658,17 @@ int ora_advance(int kind, int N, const double *pr, double *state, int64_t n, int
       }
     }
   }
-  return 0;
+  free(ws);
+  free(y);
+  return rc;
+}
+
+int ora_advance(int kind, int N, const double *pr, double *state, int64_t n, int m_s,
+                int n_l, uint32_t ind, double dt, int64_t s_begin, int64_t s_end,
+                int64_t n_total, int K, double ldp, double thr, int early_exit,
+                double escape_r2) {
+  return ora_advance_with(kind, N, pr, state, n, m_s, n_l, ind, dt, s_begin, s_end,
+                          n_total, K, ldp, thr, early_exit, escape_r2, ORA_INT_YOSHIDA4);
 }
 
 int ora_finalize(int N, const double *state, int64_t n, int m_s, int n_l, uint32_t ind,

@@ -24,7 +24,11 @@
  *     the singular values of the unit deviation vectors, SALI, and the
  *     Lagrangian-descriptor M-function (Functionalities section).
  *   - The integrator is the fourth-order symplectic triple-jump composition
- *     of Yoshida (Phys. Lett. A 150 (1990) 262) of kick-drift-kick leapfrog.
+ *     of Yoshida (Phys. Lett. A 150 (1990) 262) of kick-drift-kick leapfrog,
+ *     or, on request, the eighth-order explicit Runge-Kutta method of Dormand
+ *     and Prince (DOP853, the solver the paper's Functionalities section
+ *     builds on) with a fixed step, applied to the state, the variational
+ *     equations and the LD integrand as one system.
  *
  * All functions are per initial condition, one after another, with no
  * blocking, fusion or reordering beyond the definitions.
@@ -50,6 +54,10 @@ extern "C" {
 #define ORA_IND_LD 8
 #define ORA_IND_ENERGY 16
 
+/* Integrators. */
+#define ORA_INT_YOSHIDA4 0
+#define ORA_INT_DOP853 1
+
 /* Orbit status codes. */
 #define ORA_ST_OK 0
 #define ORA_ST_MASKED 1
@@ -72,6 +80,14 @@ void ora_yoshida_coefficients(double c[3], double d[4]);
 void ora_step(int kind, int ndof, const double *params, double dt, double *x,
               double *w, int m);
 
+/* The DOP853 coefficients: nodes c[12], row-major lower-triangular a[12][12]
+ * (zeros above the diagonal and where the method has none), weights b[12]. */
+void ora_dop853_tableau(double c[12], double a[144], double b[12]);
+/* One fixed DOP853 step of size dt of the state x[2N], m tangent vectors
+ * w[m][2N] and, if do_ld, the LD M-function *ld (integrand sum |dx_i/dt|^p). */
+void ora_dop853_step(int kind, int ndof, const double *params, double dt, double *x,
+                     double *w, int m, int do_ld, double ld_p, double *ld);
+
 /* Integration driver with explicit, resumable per-orbit state.
  *
  * state is [n][ora_state_len(ndof, m_s, n_l)] doubles.  ora_init fills it at
@@ -92,6 +108,14 @@ int ora_advance(int kind, int ndof, const double *params, double *state, int64_t
                 int m_s, int n_l, uint32_t indicators, double dt, int64_t s_begin,
                 int64_t s_end, int64_t n_total, int K, double ld_p,
                 double sali_threshold, int early_exit, double escape_r2);
+/* The same with the integrator chosen (ORA_INT_*).  With DOP853 the LD is a
+ * component of the integrated system; with Yoshida-4 it is the trapezoid rule
+ * over step endpoints. */
+int ora_advance_with(int kind, int ndof, const double *params, double *state, int64_t n,
+                     int m_s, int n_l, uint32_t indicators, double dt, int64_t s_begin,
+                     int64_t s_end, int64_t n_total, int K, double ld_p,
+                     double sali_threshold, int early_exit, double escape_r2,
+                     int integrator);
 /* Outputs (any may be NULL): x_final[n][2N], t_end[n], status[n], label[n],
  * sali_final[n], sali_min[n], t_chaos[n], gali[n][kmax-1], lyap[n][n_l],
  * ld[n], energy_err[n], ln_growth[n][m_s]. */

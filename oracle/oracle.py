@@ -4,7 +4,8 @@ Only the tests, the smoke check and the benchmark's CPU-baseline leg may
 import this module.  It loads oracle/libchx_oracle.so (built by
 oracle/build.py with gcc, no FMA contraction) and exposes the plain FP64
 reference: the systems of the paper's Examples section, the Yoshida-4 step
-with its tangent map, and the per-orbit chaos-indicator driver (SALI, GALI_k,
+with its tangent map, the fixed-step DOP853 step of the state, the
+variational equations and the LD integrand, and the per-orbit chaos-indicator driver (SALI, GALI_k,
 Lyapunov spectrum by modified Gram-Schmidt QR, Lagrangian-descriptor
 M-function, energy error) with resumable state.
 """
@@ -29,6 +30,9 @@ IND_LD = 8
 IND_ENERGY = 16
 
 ST_OK, ST_MASKED, ST_ESCAPED, ST_NONFINITE, ST_EXITED = 0, 1, 2, 3, 4
+
+INT_YOSHIDA4 = 0
+INT_DOP853 = 1
 
 _lib = None
 
@@ -58,6 +62,10 @@ def lib():
         L.ora_advance.restype = i
         L.ora_advance.argtypes = [i, i, P, P, i64, i, i, u32, d, i64, i64, i64, i, d, d,
                                   i, d]
+        L.ora_advance_with.restype = i
+        L.ora_advance_with.argtypes = L.ora_advance.argtypes + [i]
+        L.ora_dop853_tableau.argtypes = [P, P, P]
+        L.ora_dop853_step.argtypes = [i, i, P, d, P, P, i, i, d, P]
         L.ora_finalize.restype = i
         L.ora_finalize.argtypes = [i, P, i64, i, i, u32, i, d] + [P] * 12
         L.ora_gali.argtypes = [i, i, P, i, P]
@@ -149,6 +157,29 @@ def step(sys, dt, x, w=None, nsteps=1):
     return (x, w) if m else x
 
 
+def dop853_tableau():
+    """Nodes c[12], matrix a[12][12] and weights b[12] of DOP853."""
+    c, a, b = np.zeros(12), np.zeros((12, 12)), np.zeros(12)
+    lib().ora_dop853_tableau(_p(c), _p(a), _p(b))
+    return c, a, b
+
+
+def dop853_step(sys, dt, x, w=None, nsteps=1, ld=None, ld_p=0.5):
+    """Apply nsteps fixed DOP853 steps to a copy of x[2N] (and w[m][2N]; and
+    the LD M-function when ld is a number).  Returns x, (x, w), (x, ld) or
+    (x, w, ld) accordingly."""
+    x = np.array(x, dtype=np.float64)
+    m = 0 if w is None else len(w)
+    w = np.zeros((0, 2 * sys.ndof)) if w is None else np.array(w, dtype=np.float64)
+    m_ld = np.array([0.0 if ld is None else float(ld)])
+    pr = sys.parr()
+    for _ in range(nsteps):
+        lib().ora_dop853_step(sys.kind, sys.ndof, _p(pr), dt, _p(x), _p(w), m,
+                              0 if ld is None else 1, ld_p, _p(m_ld))
+    out = (x,) + ((w,) if m else ()) + ((m_ld[0],) if ld is not None else ())
+    return out[0] if len(out) == 1 else out
+
+
 def mgs(w):
     w = np.array(w, dtype=np.float64)
     m, dim = w.shape
@@ -190,6 +221,7 @@ class Run:
     early_exit: bool = False
     escape_r2: float = 0.0
     m_s: int = field(default=-1)
+    integrator: int = INT_YOSHIDA4
 
     def __post_init__(self):
         if self.m_s < 0:
@@ -234,10 +266,11 @@ class State:
         def work(lo, hi):
             sub = self.buf[lo:hi]
             assert sub.flags.c_contiguous
-            rc = lib().ora_advance(sys.kind, sys.ndof, _p(pr), _p(sub), hi - lo, run.m_s,
-                                   run.n_lyap, run.indicators, run.dt, self.s_done, s_end,
-                                   self.n_total, run.K, run.ld_p, run.sali_threshold,
-                                   int(run.early_exit), run.escape_r2)
+            rc = lib().ora_advance_with(sys.kind, sys.ndof, _p(pr), _p(sub), hi - lo,
+                                        run.m_s, run.n_lyap, run.indicators, run.dt,
+                                        self.s_done, s_end, self.n_total, run.K, run.ld_p,
+                                        run.sali_threshold, int(run.early_exit),
+                                        run.escape_r2, run.integrator)
             if rc:
                 raise RuntimeError("ora_advance failed (%d)" % rc)
 

@@ -1,0 +1,222 @@
+"""Pins of the oracle's fixed-step DOP853 integrator (the eighth-order
+Runge-Kutta method of Dormand and Prince that the paper's solvers build on,
+Functionalities section) applied to the state, the variational equations and
+the LD integrand as one system.
+
+Checked against: Butcher's order conditions for every rooted tree up to
+order 8 (a mistyped coefficient fails one of them), the harmonic
+oscillator's closed form (eighth-order convergence), an independent solver
+(SciPy's adaptive DOP853 at tight tolerance), central finite differences of
+the step map (the tangent vectors follow its exact Jacobian), the closed-form
+LD M-function of the oscillator over one period, and the trace of the
+linearised flow (the sum of the Lyapunov exponents of a Hamiltonian flow is
+zero; the method is not symplectic, so only to its truncation error).
+"""
+from functools import lru_cache
+import math
+
+import mpmath as mp
+import numpy as np
+import pytest
+from scipy.integrate import solve_ivp
+
+
+# --- the tableau -------------------------------------------------------------
+
+@lru_cache(None)
+def rooted_trees(n):
+    """Rooted trees with n nodes, each a sorted tuple of its subtrees."""
+    if n == 1:
+        return ((),)
+    out = set()
+
+    def forests(rem, acc):
+        if rem == 0:
+            out.add(tuple(sorted(acc)))
+            return
+        for k in range(1, rem + 1):
+            for t in rooted_trees(k):
+                forests(rem - k, acc + [t])
+
+    forests(n - 1, [])
+    return tuple(sorted(out))
+
+
+def order(t):
+    return 1 + sum(order(u) for u in t)
+
+
+def density(t):
+    g = order(t)
+    for u in t:
+        g *= density(u)
+    return g
+
+
+def order_residuals(c, a, b, pmax=8):
+    """sum_i b_i Phi_i(t) - 1/gamma(t) for every rooted tree t up to pmax
+    nodes, in 60-digit arithmetic on the given binary64 coefficients."""
+    mp.mp.dps = 60
+    s = len(b)
+    A = [[mp.mpf(float(a[i][j])) for j in range(s)] for i in range(s)]
+    B = [mp.mpf(float(v)) for v in b]
+    memo = {}
+
+    def phi(t):
+        if t in memo:
+            return memo[t]
+        v = [mp.mpf(1)] * s
+        for u in t:
+            pu = phi(u)
+            for i in range(s):
+                v[i] *= mp.fsum(A[i][j] * pu[j] for j in range(i))
+        memo[t] = v
+        return v
+
+    res = []
+    for n in range(1, pmax + 1):
+        for t in rooted_trees(n):
+            lhs = mp.fsum(B[i] * phi(t)[i] for i in range(s))
+            res.append((n, float(lhs - mp.mpf(1) / density(t))))
+    return res
+
+
+def test_tree_count():
+    # 1, 1, 2, 4, 9, 20, 48, 115 rooted trees of orders 1..8 (OEIS A000081)
+    assert [len(rooted_trees(n)) for n in range(1, 9)] == [1, 1, 2, 4, 9, 20, 48, 115]
+
+
+def test_tableau_is_explicit_and_consistent(O):
+    c, a, b = O.dop853_tableau()
+    assert np.all(np.triu(a) == 0.0)  # explicit: a_ij = 0 for j >= i
+    assert np.max(np.abs(a.sum(axis=1) - c)) < 2e-15  # c_i = sum_j a_ij
+    assert c[0] == 0.0 and c[-1] == 1.0
+    # the nodes that are rational in the published method
+    assert c[5] == pytest.approx(1 / 3, abs=1e-16) and c[6] == 0.25
+    assert c[7] == pytest.approx(4 / 13, abs=1e-16) and c[8] == pytest.approx(127 / 195, abs=1e-16)
+    assert c[9] == pytest.approx(0.6, abs=1e-16) and c[10] == pytest.approx(6 / 7, abs=1e-16)
+    # c_4, c_5 = (6 -/+ sqrt 6)/30 and c_3 = 2 c_4 / 3, c_2 = 2 c_3 / 3
+    assert c[3] == pytest.approx((6 - math.sqrt(6)) / 30, abs=1e-16)
+    assert c[4] == pytest.approx((6 + math.sqrt(6)) / 30, abs=1e-16)
+    assert c[2] == pytest.approx(2 * c[3] / 3, abs=1e-16)
+    assert c[1] == pytest.approx(2 * c[2] / 3, abs=1e-16)
+    # the eighth-order solution does not use stages 2..5
+    assert list(b[1:5]) == [0.0, 0.0, 0.0, 0.0]
+
+
+def test_all_order_conditions_to_order_8(O):
+    c, a, b = O.dop853_tableau()
+    res = order_residuals(c, a, b)
+    assert len(res) == 200
+    worst = max(abs(r) for _, r in res)
+    assert worst < 1e-13, worst
+
+
+def test_order_conditions_catch_a_mistyped_coefficient(O):
+    # the check above is sensitive: a change in the 11th digit of one
+    # coefficient breaks conditions of order <= 8
+    c, a, b = O.dop853_tableau()
+    a = a.copy()
+    a[8][5] *= 1 + 1e-10
+    res = order_residuals(c, a, b)
+    assert max(abs(r) for _, r in res) > 1e-10
+
+
+# --- the integrator ----------------------------------------------------------
+
+def test_eighth_order_convergence_harmonic(O):
+    # x'' = -w^2 x: closed form after one period is the initial point
+    w = 1.3
+    s = O.harmonic([w])
+    x0 = np.array([0.7, 0.4])
+    T = 2 * math.pi / w
+    errs = []
+    for n in (12, 24, 48):
+        x = O.dop853_step(s, T / n, x0, nsteps=n)
+        errs.append(np.max(np.abs(x - x0)))
+    slopes = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(7.8 < p < 8.2 for p in slopes), (errs, slopes)
+
+
+def hh_rhs(t, y):
+    x, yy, px, py = y
+    return [px, py, -x - 2 * x * yy, -yy - x * x + yy * yy]
+
+
+def test_agrees_with_scipy_dop853(O):
+    s = O.henon_heiles()
+    x0 = np.array([0.0, 0.1, 0.45, 0.05])
+    dt, n = 0.01, 5000
+    x = O.dop853_step(s, dt, x0, nsteps=n)
+    ref = solve_ivp(hh_rhs, (0, dt * n), x0, method="DOP853", rtol=1e-13, atol=1e-13)
+    assert np.max(np.abs(x - ref.y[:, -1])) < 1e-10
+
+
+def test_tangent_vectors_follow_the_step_jacobian(O):
+    s = O.henon_heiles()
+    x0 = np.array([0.05, -0.2, 0.4, 0.1])
+    dt, n, h = 0.05, 8, 1e-6
+    _, W = O.dop853_step(s, dt, x0, np.eye(4), nsteps=n)
+    J = np.zeros((4, 4))
+    for k in range(4):
+        e = np.zeros(4)
+        e[k] = h
+        J[:, k] = (O.dop853_step(s, dt, x0 + e, nsteps=n) - O.dop853_step(s, dt, x0 - e, nsteps=n)) / (2 * h)
+    # row v of W is the image of the unit vector e_v
+    assert np.max(np.abs(W.T - J)) < 1e-8
+    # for a linear system the tangent map is the step map itself
+    hs = O.harmonic([0.9, 1.4])
+    y0 = np.array([0.3, -0.2, 0.1, 0.5])
+    _, W = O.dop853_step(hs, 0.1, y0, np.eye(4), nsteps=5)
+    cols = np.array([O.dop853_step(hs, 0.1, e, nsteps=5) for e in np.eye(4)])
+    assert np.max(np.abs(W - cols)) < 1e-15
+
+
+B_QUARTER = 1.198140234735592  # integral of sqrt(sin t) over [0, pi/2]
+
+
+def test_ld_component_closed_form_oscillator(O):
+    # q = A cos t, p = -A sin t: |dq/dt|^(1/2) + |dp/dt|^(1/2) over one period
+    # is 8 sqrt(A) B.  The integrand has square-root cusps at the zero
+    # crossings, so the error falls like dt^1.5, not dt^8.
+    s = O.harmonic([1.0])
+    A = 0.64
+    exact = 8 * math.sqrt(A) * B_QUARTER
+    errs = []
+    for n in (500, 2000):
+        _, M = O.dop853_step(s, 2 * math.pi / n, [A, 0.0], nsteps=n, ld=0.0)
+        errs.append(abs(M - exact))
+    assert errs[0] < 2e-3 * exact
+    assert errs[1] < errs[0] / 5
+
+
+def test_driver_matches_the_step_and_resumes_bitwise(O):
+    s = O.henon_heiles()
+    x0 = np.array([[0.0, 0.1, 0.45, 0.05], [0.0, -0.3, 0.2, 0.1]])
+    w0 = np.array([[[1.0, 0.2, -0.1, 0.3], [0.1, 1.0, 0.2, -0.4]]] * 2)
+    run = O.Run(dt=0.01, T=3.0, indicators=O.IND_SALI | O.IND_LD | O.IND_LYAP | O.IND_ENERGY,
+                K=10, n_lyap=4, integrator=O.INT_DOP853)
+    full = O.integrate(s, x0, run, w0=w0)
+    # state and LD do not depend on the checkpoints: the same as plain steps
+    for i in range(2):
+        x, M = O.dop853_step(s, 0.01, x0[i], nsteps=300, ld=0.0)
+        assert np.array_equal(full["x_final"][i], x)
+        assert full["ld"][i] == M
+    st = O.State(s, run, x0, w0=w0)
+    st.advance(120)
+    st.advance(300)
+    part = st.finalize()
+    for k in ("x_final", "sali_min", "lyap", "ld", "energy_err"):
+        assert np.array_equal(full[k], part[k]), k
+
+
+def test_lyapunov_sum_and_energy(O):
+    s = O.henon_heiles()
+    x0 = np.array([[0.0, -0.25, 0.4330127018922193, 0.0]])
+    run = O.Run(dt=0.01, T=100.0, indicators=O.IND_LYAP | O.IND_ENERGY, K=10, n_lyap=4,
+                integrator=O.INT_DOP853)
+    o = O.integrate(s, x0, run)
+    # the flow preserves volume, so the exponents sum to zero up to the
+    # method's local truncation error
+    assert abs(o["lyap"][0].sum()) < 1e-10
+    assert o["energy_err"][0] < 1e-12
