@@ -84,6 +84,44 @@ def flops_per_step(N, m_s, n_l, ld, energy, sali, K, system="hh"):
     per = state + 3 * hess_scaled + M * vec
     if ld:
         per += (2 * N - 1) + 1 + 2  # sum of 2N roots, g_prev + g, FMA into LD
+    return per + checkpoint_flops_hh(N, m_s, n_l, energy, sali) / K
+
+
+# Non-zero pattern of the DOP853 tableau: entries a_ij (j < i) per stage
+# i = 1..12 and the stages with a non-zero weight b_i in the eighth-order
+# solution (stages 2..5 have none).
+DOP853_ROW_NNZ = (0, 1, 2, 2, 3, 3, 4, 5, 6, 7, 8, 9)
+DOP853_B_NNZ = 8
+
+
+def flops_per_step_dop853(N, m_s, n_l, ld, energy, sali, K, system="hh"):
+    """Algorithmic FP64 flops of one orbit-step of the fixed-step DOP853
+    lane kernel for Henon-Heiles (same conventions as flops_per_step): per
+    stage the stage input (one FMA per non-zero a_ij and component, plus the
+    add to the step's start value), one force (state) or step-scaled Hessian
+    and its mat-vec (vectors), the h-scaling of the stage derivative; the
+    final combination (one FMA per non-zero b_i and component, one add);
+    the LD integrand at every stage with a weight; checkpoints as for
+    Yoshida-4, divided by K."""
+    assert system == "hh" and N == 2
+    M = m_s + n_l
+    D = 2 * N
+    force = 2 + 4
+    hess_scaled = 2 + 1 + 2
+    sums = 2 * D * sum(DOP853_ROW_NNZ) + D * (len(DOP853_ROW_NNZ) - 1)
+    final = 2 * D * DOP853_B_NNZ + D
+    state = sums + 12 * force + 12 * D + final
+    vec = sums + 12 * (hess_scaled + 2 * N * N + N) + final
+    per = state + M * vec
+    if ld:
+        per += DOP853_B_NNZ * ((2 * N - 1) + 2) + 2
+    return per + checkpoint_flops_hh(N, m_s, n_l, energy, sali) / K
+
+
+def checkpoint_flops_hh(N, m_s, n_l, energy, sali):
+    """Flops of one Henon-Heiles checkpoint: renormalisation of the
+    SALI/GALI set, SALI, modified Gram-Schmidt of the Lyapunov set, energy."""
+    D = 2 * N
     ck = 0
     norm = 2 * D - 1 + D + 1  # |w|^2, rescale, growth product
     ck += m_s * norm
@@ -93,7 +131,7 @@ def flops_per_step(N, m_s, n_l, ld, energy, sali, K, system="hh"):
         ck += j * ((2 * D - 1) + 2 * D) + norm  # projections + normalisation
     if energy:
         ck += 14  # H (kinetic 2 FMA, potential 5 ops) and |H - H0|
-    return per + ck / K
+    return ck
 
 
 def flops_per_step_fput(N, m_s, n_l, ld, energy, sali, K):
@@ -253,6 +291,91 @@ def bench_fput(args, P, chx, torch, dev):
                  "unit": "TFLOP/s", "frac": r["achieved"] / PEAK_FP64, "traffic": None,
                  "kernel": "chx::fput_row_kernel<16, 2, 2>", "flops_per_orbit_step": r["fps"],
                  "launch_ms": r["ms"], "launches_timed": r["launches"]}, cpu)
+
+
+def bench_dop853(args, P, chx, torch, dev):
+    """The headline Henon-Heiles grids (1024^2 section points at E = 0.125
+    and E = 1/6, SALI + GALI_2 + 4 Lyapunov vectors + LD + energy, dt = 0.01)
+    integrated with the fixed-step DOP853 kernels; T = 200 by default."""
+    import numpy as np
+
+    import seeded_inputs as S
+    energies = (0.125, 1.0 / 6.0)
+    n_side = args.grid
+    dt, T, K = 0.01, args.T or 200.0, 10
+    ind = chx.IND_SALI | chx.IND_GALI | chx.IND_LYAP | chx.IND_LD | chx.IND_ENERGY
+    opts = dict(dt=dt, T=T, indicators=ind, gali_kmax=2, n_lyap=4, renorm_every=K,
+                seed=1002, escape_r2=4.0, block_size=args.block, integrator="dop853")
+    n_steps = int(round(T / dt))
+    spl = min(args.steps_per_launch or 5000, n_steps)
+    stream = torch.cuda.current_stream()
+    xs, ms = [], []
+    for E in energies:
+        x, m = P.grid_hh_section(E, n_side, n_side, device=dev)
+        xs.append(x)
+        ms.append(m)
+    x0, mask = torch.cat(xs), torch.cat(ms)
+    log = []
+    n_active = 0
+
+    def one_pass(record):
+        nonlocal n_active
+        progress(f"dop853: {n_side}^2 x 2 grids, T={T:g}")
+        e = P.Ensemble(P.henon_heiles(), x0, mask=mask, steps_per_launch=spl,
+                       outputs=("status", "label", "lyap"), **opts)
+        advance_timed(e, n_steps, spl, stream, torch, log if record else None)
+        out = e.results()
+        n_active = e.info()[2]
+        e.close()
+        return out
+
+    for _ in range(args.warmup):
+        one_pass(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = one_pass(True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = n_active * n_steps * args.steps / elapsed
+    fps = flops_per_step_dop853(2, 2, 4, True, True, True, K)
+    full = [a.elapsed_time(b) for a, b, k in log if k == spl]
+    ms_avg = float(np.mean(full))
+    achieved = fps * n_active * spl / (ms_avg * 1e-3)
+    lab = out["label"].cpu().numpy()
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        threads = max(1, min(16, len(os.sched_getaffinity(0))))
+        m, cT = 2048, 150.0
+        tot, el = 0, 0.0
+        for E in energies:
+            xg, mg = O.hh_grid(E, n_side, n_side)
+            act = np.flatnonzero(mg)
+            idx = act[np.linspace(0, len(act) - 1, m // 2).astype(int)]
+            w0 = np.concatenate([S.deviation_vectors(1002, 1, 2, 4, first_ic=int(i))
+                                 for i in idx])
+            run = O.Run(dt=dt, T=cT, indicators=ind, gali_kmax=2, n_lyap=4, K=K,
+                        escape_r2=4.0, integrator=O.INT_DOP853)
+            t1 = time.perf_counter()
+            O.integrate(O.henon_heiles(), xg[idx], run, w0=w0, threads=threads)
+            el += time.perf_counter() - t1
+            tot += len(idx) * int(round(cT / dt))
+        cpu = {"value": tot / el, "unit": "orbit-steps/s", "cores": threads, "kind": "oracle",
+               "sample": f"{m} strided grid orbits (both energies), T={cT:g} "
+                         f"({tot:.3g} orbit-steps, {el:.1f} s)"}
+    return emit(args, "FP64 trajectory-steps/s (with tangents)", value, "orbit-steps/s", elapsed,
+                "f64", {
+                    "workload": f"henon-heiles {n_side}x{n_side} section grids at E=0.125 and "
+                                f"E=1/6, fixed-step DOP853, dt={dt}, T={T:g}, SALI+GALI_2+4 "
+                                "Lyapunov (MGS/10)+LD(p=0.5, integrated as a component)+energy",
+                    "orbits": int(n_active), "steps_per_orbit": n_steps,
+                    "deviation_vectors": 6, "steps_per_launch": spl,
+                    "chaotic_fraction": float(np.mean(lab[lab >= 0] == 1))},
+                {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
+                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
+                 "kernel": "chx::lane_rk_kernel<SysHH, 6, false>", "flops_per_orbit_step": fps,
+                 "launch_ms": ms_avg, "launches_timed": len(full)}, cpu)
 
 
 def bench_batched(args, P, chx, torch, dev):
@@ -476,15 +599,17 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=("hh", "fput", "batched", "gate", "sweep"),
+    ap.add_argument("--workload", choices=("hh", "fput", "batched", "gate", "sweep", "dop853"),
                     default="hh",
                     help="hh: the headline Henon-Heiles grids (default); fput: FPU-beta "
                          "chains with 3N deviation vectors; batched: the persistent mixed "
                          "form with early exit; gate: the learned gate against the plain "
-                         "form; sweep: time per orbit against the ensemble size")
+                         "form; sweep: time per orbit against the ensemble size; dop853: "
+                         "the headline grids with the fixed-step DOP853 integrator")
     ap.add_argument("--grid", type=int, default=1024, help="grid side per energy")
     ap.add_argument("--T", type=float, default=None,
-                    help="final time (default: 1e4 for hh, gate and batched, 2e3 for fput)")
+                    help="final time (default: 1e4 for hh, gate and batched, 2e3 for fput, "
+                         "200 for dop853)")
     ap.add_argument("--steps-per-launch", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -524,7 +649,7 @@ def main():
         return
     if args.workload != "hh":
         fn = {"fput": bench_fput, "batched": bench_batched, "gate": bench_gate,
-              "sweep": bench_sweep}[args.workload]
+              "sweep": bench_sweep, "dop853": bench_dop853}[args.workload]
         print(json.dumps(fn(args, P, chx, torch, dev)), flush=True)
         return
     if args.T is None:

@@ -87,6 +87,18 @@ enum {
 /* Option flags. */
 enum { CHX_PTR_DEVICE = 1 };
 
+/* Integrators (chx_options.integrator). */
+enum {
+  CHX_INT_YOSHIDA4 = 0, /* fourth-order symplectic triple jump of kick-drift-kick
+                           leapfrog (Yoshida 1990); the tangent map is its exact
+                           Jacobian; LD by the trapezoid rule over step ends */
+  CHX_INT_DOP853 = 1    /* the eighth-order explicit Runge-Kutta method of
+                           Dormand and Prince that the paper's solvers build on
+                           (Functionalities section), fixed step, applied to the
+                           state, the variational equations and the LD integrand
+                           as one system; lane-per-orbit systems only (not FPU) */
+};
+
 /* Per-orbit status. */
 enum {
   CHX_ORBIT_OK = 0,
@@ -120,6 +132,8 @@ typedef struct {
   uint32_t flags;         /* CHX_PTR_DEVICE */
   int32_t block_size;     /* threads per block for the lane kernel; 0 -> tuned */
   void *stream;           /* hipStream_t for CHX_PTR_DEVICE calls */
+  int32_t integrator;     /* CHX_INT_*; 0 -> Yoshida-4.  The batched form and
+                             the convenience calls use Yoshida-4 */
 } chx_options;
 
 /* Fills *o with dt = T = 0 (must be set) and all defaults above. */

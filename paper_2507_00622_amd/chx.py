@@ -20,6 +20,8 @@ OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_INTERNA
 SYS_HENON_HEILES, SYS_FPUT, SYS_QUARTIC, SYS_HARMONIC = 1, 2, 3, 4
 IND_SALI, IND_GALI, IND_LYAP, IND_LD, IND_ENERGY = 1, 2, 4, 8, 16
 PTR_DEVICE = 1
+INT_YOSHIDA4, INT_DOP853 = 0, 1
+_INTEGRATORS = {"yoshida4": INT_YOSHIDA4, "dop853": INT_DOP853}
 ORBIT_OK, ORBIT_MASKED, ORBIT_ESCAPED, ORBIT_NONFINITE, ORBIT_EXITED = range(5)
 
 # Every function include/chx.h declares.
@@ -53,7 +55,8 @@ class _Options(C.Structure):
                 ("ld_p", C.c_double), ("sali_threshold", C.c_double),
                 ("early_exit", C.c_int32), ("steps_per_launch", C.c_int32),
                 ("seed", C.c_uint64), ("w0", C.c_void_p), ("escape_r2", C.c_double),
-                ("flags", C.c_uint32), ("block_size", C.c_int32), ("stream", C.c_void_p)]
+                ("flags", C.c_uint32), ("block_size", C.c_int32), ("stream", C.c_void_p),
+                ("integrator", C.c_int32)]
 
 
 RESULT_FIELDS = ["x_final", "t_end", "status", "label", "sali_final", "sali_min", "t_chaos",
@@ -235,7 +238,8 @@ class _Arrays:
 
 def make_options(dt, T, indicators, renorm_every=10, n_lyap=0, gali_kmax=0, ld_p=0.5,
                  sali_threshold=1e-8, early_exit=False, steps_per_launch=0, seed=0,
-                 escape_r2=0.0, block_size=0):
+                 escape_r2=0.0, block_size=0, integrator=INT_YOSHIDA4):
+    """integrator: INT_YOSHIDA4 / INT_DOP853, or "yoshida4" / "dop853"."""
     o = _Options()
     lib().chx_options_default(C.byref(o))
     o.dt, o.T, o.indicators = float(dt), float(T), int(indicators)
@@ -243,6 +247,7 @@ def make_options(dt, T, indicators, renorm_every=10, n_lyap=0, gali_kmax=0, ld_p
     o.ld_p, o.sali_threshold = float(ld_p), float(sali_threshold)
     o.early_exit, o.steps_per_launch = int(bool(early_exit)), int(steps_per_launch)
     o.seed, o.escape_r2, o.block_size = int(seed) & (2**64 - 1), float(escape_r2), int(block_size)
+    o.integrator = _INTEGRATORS[integrator] if isinstance(integrator, str) else int(integrator)
     return o
 
 

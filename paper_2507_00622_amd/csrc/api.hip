@@ -113,6 +113,10 @@ chx_status make_plan(const chx_system *sys, const chx_options *opt, Plan *p) {
   if (!(o.block_size == 0 || o.block_size == 64 || o.block_size == 128 || o.block_size == 256))
     return fail(CHX_ERR_INVALID_ARG, "block_size must be 0, 64, 128 or 256");
   if (o.flags & ~1u) return fail(CHX_ERR_INVALID_ARG, "unknown flags 0x%x", o.flags);
+  if (o.integrator != CHX_INT_YOSHIDA4 && o.integrator != CHX_INT_DOP853)
+    return fail(CHX_ERR_INVALID_ARG, "unknown integrator %d", o.integrator);
+  if (o.integrator == CHX_INT_DOP853 && sys->kind == CHX_SYS_FPUT)
+    return fail(CHX_ERR_UNSUPPORTED, "DOP853 is available for the lane-per-orbit systems (Henon-Heiles, quartic, harmonic), not FPUT");
   int m_s = 0;
   if (o.indicators & CHX_IND_SALI) m_s = 2;
   if (kmax > m_s) m_s = kmax;
@@ -290,6 +294,8 @@ chx_status advance(chx_ensemble *e, int64_t s_end) {
     if (a.n > 0) {
       hipError_t he = (e->kind == CHX_SYS_FPUT)
                           ? launch_fput_row(pl.N, pl.M, a, e->stream)
+                      : (pl.o.integrator == CHX_INT_DOP853)
+                          ? launch_lane_rk(e->kind, pl.N, pl.M, a, e->block, e->stream)
                           : launch_lane(e->kind, pl.N, pl.M, a, e->block, e->stream);
       if (he != hipSuccess) return dev_fail(he, "integration kernel");
     }

@@ -156,6 +156,8 @@ extern "C" chx_status chx_integrate_batched(const chx_batch_item *items, int32_t
   if (opt->indicators & (CHX_IND_GALI | CHX_IND_LYAP))
     return fail(CHX_ERR_UNSUPPORTED, "the batched form carries two deviation vectors: no GALI or Lyapunov");
   if (opt->w0) return fail(CHX_ERR_INVALID_ARG, "the batched form draws its deviation vectors: w0 must be NULL");
+  if (opt->integrator != CHX_INT_YOSHIDA4)
+    return fail(CHX_ERR_UNSUPPORTED, "the batched form integrates with Yoshida-4 only");
   std::vector<Plan> plans(n_items);
   std::vector<int> kinds(n_items);
   for (int i = 0; i < n_items; ++i) {

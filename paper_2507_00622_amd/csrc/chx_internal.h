@@ -63,6 +63,8 @@ struct StepArgs {
 hipError_t launch_lane(int sys, int ndof, int M, const StepArgs &a, int block,
                        hipStream_t s);
 bool lane_supported(int sys, int ndof, int M);
+hipError_t launch_lane_rk(int sys, int ndof, int M, const StepArgs &a, int block,
+                          hipStream_t s);
 hipError_t launch_fput_row(int ndof, int M, const StepArgs &a, hipStream_t s);
 bool fput_row_supported(int ndof, int M, int n_l, bool sali);
 

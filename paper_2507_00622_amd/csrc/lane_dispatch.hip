@@ -10,6 +10,14 @@ hipError_t launch_lane_harmonic1(int M, const StepArgs &a, int block, hipStream_
 hipError_t launch_lane_harmonic2(int M, const StepArgs &a, int block, hipStream_t s);
 hipError_t launch_lane_harmonic3(int M, const StepArgs &a, int block, hipStream_t s);
 
+hipError_t launch_lane_rk_hh(int M, const StepArgs &a, int block, hipStream_t s);
+hipError_t launch_lane_rk_quartic1(int M, const StepArgs &a, int block, hipStream_t s);
+hipError_t launch_lane_rk_quartic2(int M, const StepArgs &a, int block, hipStream_t s);
+hipError_t launch_lane_rk_quartic3(int M, const StepArgs &a, int block, hipStream_t s);
+hipError_t launch_lane_rk_harmonic1(int M, const StepArgs &a, int block, hipStream_t s);
+hipError_t launch_lane_rk_harmonic2(int M, const StepArgs &a, int block, hipStream_t s);
+hipError_t launch_lane_rk_harmonic3(int M, const StepArgs &a, int block, hipStream_t s);
+
 bool lane_supported(int sys, int ndof, int M) {
   if (M < 0 || M > 4 * ndof) return false;
   switch (sys) {
@@ -34,6 +42,25 @@ hipError_t launch_lane(int sys, int ndof, int M, const StepArgs &a, int block,
     return ndof == 1 ? launch_lane_harmonic1(M, a, block, s)
          : ndof == 2 ? launch_lane_harmonic2(M, a, block, s)
                      : launch_lane_harmonic3(M, a, block, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// The same systems with the DOP853 kernels.
+hipError_t launch_lane_rk(int sys, int ndof, int M, const StepArgs &a, int block,
+                          hipStream_t s) {
+  if (!lane_supported(sys, ndof, M)) return hipErrorInvalidValue;
+  if (a.n == 0) return hipSuccess;
+  switch (sys) {
+  case SYS_HH: return launch_lane_rk_hh(M, a, block, s);
+  case SYS_QUARTIC:
+    return ndof == 1 ? launch_lane_rk_quartic1(M, a, block, s)
+         : ndof == 2 ? launch_lane_rk_quartic2(M, a, block, s)
+                     : launch_lane_rk_quartic3(M, a, block, s);
+  case SYS_HARMONIC:
+    return ndof == 1 ? launch_lane_rk_harmonic1(M, a, block, s)
+         : ndof == 2 ? launch_lane_rk_harmonic2(M, a, block, s)
+                     : launch_lane_rk_harmonic3(M, a, block, s);
   }
   return hipErrorInvalidValue;
 }

@@ -1,0 +1,235 @@
+// lane_rk.h -- one lane per orbit with the fixed-step DOP853 integrator.
+//
+// The paper's solvers are built on DOP853, the explicit Runge-Kutta method
+// of order 8 of Dormand and Prince (Functionalities section).  Here it is
+// used with a fixed step and only its eighth-order solution (no error
+// estimate, no step-size control), applied to one extended system per
+// orbit:
+//   dq/dt = p,  dp/dt = -grad V(q)                 (Hamilton's equations)
+//   d(dq)/dt = dp,  d(dp)/dt = -Hess V(q) dq      (variational equations)
+//   dM/dt = sum over the 2N components |dx_i/dt|^p (LD M-function)
+// so the deviation vectors follow the exact Jacobian of the discrete step
+// and the LD is integrated to the method's order.
+//
+// A step k_i = dt f(y + sum_{j<i} a_ij k_j), y <- y + sum_i b_i k_i is done
+// in two passes to keep the live registers few: first the state (12 stages;
+// the stage positions go to LDS), then each deviation vector on its own,
+// whose stages need only the Hessian at those positions.  The stage
+// derivatives a pass still needs are held in registers; with the method's
+// zero pattern (stages 2 and 3 feed only stages 3..5, and the solution
+// does not use stages 2..5) at most nine are live at once.  The stage
+// positions (12 N doubles per orbit) live in dynamic LDS, field-major
+// (position component f of thread t at f * blockDim + t), so the vectors'
+// registers stay below the three-wavefronts-per-SIMD budget.
+//
+// Load, store and the checkpoints (renormalisation, SALI, Gram-Schmidt,
+// energy, escape, early exit) are those of the Yoshida-4 lane kernel.
+#pragma once
+#include <type_traits>
+
+#include "lane_kernel.h"
+
+namespace chx {
+
+namespace dop853 {
+
+// The published coefficients (Prince and Dormand 1981, in the 12-stage
+// form of Hairer, Norsett and Wanner, Solving ODEs I, Sect. II.10) to 30
+// significant digits; zero where the method has none.
+constexpr double A[12][12] = {
+    {},
+    {5.26001519587677318785587544488e-2},
+    {1.97250569845378994544595329183e-2, 5.91751709536136983633785987549e-2},
+    {2.95875854768068491816892993775e-2, 0.0, 8.87627564304205475450678981324e-2},
+    {2.41365134159266685502369798665e-1, 0.0, -8.84549479328286085344864962717e-1,
+     9.24834003261792003115737966543e-1},
+    {3.7037037037037037037037037037e-2, 0.0, 0.0, 1.70828608729473871279604482173e-1,
+     1.25467687566822425016691814123e-1},
+    {3.7109375e-2, 0.0, 0.0, 1.70252211019544039314978060272e-1,
+     6.02165389804559606850219397283e-2, -1.7578125e-2},
+    {3.70920001185047927108779319836e-2, 0.0, 0.0, 1.70383925712239993810214054705e-1,
+     1.07262030446373284651809199168e-1, -1.53194377486244017527936158236e-2,
+     8.27378916381402288758473766002e-3},
+    {6.24110958716075717114429577812e-1, 0.0, 0.0, -3.36089262944694129406857109825,
+     -8.68219346841726006818189891453e-1, 2.75920996994467083049415600797e1,
+     2.01540675504778934086186788979e1, -4.34898841810699588477366255144e1},
+    {4.77662536438264365890433908527e-1, 0.0, 0.0, -2.48811461997166764192642586468,
+     -5.90290826836842996371446475743e-1, 2.12300514481811942347288949897e1,
+     1.52792336328824235832596922938e1, -3.32882109689848629194453265587e1,
+     -2.03312017085086261358222928593e-2},
+    {-9.3714243008598732571704021658e-1, 0.0, 0.0, 5.18637242884406370830023853209,
+     1.09143734899672957818500254654, -8.14978701074692612513997267357,
+     -1.85200656599969598641566180701e1, 2.27394870993505042818970056734e1,
+     2.49360555267965238987089396762, -3.0467644718982195003823669022},
+    {2.27331014751653820792359768449, 0.0, 0.0, -1.05344954667372501984066689879e1,
+     -2.00087205822486249909675718444, -1.79589318631187989172765950534e1,
+     2.79488845294199600508499808837e1, -2.85899827713502369474065508674,
+     -8.87285693353062954433549289258, 1.23605671757943030647266201528e1,
+     6.43392746015763530355970484046e-1},
+};
+constexpr double B[12] = {5.42937341165687622380535766363e-2, 0.0, 0.0, 0.0, 0.0,
+                          4.45031289275240888144113950566,   1.89151789931450038304281599044,
+                          -5.8012039600105847814672114227,   3.1116436695781989440891606237e-1,
+                          -1.52160949662516078556178806805e-1,
+                          2.01365400804030348374776537501e-1,
+                          4.47106157277725905176885569043e-2};
+
+template <int I, int E, class Fn>
+__device__ __forceinline__ void static_for(Fn &&f) {
+  if constexpr (I < E) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, E>(f);
+  }
+}
+
+// sum_{j<I} A[I][j] k[j][c] over the non-zero entries, in order of j
+template <int I, int D>
+__device__ __forceinline__ double stage_sum(const double (&k)[12][D], int c) {
+  double s = 0.0;
+  static_for<0, I>([&](auto jc) {
+    constexpr int J = decltype(jc)::value;
+    if constexpr (A[I][J] != 0.0) s = __builtin_fma(A[I][J], k[J][c], s);
+  });
+  return s;
+}
+template <int D>
+__device__ __forceinline__ double final_sum(const double (&k)[12][D], int c) {
+  double s = 0.0;
+  static_for<0, 12>([&](auto jc) {
+    constexpr int J = decltype(jc)::value;
+    if constexpr (B[J] != 0.0) s = __builtin_fma(B[J], k[J][c], s);
+  });
+  return s;
+}
+
+}  // namespace dop853
+
+template <class S, int M, bool GP>
+struct RKOrbit : LaneOrbit<S, M, GP, -1> {
+  using Base = LaneOrbit<S, M, GP, -1>;
+  using Base::N;
+  using Base::D;
+  using Base::x;
+  using Base::w;
+  using Base::ld;
+
+  // one fixed DOP853 step of size h of the state, the M vectors and the LD;
+  // qs: this thread's stage positions in LDS, component f at qs[f * stride]
+  __device__ __forceinline__ void rk_step(const StepArgs &a, double h, bool do_ld, double *qs,
+                                          int stride) {
+    {
+      double k[12][D];  // h f(Y_i) of the state
+      double g = 0.0;   // sum_i b_i (LD integrand at stage i)
+      dop853::static_for<0, 12>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        double Y[D], F[N];
+#pragma unroll
+        for (int c = 0; c < D; ++c) Y[c] = x[c] + dop853::stage_sum<I>(k, c);
+        if constexpr (M > 0) {
+#pragma unroll
+          for (int r = 0; r < N; ++r) qs[(I * N + r) * stride] = Y[r];
+        }
+        S::force(Y, F, a.prm);
+        if constexpr (dop853::B[I] != 0.0) {
+          if (do_ld) {
+            double gi = 0.0;
+#pragma unroll
+            for (int r = 0; r < N; ++r) gi += this->ld_term(a, Y[N + r]) + this->ld_term(a, F[r]);
+            g = __builtin_fma(dop853::B[I], gi, g);
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+          k[I][r] = h * Y[N + r];
+          k[I][N + r] = -h * F[r];
+        }
+      });
+#pragma unroll
+      for (int c = 0; c < D; ++c) x[c] += dop853::final_sum(k, c);
+      if (do_ld) ld = __builtin_fma(h, g, ld);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+      double k[12][D];  // h f(dY_i) of vector v
+      dop853::static_for<0, 12>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        double Y[D], Hs[S::NH], q[N];
+#pragma unroll
+        for (int r = 0; r < N; ++r) q[r] = qs[(I * N + r) * stride];
+#pragma unroll
+        for (int c = 0; c < D; ++c) Y[c] = w[v][c] + dop853::stage_sum<I>(k, c);
+        S::hess_scaled(q, h, Hs, a.prm);
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+          double s = 0.0;
+#pragma unroll
+          for (int j = 0; j < N; ++j) s = __builtin_fma(Hs[hidx(N, r, j)], Y[j], s);
+          k[I][r] = h * Y[N + r];
+          k[I][N + r] = -s;
+        }
+      });
+#pragma unroll
+      for (int c = 0; c < D; ++c) w[v][c] += dop853::final_sum(k, c);
+      // one vector pass at a time: overlapped by the scheduler, two passes'
+      // stage derivatives would be live together
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+};
+
+// Dynamic LDS of the DOP853 lane kernels: 12 N doubles per thread.
+extern __shared__ double lane_rk_lds[];
+
+template <class S, int M, bool GP>
+__global__ void __launch_bounds__(256) lane_rk_kernel(const StepArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  if (a.st[i] != CHX_ORBIT_OK) return;
+  RKOrbit<S, M, GP> o;
+  o.load(a, i);
+  const bool do_ld = (a.ind & CHX_IND_LD) != 0;
+  const double h = a.dt;
+  int64_t s = a.s_begin;
+  const int64_t K = a.K;
+  while (s < a.s_end) {
+    int64_t next = (s / K + 1) * K;
+    if (next > a.n_total) next = a.n_total;
+    for (int64_t j = s; j < next; ++j) o.rk_step(a, h, do_ld, lane_rk_lds + threadIdx.x, blockDim.x);
+    s = next;
+    if (!o.checkpoint(a, (double)s * a.dt)) break;
+  }
+  // the store addresses are formed here, not kept from the loads
+  int64_t ob = i;
+  asm volatile("" : "+v"(ob));
+  o.store(a, ob);
+}
+
+template <class S, int M>
+struct LaneRKDispatch {
+  static hipError_t go(int m, const StepArgs &a, int block, hipStream_t s) {
+    if (m == M) {
+      const bool gp = (a.ind & CHX_IND_LD) && a.ld_p != 0.5;
+      // at most 64 KB of stage positions per block (the 3-dof kernels run
+      // 128-thread blocks)
+      if (M > 0)
+        while (block > 64 && sizeof(double) * 12 * S::N * (size_t)block > 65536) block /= 2;
+      const int64_t grid = (a.n + block - 1) / block;
+      const size_t lds = M > 0 ? sizeof(double) * 12 * S::N * (size_t)block : 0;
+      if (gp)
+        hipLaunchKernelGGL((lane_rk_kernel<S, M, true>), dim3((unsigned)grid), dim3(block), lds,
+                           s, a);
+      else
+        hipLaunchKernelGGL((lane_rk_kernel<S, M, false>), dim3((unsigned)grid), dim3(block), lds,
+                           s, a);
+      return hipGetLastError();
+    }
+    return LaneRKDispatch<S, M - 1>::go(m, a, block, s);
+  }
+};
+template <class S>
+struct LaneRKDispatch<S, -1> {
+  static hipError_t go(int, const StepArgs &, int, hipStream_t) { return hipErrorInvalidValue; }
+};
+
+}  // namespace chx

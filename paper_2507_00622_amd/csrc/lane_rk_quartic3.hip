@@ -1,0 +1,9 @@
+// DOP853 lane-per-orbit kernels for the coupled quartic oscillator with 3 degree(s) of freedom:
+// up to 12 deviation vectors.
+#include "lane_rk.h"
+
+namespace chx {
+hipError_t launch_lane_rk_quartic3(int M, const StepArgs &a, int block, hipStream_t s) {
+  return LaneRKDispatch<SysQuartic<3>, 12>::go(M, a, block, s);
+}
+}  // namespace chx

@@ -32,7 +32,7 @@ def test_exports_every_declared_function():
 def test_struct_layouts_match_header():
     L = chx.lib()
     assert L.chx_struct_size(0) == C.sizeof(chx._System) == 24
-    assert L.chx_struct_size(1) == C.sizeof(chx._Options) == 96
+    assert L.chx_struct_size(1) == C.sizeof(chx._Options) == 104
     assert L.chx_struct_size(2) == C.sizeof(chx._Result) == 12 * 8
     assert L.chx_struct_size(3) == C.sizeof(chx._BatchItem) == 64
     assert L.chx_struct_size(4) == C.sizeof(chx._BatchStats)
@@ -46,6 +46,7 @@ def test_options_default():
     chx.lib().chx_options_default(C.byref(o))
     assert o.renorm_every == 10 and o.ld_p == 0.5 and o.sali_threshold == 1e-8
     assert o.dt == 0 and o.flags == 0 and o.w0 is None
+    assert o.integrator == chx.INT_YOSHIDA4
 
 
 def hh_x0(n=3):
@@ -85,11 +86,23 @@ def test_bad_systems():
     (dict(indicators=chx.IND_SALI, block_size=96), "block_size"),
     (dict(indicators=chx.IND_SALI, escape_r2=-1.0), "escape_r2"),
     (dict(indicators=chx.IND_SALI, sali_threshold=-1.0), "sali_threshold"),
+    (dict(indicators=chx.IND_SALI, integrator=7), "integrator"),
 ])
 def test_bad_options(kw, msg):
     with pytest.raises(chx.ChxError) as e:
         chx.integrate_ensemble(P.henon_heiles(), hh_x0(), dt=0.01, T=1.0, **kw)
     assert e.value.status == chx.ERR_INVALID_ARG and msg in str(e.value)
+
+
+def test_dop853_is_for_lane_systems_only():
+    with pytest.raises(chx.ChxError) as e:
+        chx.integrate_ensemble(P.fput(4), np.zeros((2, 8)), dt=0.01, T=1.0,
+                               indicators=chx.IND_SALI, integrator="dop853")
+    assert e.value.status == chx.ERR_UNSUPPORTED and "DOP853" in str(e.value)
+    with pytest.raises(chx.ChxError) as e:
+        chx.integrate_batched([dict(sys=P.henon_heiles(), x0=hh_x0(4), dt=0.01, T=1.0)],
+                              indicators=chx.IND_SALI, integrator="dop853")
+    assert e.value.status == chx.ERR_UNSUPPORTED and "Yoshida-4" in str(e.value)
 
 
 def test_label_needs_sali():

@@ -30,6 +30,28 @@ def test_henon_heiles_flop_model():
     assert bench.flops_per_step(2, 2, 0, False, True, True, 10) == pytest.approx(139.0)
 
 
+def test_dop853_flop_model():
+    # per stage: FMA per non-zero a_ij and component (50 in all) + the add to
+    # the start value; state: 12 forces (6) and h-scalings (4); vectors: 12
+    # scaled Hessians (5), 2x2 mat-vecs (8) and h-scalings (2); final sums
+    # over the 8 weighted stages; LD at those stages; checkpoints / 10
+    # as for Yoshida-4
+    sums = 2 * 4 * 50 + 4 * 11
+    final = 2 * 4 * 8 + 4
+    state = sums + 12 * 6 + 12 * 4 + final
+    vec = sums + 12 * (5 + 8 + 2) + final
+    assert bench.flops_per_step_dop853(2, 2, 4, True, True, True, 10) == pytest.approx(
+        state + 6 * vec + 8 * 5 + 2 + 19.8)
+    assert bench.DOP853_ROW_NNZ == (0, 1, 2, 2, 3, 3, 4, 5, 6, 7, 8, 9)
+
+
+def test_dop853_tableau_pattern_matches_the_oracle():
+    from oracle import oracle as O
+    c, a, b = O.dop853_tableau()
+    assert tuple(int(v) for v in (a != 0).sum(axis=1)) == bench.DOP853_ROW_NNZ
+    assert int((b != 0).sum()) == bench.DOP853_B_NNZ
+
+
 def test_fput_and_quartic_flop_models():
     assert bench.flops_per_step_fput(16, 16, 32, False, True, True, 10) == pytest.approx(26202.0)
     assert bench.flops_per_step_fput(8, 8, 16, False, True, True, 10) == pytest.approx(5999.6)

@@ -1,0 +1,270 @@
+"""GPU parity of the fixed-step DOP853 lane kernels (Henon-Heiles, quartic,
+harmonic) against the oracle's DOP853 driver, through the C ABI.
+
+Same tolerances as the Yoshida-4 lane tests (the two sides round
+differently: the HIP path sums each stage with fused multiply-adds of
+h-scaled stage derivatives, the oracle sums unscaled ones and multiplies by
+dt once):
+  - state of regular orbits (oracle label at T = 1e4), T = 200: relative 1e-9;
+  - at short T (T = 100 at E = 0.125, 50 at E = 1/6): |log10 SALI| 1e-6
+    where both are >= 1e-12, |log10 GALI| 1e-6 where both are >= 1e-8,
+    Lyapunov exponents 1e-6 absolute, LD 1e-9 relative, energy error 1e-12
+    absolute;
+  - status codes, t_end and masks exactly.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import seeded_inputs as S
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ALL = 1 | 2 | 4 | 8 | 16
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2507_00622_amd as P
+    from oracle import oracle as O
+    return torch, P, O
+
+
+def run_gpu(env, sys_, x0, mask=None, w0=None, **kw):
+    torch, P, _ = env
+    dev = torch.device("cuda:0")
+    t = lambda a: None if a is None else torch.as_tensor(a, device=dev)
+    out = P.integrate_ensemble(sys_, t(x0), mask=t(mask), w0=t(w0), integrator="dop853", **kw)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def oracle_run(O, **kw):
+    return O.Run(integrator=O.INT_DOP853, **kw)
+
+
+def state_err(a, b):
+    return np.max(np.abs(a - b), axis=1) / np.maximum(1.0, np.max(np.abs(b), axis=1))
+
+
+def log_err(a, b, floor=1e-12):
+    ok = (a >= floor) & (b >= floor)
+    if not ok.any():
+        return 0.0
+    return float(np.max(np.abs(np.log10(a[ok]) - np.log10(b[ok]))))
+
+
+def golden_labels():
+    lab = {}
+    for line in open(os.path.join(HERE, "golden", "hh_e0125_32x32_T1e4.txt")):
+        if line.startswith("#"):
+            continue
+        i, l, _ = line.split()
+        lab[int(i)] = int(l)
+    return np.array([lab[i] for i in range(len(lab))])
+
+
+def test_dop853_hh_state_regular_T200(env):
+    torch, P, O = env
+    say("case: DOP853 HH E=0.125 32x32, SALI+LD+energy, T=200")
+    x0, mask = O.hh_grid(0.125, 32, 32)
+    w0 = S.deviation_vectors(1001, len(x0), 2, 4)
+    ind = O.IND_SALI | O.IND_LD | O.IND_ENERGY
+    g = run_gpu(env, P.henon_heiles(), x0, mask, w0, dt=0.01, T=200.0, indicators=ind)
+    o = O.integrate(O.henon_heiles(), x0, oracle_run(O, dt=0.01, T=200.0, indicators=ind),
+                    w0=w0, mask=mask, threads=8)
+    assert np.array_equal(g["status"], o["status"])
+    assert np.array_equal(g["label"] == -1, mask == 0)
+    reg = golden_labels() == 0
+    err = state_err(g["x_final"][reg], o["x_final"][reg])
+    say("  max regular-orbit state error:", err.max())
+    assert err.max() < 1e-9
+    act = mask == 1
+    say("  energy error: max", o["energy_err"][act].max(), "diff",
+        np.max(np.abs(g["energy_err"][act] - o["energy_err"][act])))
+    assert np.max(np.abs(g["energy_err"][act] - o["energy_err"][act])) < 1e-12
+    assert np.max(np.abs(g["ld"][reg] / o["ld"][reg] - 1)) < 1e-9
+    assert np.array_equal(g["label"][reg], o["label"][reg])
+
+
+def test_dop853_hh_all_indicators_short_T(env):
+    torch, P, O = env
+    for E, T in ((0.125, 100.0), (1.0 / 6.0, 50.0)):
+        say(f"case: DOP853 HH E={E:.6f} 24x24, all indicators, T={T}")
+        x0, mask = O.hh_grid(E, 24, 24)
+        w0 = S.deviation_vectors(7, len(x0), 2, 4)
+        kw = dict(dt=0.01, T=T, indicators=ALL, gali_kmax=2, n_lyap=4, escape_r2=4.0)
+        g = run_gpu(env, P.henon_heiles(), x0, mask, w0, **kw)
+        o = O.integrate(O.henon_heiles(), x0, oracle_run(O, **kw), w0=w0, mask=mask,
+                        threads=8)
+        act = mask == 1
+        assert np.array_equal(g["status"], o["status"])
+        ok = act & (o["status"] == 0)
+        le = np.max(np.abs(g["lyap"][ok] - o["lyap"][ok]))
+        say("  sali", log_err(g["sali_min"][ok], o["sali_min"][ok]),
+            "gali", log_err(g["gali"][ok, 0], o["gali"][ok, 0], floor=1e-8), "lyap", le,
+            "max |sum of exponents|", np.max(np.abs(g["lyap"][ok].sum(axis=1))))
+        assert log_err(g["sali_min"][ok], o["sali_min"][ok]) < 1e-6
+        assert log_err(g["sali_final"][ok], o["sali_final"][ok]) < 1e-6
+        assert log_err(g["gali"][ok, 0], o["gali"][ok, 0], floor=1e-8) < 1e-6
+        assert le < 1e-6
+        assert np.max(np.abs(g["ld"][ok] / o["ld"][ok] - 1)) < 1e-9
+        assert np.max(np.abs(g["energy_err"][ok] - o["energy_err"][ok])) < 1e-12
+        # volume preservation of the flow, to the method's truncation error
+        assert np.max(np.abs(g["lyap"][ok].sum(axis=1))) < 1e-9
+
+
+@pytest.mark.parametrize("K,T", [(10, 3.0), (7, 2.53), (1, 0.5)])
+def test_dop853_checkpoint_periods_and_ragged_tail(env, K, T):
+    torch, P, O = env
+    say(f"case: DOP853 HH K={K} T={T}")
+    rng = np.random.default_rng(K)
+    n = 333  # not a multiple of the block or the wavefront
+    x0, mask = O.hh_points(0.125, rng.uniform(-0.4, 0.7, n), rng.uniform(-0.45, 0.45, n))
+    w0 = S.deviation_vectors(3, n, 2, 4)
+    kw = dict(dt=0.01, T=T, indicators=ALL, gali_kmax=2, n_lyap=4, renorm_every=K)
+    g = run_gpu(env, P.henon_heiles(), x0, mask, w0, **kw)
+    o = O.integrate(O.henon_heiles(), x0,
+                    oracle_run(O, dt=0.01, T=T, indicators=ALL, gali_kmax=2, n_lyap=4, K=K),
+                    w0=w0, mask=mask)
+    act = mask == 1
+    assert np.array_equal(g["status"], o["status"])
+    assert np.array_equal(g["t_end"][act], o["t_end"][act])
+    assert np.max(np.abs(g["lyap"][act] - o["lyap"][act])) < 1e-9
+    assert np.max(state_err(g["x_final"][act], o["x_final"][act])) < 1e-11
+    assert np.max(np.abs(g["ld"][act] / o["ld"][act] - 1)) < 1e-11
+
+
+def test_dop853_status_codes_and_early_exit(env):
+    torch, P, O = env
+    say("case: DOP853 status codes")
+
+    def hh(E, y, py):
+        r = 2 * E - py * py - y * y + 2 * y**3 / 3
+        return [0.0, y, np.sqrt(r), py]
+
+    x0 = np.array([hh(0.125, 0.1, 0.0), [np.nan, 0, 0, 0], hh(0.2, 0.1, 0.0),
+                   hh(0.125, 0.1, 0.0), hh(0.125, -0.25, 0.0), [np.inf, 1, 0, 0]])
+    mask = np.array([1, 1, 1, 0, 1, 1], np.uint8)
+    w0 = S.deviation_vectors(2, len(x0), 2, 4)
+    kw = dict(dt=0.01, T=2000.0, indicators=O.IND_SALI | O.IND_LD | O.IND_LYAP, n_lyap=4,
+              escape_r2=4.0, early_exit=True)
+    g = run_gpu(env, P.henon_heiles(), x0, mask, w0, **kw)
+    o = O.integrate(O.henon_heiles(), x0, oracle_run(O, **kw), w0=w0, mask=mask)
+    say("  status", g["status"], o["status"], "t_end", g["t_end"], o["t_end"])
+    assert list(g["status"]) == [0, 3, 2, 1, 4, 3]
+    assert np.array_equal(g["status"], o["status"])
+    assert np.array_equal(g["label"], o["label"])
+    assert g["t_end"][2] == o["t_end"][2] and g["t_end"][4] == o["t_end"][4]
+
+
+def test_dop853_resume_bitwise_and_block_sizes(env):
+    torch, P, O = env
+    say("case: DOP853 resume and block sizes")
+    x0, mask = O.hh_grid(0.125, 16, 16)
+    w0 = S.deviation_vectors(5, len(x0), 2, 4)
+    dev = torch.device("cuda:0")
+    kw = dict(dt=0.01, T=20.0, indicators=ALL, gali_kmax=2, n_lyap=4)
+    ref = run_gpu(env, P.henon_heiles(), x0, mask, w0, **kw)
+    e = P.Ensemble(P.henon_heiles(), torch.as_tensor(x0, device=dev),
+                   mask=torch.as_tensor(mask, device=dev), w0=torch.as_tensor(w0, device=dev),
+                   steps_per_launch=130, integrator="dop853", **kw)
+    for s in (400, 1170, 2000):
+        e.advance(s)
+    r = {k: v.cpu().numpy() for k, v in e.results().items()}
+    e.close()
+    for k in ref:
+        assert np.array_equal(ref[k], r[k], equal_nan=True), k
+    for block in (64, 128):
+        b = run_gpu(env, P.henon_heiles(), x0, mask, w0, block_size=block, **kw)
+        for k in ref:
+            assert np.array_equal(ref[k], b[k], equal_nan=True), (block, k)
+
+
+@pytest.mark.parametrize("N", [1, 2, 3])
+def test_dop853_quartic_parity(env, N):
+    torch, P, O = env
+    say(f"case: DOP853 quartic N={N}")
+    so, sg = O.quartic(N, 0.1), P.quartic(N, 0.1)
+    x0 = O.quartic_ic(so, S.quartic_draws(31, 200, N))
+    w0 = S.deviation_vectors(4, len(x0), 2, 2 * N)
+    kw = dict(dt=0.01, T=50.0, indicators=ALL, gali_kmax=2, n_lyap=2 * N)
+    g = run_gpu(env, sg, x0, None, w0, **kw)
+    o = O.integrate(so, x0, oracle_run(O, **kw), w0=w0)
+    say("  state", np.max(state_err(g["x_final"], o["x_final"])), "lyap",
+        np.max(np.abs(g["lyap"] - o["lyap"])))
+    assert np.max(state_err(g["x_final"], o["x_final"])) < 1e-9
+    assert np.max(np.abs(g["lyap"] - o["lyap"])) < 1e-6
+    assert log_err(g["sali_min"], o["sali_min"]) < 1e-6
+    assert np.max(np.abs(g["ld"] / o["ld"] - 1)) < 1e-9
+
+
+def test_dop853_harmonic_parity_and_bounds(env):
+    torch, P, O = env
+    say("case: DOP853 harmonic")
+    w = [1.0, np.sqrt(2.0), 0.5]
+    rng = np.random.default_rng(1)
+    x0 = rng.uniform(-1, 1, (100, 6))
+    w0 = S.deviation_vectors(8, 100, 4, 6)
+    kw = dict(dt=0.01, T=100.0, indicators=ALL, gali_kmax=4, n_lyap=6)
+    g = run_gpu(env, P.harmonic(w), x0, None, w0, **kw)
+    o = O.integrate(O.harmonic(w), x0, oracle_run(O, **kw), w0=w0)
+    assert np.max(state_err(g["x_final"], o["x_final"])) < 1e-11
+    assert np.max(np.abs(g["lyap"] - o["lyap"])) < 1e-9
+    # integrable: the exponents vanish like ln(t)/t, GALI_k stays bounded
+    assert np.max(np.abs(g["lyap"])) <= np.log(2.0) / 100.0 + 1e-9
+    for k in range(3):
+        assert log_err(g["gali"][:, k], o["gali"][:, k]) < 1e-9
+    # closed form of the state: x(t) = A cos(w t + phi)
+    T = 100.0
+    om = np.array(w)
+    q0, p0 = x0[:, :3], x0[:, 3:]
+    q = q0 * np.cos(om * T) + p0 / om * np.sin(om * T)
+    p = -q0 * om * np.sin(om * T) + p0 * np.cos(om * T)
+    assert np.max(np.abs(g["x_final"] - np.hstack([q, p]))) < 1e-11
+
+
+def test_dop853_general_ld_exponent(env):
+    torch, P, O = env
+    say("case: DOP853 ld p=0.3")
+    x0, mask = O.hh_grid(0.125, 10, 10)
+    kw = dict(dt=0.01, T=20.0, indicators=O.IND_LD, ld_p=0.3)
+    g = run_gpu(env, P.henon_heiles(), x0, mask, None, **kw)
+    o = O.integrate(O.henon_heiles(), x0, oracle_run(O, **kw), mask=mask)
+    act = mask == 1
+    assert np.max(np.abs(g["ld"][act] / o["ld"][act] - 1)) < 1e-9
+
+
+def test_dop853_full_hh_grid_sampled(env):
+    # the launch configuration the DOP853 benchmark times: the 1024^2 grid at
+    # E = 0.125 with 6 vectors; sampled orbits against the oracle
+    torch, P, O = env
+    say("case: DOP853 HH 1024x1024 grid, 6 vectors, T=10, sampled")
+    dev = torch.device("cuda:0")
+    x0, mask = P.grid_hh_section(0.125, 1024, 1024, device=dev)
+    kw = dict(dt=0.01, T=10.0, indicators=ALL, gali_kmax=2, n_lyap=4, seed=1002)
+    out = P.integrate_ensemble(P.henon_heiles(), x0, mask=mask, integrator="dop853", **kw)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    m = mask.cpu().numpy()
+    act = np.flatnonzero(m)
+    assert len(act) == 850874
+    idx = act[np.linspace(0, len(act) - 1, 24).astype(int)]
+    x0h = x0.cpu().numpy()[idx]
+    w0 = np.concatenate([S.deviation_vectors(1002, 1, 2, 4, first_ic=int(i)) for i in idx])
+    o = O.integrate(O.henon_heiles(), x0h, oracle_run(O, **{k: v for k, v in kw.items()
+                                                             if k != "seed"}), w0=w0)
+    assert np.max(state_err(g["x_final"][idx], o["x_final"])) < 1e-11
+    assert np.max(np.abs(g["lyap"][idx] - o["lyap"])) < 1e-9
+    assert log_err(g["sali_min"][idx], o["sali_min"]) < 1e-9
+    assert np.all(g["status"][act] == 0)
