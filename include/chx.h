@@ -92,11 +92,23 @@ enum {
   CHX_INT_YOSHIDA4 = 0, /* fourth-order symplectic triple jump of kick-drift-kick
                            leapfrog (Yoshida 1990); the tangent map is its exact
                            Jacobian; LD by the trapezoid rule over step ends */
-  CHX_INT_DOP853 = 1    /* the eighth-order explicit Runge-Kutta method of
+  CHX_INT_DOP853 = 1,   /* the eighth-order explicit Runge-Kutta method of
                            Dormand and Prince that the paper's solvers build on
                            (Functionalities section), fixed step, applied to the
                            state, the variational equations and the LD integrand
                            as one system; lane-per-orbit systems only (not FPU) */
+  CHX_INT_DOP853_ADAPTIVE = 2 /* the adaptive DOP 8(5) solver of the same
+                           section: the same system, each orbit with its own step
+                           size chosen from DOP853's embedded error estimate
+                           (measured on the state and the deviation vectors,
+                           tolerances rtol/atol) by the step-size controller of
+                           Hairer-Norsett-Wanner's DOP853 (safety 0.9, step ratio
+                           in [1/3.003, 6], exponent 1/8).  dt is the first step
+                           and the unit of the checkpoint schedule: checkpoints
+                           stay at multiples of K dt and at T, which the steps hit
+                           exactly.  More than 100000 attempts between two
+                           checkpoints stop the orbit (CHX_ORBIT_STEP_FAILED).
+                           Lane-per-orbit systems only. */
 };
 
 /* Per-orbit status. */
@@ -105,7 +117,9 @@ enum {
   CHX_ORBIT_MASKED = 1,    /* mask[i] == 0: not integrated */
   CHX_ORBIT_ESCAPED = 2,   /* |q|^2 > escape_r2 at a checkpoint: stopped there */
   CHX_ORBIT_NONFINITE = 3, /* non-finite state at t = 0 or at a checkpoint */
-  CHX_ORBIT_EXITED = 4     /* early exit: SALI < threshold at a checkpoint */
+  CHX_ORBIT_EXITED = 4,    /* early exit: SALI < threshold at a checkpoint */
+  CHX_ORBIT_STEP_FAILED = 5 /* adaptive solver: no acceptable step between two
+                              checkpoints (label 3, outputs NaN like non-finite) */
 };
 
 typedef struct {
@@ -134,6 +148,8 @@ typedef struct {
   void *stream;           /* hipStream_t for CHX_PTR_DEVICE calls */
   int32_t integrator;     /* CHX_INT_*; 0 -> Yoshida-4.  The batched form and
                              the convenience calls use Yoshida-4 */
+  double rtol, atol;      /* CHX_INT_DOP853_ADAPTIVE tolerances, >= 0, not both
+                             0; 0 and 0 -> 1e-10 each.  Ignored otherwise */
 } chx_options;
 
 /* Fills *o with dt = T = 0 (must be set) and all defaults above. */
@@ -154,6 +170,8 @@ typedef struct {
   double *ld;         /* [n] M-function over [0, t_end] */
   double *energy_err; /* [n] max |H - H(0)| */
   double *ln_growth;  /* [n][m_s] sum of ln |w_v| over renormalisations */
+  int64_t *steps;     /* [n][2] accepted and rejected steps of the adaptive
+                         solver (zeros for the fixed-step integrators) */
 } chx_result;
 
 /* Whole-ensemble integration (Functionalities section: the solvers with

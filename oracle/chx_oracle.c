@@ -321,6 +321,27 @@ void ora_dop853_tableau(double c[12], double a[144], double b[12]) {
   }
 }
 
+/* Error estimators of DOP853 (same sources): the difference between the
+ * eighth-order solution and an embedded fifth-order one, weights er_i, and an
+ * embedded third-order solution on stages 1, 9 and 12, weights bhh. */
+static const double DOP_ER[12] = {
+    0.1312004499419488073250102996e-01, 0.0, 0.0, 0.0, 0.0,
+    -0.1225156446376204440720569753e+01,
+    -0.4957589496572501915214079952,
+    0.1664377182454986536961530415e+01,
+    -0.3503288487499736816886487290,
+    0.3341791187130174790297318841,
+    0.8192320648511571246570742613e-01,
+    -0.2235530786388629525884427845e-01};
+static const double DOP_BHH[3] = {0.244094488188976377952755905512,
+                                  0.733846688281611857341361741547,
+                                  0.220588235294117647058823529412e-01};
+
+void ora_dop853_error_weights(double er[12], double bhh[3]) {
+  for (int i = 0; i < 12; ++i) er[i] = DOP_ER[i];
+  for (int i = 0; i < 3; ++i) bhh[i] = DOP_BHH[i];
+}
+
 /* Right-hand side of the extended system y = (x, w_1..w_m, M):
  *   dq/dt = p, dp/dt = -grad V(q)               (Hamilton's equations)
  *   d(dq)/dt = dp, d(dp)/dt = -Hess V(q) dq    (variational equations)
@@ -377,9 +398,55 @@ static void dop853_step_ws(int kind, int N, const double *pr, double dt, double 
   }
 }
 
+/* One attempted step of size h with DOP853's error estimate.  ynew receives
+ * y + h sum_i b_i k_i.  The error is measured on the first ne components
+ * (the state and the deviation vectors; the LD accumulator is left out: its
+ * integrand |dx_i/dt|^p has a square-root cusp at every zero crossing of a
+ * component, which no step size resolves):
+ *   sk_c = atol + rtol max(|y_c|, |ynew_c|),
+ *   e5 = sum_c (sum_i er_i k_i,c / sk_c)^2,
+ *   e3 = sum_c ((sum_i b_i k_i,c - bhh1 k_1,c - bhh2 k_9,c - bhh3 k_12,c) / sk_c)^2,
+ *   err = |h| e5 / sqrt(ne (e5 + 0.01 e3))   (err = 0 when e5 = e3 = 0).
+ * ws as for dop853_step_ws plus ny more doubles. */
+static double dop853_attempt(int kind, int N, const double *pr, double h, const double *y,
+                             double *ynew, int m, int do_ld, double ldp, double rtol,
+                             double atol, double *ws) {
+  const int64_t ny = (int64_t)2 * N * (1 + m) + (do_ld ? 1 : 0);
+  const int64_t ne = (int64_t)2 * N * (1 + m);
+  double *k = ws, *Y = ws + 12 * ny, *g = Y + ny, *hh = g + N;
+  for (int i = 0; i < 12; ++i) {
+    for (int64_t c = 0; c < ny; ++c) {
+      double s = 0.0;
+      for (int j = 0; j < i; ++j) s += dop_a(i + 1, j + 1) * k[j * ny + c];
+      Y[c] = y[c] + h * s;
+    }
+    ext_rhs(kind, N, pr, m, do_ld, ldp, Y, k + i * ny, g, hh);
+  }
+  double e5 = 0.0, e3 = 0.0;
+  for (int64_t c = 0; c < ny; ++c) {
+    double sb = 0.0, s5 = 0.0;
+    for (int i = 0; i < 12; ++i) {
+      sb += DOP_B[i] * k[i * ny + c];
+      s5 += DOP_ER[i] * k[i * ny + c];
+    }
+    ynew[c] = y[c] + h * sb;
+    if (c < ne) {
+      double s3 = sb - DOP_BHH[0] * k[0 * ny + c] - DOP_BHH[1] * k[8 * ny + c] -
+                  DOP_BHH[2] * k[11 * ny + c];
+      double a = fabs(y[c]), b = fabs(ynew[c]);
+      double sk = atol + rtol * (a > b ? a : b);
+      e5 += (s5 / sk) * (s5 / sk);
+      e3 += (s3 / sk) * (s3 / sk);
+    }
+  }
+  double deno = e5 + 0.01 * e3;
+  if (deno <= 0.0) return 0.0;
+  return fabs(h) * e5 * sqrt(1.0 / ((double)ne * deno));
+}
+
 static double *dop853_workspace(int N, int m) {
   const int64_t ny = (int64_t)2 * N * (1 + m) + 1;
-  return (double *)malloc(sizeof(double) * (size_t)(13 * ny + N + (int64_t)N * N));
+  return (double *)malloc(sizeof(double) * (size_t)(14 * ny + N + (int64_t)N * N));
 }
 
 void ora_dop853_step(int kind, int N, const double *pr, double dt, double *x, double *w,
@@ -465,6 +532,10 @@ enum {
   ST_STATUS,     /* status code                                          */
   ST_T_END,      /* time of the last checkpoint reached                  */
   ST_S_DONE,     /* steps performed                                      */
+  ST_H,          /* adaptive: the step the controller proposes next      */
+  ST_REJ,        /* adaptive: the last attempt was rejected (0 / 1)      */
+  ST_NACC,       /* adaptive: accepted steps                             */
+  ST_NREJ,       /* adaptive: rejected steps                             */
   ST_NSCAL
 };
 
@@ -671,6 +742,125 @@ int ora_advance(int kind, int N, const double *pr, double *state, int64_t n, int
                           n_total, K, ldp, thr, early_exit, escape_r2, ORA_INT_YOSHIDA4);
 }
 
+/* Adaptive DOP8(5) (the paper's Functionalities section lists the adaptive
+ * DOP 8(5) solvers, with the error of each step): the checkpoint schedule is
+ * that of the fixed-step driver -- checkpoints at t = s dt for s a multiple
+ * of K or the last step -- and between two checkpoints the step size is
+ * chosen by the error estimate of dop853_attempt with the controller of
+ * Hairer, Norsett and Wanner's DOP853 code (defaults: safety 0.9, step
+ * ratio in [1/3.003, 6], exponent 1/8, no step-size memory):
+ *   accept iff err <= 1;  q = err^(1/8) (three square roots);
+ *   accepted: h <- h / max(1/6, min(1/0.333, q / 0.9)), and not larger than
+ *             the accepted step when the attempt before it was rejected;
+ *   rejected: h <- h / min(1/0.333, q / 0.9).
+ * The first step is dt.  A step that would end within 1.01 h of the next
+ * checkpoint is shortened to end on it exactly.  More than 100000 attempts
+ * between two checkpoints stop the orbit (ORA_ST_STEPFAIL); a non-finite
+ * error or state stops it as ORA_ST_NONFINITE. */
+#define ADAPT_SAFE 0.9
+#define ADAPT_FACC1 (1.0 / 0.333)
+#define ADAPT_FACC2 (1.0 / 6.0)
+#define ADAPT_MAX_ATTEMPTS 100000
+
+int ora_advance_adaptive(int kind, int N, const double *pr, double *state, int64_t n,
+                         int m_s, int n_l, uint32_t ind, double dt, int64_t s_begin,
+                         int64_t s_end, int64_t n_total, int K, double ldp, double thr,
+                         int early_exit, double escape_r2, double rtol, double atol) {
+  int64_t L = ora_state_len(N, m_s, n_l);
+  if (K < 1 || s_begin < 0 || s_end > n_total || s_begin > s_end) return 1;
+  if (!(rtol >= 0.0) || !(atol >= 0.0) || !(rtol + atol > 0.0)) return 3;
+  const int m = m_s + n_l, do_ld = (ind & ORA_IND_LD) != 0;
+  const int64_t ny = (int64_t)2 * N * (1 + m) + (do_ld ? 1 : 0);
+  double *ws = dop853_workspace(N, m);
+  double *y = (double *)malloc(sizeof(double) * (size_t)ny);
+  double *ynew = (double *)malloc(sizeof(double) * (size_t)ny);
+  int rc = 0;
+  for (int64_t o = 0; o < n && !rc; ++o) {
+    double *st = state + o * L;
+    ora_view v = view(st, N, m_s, n_l);
+    if ((int)v.sc[ST_STATUS] != ORA_ST_OK) continue;
+    if ((int64_t)v.sc[ST_S_DONE] != s_begin) {
+      rc = 2;
+      break;
+    }
+    if (!(v.sc[ST_H] > 0.0)) v.sc[ST_H] = dt; /* the first step */
+    for (int i = 0; i < 2 * N; ++i) y[i] = v.x[i];
+    for (int64_t c = 0; c < (int64_t)m * 2 * N; ++c) y[2 * N + c] = v.ws[c];
+    if (do_ld) y[ny - 1] = v.sc[ST_LD];
+    int64_t s = s_begin;
+    while (s < s_end) {
+      int64_t sb = (s / K + 1) * K;
+      if (sb > n_total) sb = n_total;
+      double t = (double)s * dt, tb = (double)sb * dt;
+      int stt = ORA_ST_OK, attempts = 0;
+      while (t < tb) {
+        double h = v.sc[ST_H];
+        int last = 0;
+        if (t + 1.01 * h >= tb) {
+          h = tb - t;
+          last = 1;
+        }
+        double err = dop853_attempt(kind, N, pr, h, y, ynew, m, do_ld, ldp, rtol, atol, ws);
+        if (!isfinite(err) || !all_finite((int)ny, ynew)) {
+          stt = ORA_ST_NONFINITE;
+          break;
+        }
+        if (++attempts > ADAPT_MAX_ATTEMPTS) {
+          stt = ORA_ST_STEPFAIL;
+          break;
+        }
+        double q = sqrt(sqrt(sqrt(err)));
+        if (err <= 1.0) {
+          double fac = q / ADAPT_SAFE;
+          if (fac > ADAPT_FACC1) fac = ADAPT_FACC1;
+          if (fac < ADAPT_FACC2) fac = ADAPT_FACC2;
+          double hnew = h / fac;
+          if (v.sc[ST_REJ] != 0.0 && hnew > h) hnew = h;
+          v.sc[ST_REJ] = 0.0;
+          v.sc[ST_H] = hnew;
+          v.sc[ST_NACC] += 1.0;
+          for (int64_t c = 0; c < ny; ++c) y[c] = ynew[c];
+          t = last ? tb : t + h;
+        } else {
+          double fac = q / ADAPT_SAFE;
+          if (fac > ADAPT_FACC1) fac = ADAPT_FACC1;
+          v.sc[ST_H] = h / fac;
+          v.sc[ST_REJ] = 1.0;
+          v.sc[ST_NREJ] += 1.0;
+        }
+      }
+      for (int i = 0; i < 2 * N; ++i) v.x[i] = y[i];
+      for (int64_t c = 0; c < (int64_t)m * 2 * N; ++c) v.ws[c] = y[2 * N + c];
+      if (do_ld) v.sc[ST_LD] = y[ny - 1];
+      v.sc[ST_S_DONE] = (double)sb;
+      if (stt == ORA_ST_OK) {
+        stt = checkpoint(kind, N, pr, v, m_s, n_l, ind, tb, thr, early_exit, escape_r2);
+        v.sc[ST_T_END] = tb;
+      }
+      if (stt != ORA_ST_OK) {
+        v.sc[ST_STATUS] = stt;
+        break;
+      }
+      /* the checkpoint renormalised the vectors: continue from them */
+      for (int64_t c = 0; c < (int64_t)m * 2 * N; ++c) y[2 * N + c] = v.ws[c];
+      s = sb;
+    }
+  }
+  free(ws);
+  free(y);
+  free(ynew);
+  return rc;
+}
+
+void ora_step_counts(int N, const double *state, int64_t n, int m_s, int n_l,
+                     int64_t *accepted, int64_t *rejected) {
+  int64_t L = ora_state_len(N, m_s, n_l);
+  for (int64_t o = 0; o < n; ++o) {
+    accepted[o] = (int64_t)state[o * L + ST_NACC];
+    rejected[o] = (int64_t)state[o * L + ST_NREJ];
+  }
+}
+
 int ora_finalize(int N, const double *state, int64_t n, int m_s, int n_l, uint32_t ind,
                  int kmax, double thr, double *x_final, double *t_end,
                  int32_t *status, int8_t *label, double *sali_final, double *sali_min,
@@ -681,7 +871,7 @@ int ora_finalize(int N, const double *state, int64_t n, int m_s, int n_l, uint32
     const double *st = state + o * L;
     ora_view v = view((double *)st, N, m_s, n_l);
     int stt = (int)v.sc[ST_STATUS];
-    int bad = (stt == ORA_ST_MASKED || stt == ORA_ST_NONFINITE);
+    int bad = (stt == ORA_ST_MASKED || stt == ORA_ST_NONFINITE || stt == ORA_ST_STEPFAIL);
     double te = v.sc[ST_T_END];
     if (x_final)
       for (int i = 0; i < 2 * N; ++i) x_final[o * 2 * N + i] = v.x[i];
@@ -690,7 +880,7 @@ int ora_finalize(int N, const double *state, int64_t n, int m_s, int n_l, uint32
     if (label) {
       int8_t lb;
       if (stt == ORA_ST_MASKED) lb = -1;
-      else if (stt == ORA_ST_NONFINITE) lb = 3;
+      else if (stt == ORA_ST_NONFINITE || stt == ORA_ST_STEPFAIL) lb = 3;
       else if (stt == ORA_ST_ESCAPED) lb = 2;
       else lb = (v.sc[ST_SALI_MIN] < thr) ? 1 : 0;
       label[o] = lb;

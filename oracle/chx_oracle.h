@@ -57,6 +57,7 @@ extern "C" {
 /* Integrators. */
 #define ORA_INT_YOSHIDA4 0
 #define ORA_INT_DOP853 1
+#define ORA_INT_DOP853_ADAPTIVE 2 /* driver: ora_advance_adaptive */
 
 /* Orbit status codes. */
 #define ORA_ST_OK 0
@@ -64,6 +65,7 @@ extern "C" {
 #define ORA_ST_ESCAPED 2
 #define ORA_ST_NONFINITE 3
 #define ORA_ST_EXITED 4
+#define ORA_ST_STEPFAIL 5 /* adaptive: too many attempts between checkpoints */
 
 /* Potential, gradient and dense Hessian (row-major ndof x ndof). */
 double ora_potential(int kind, int ndof, const double *params, const double *q);
@@ -83,6 +85,9 @@ void ora_step(int kind, int ndof, const double *params, double dt, double *x,
 /* The DOP853 coefficients: nodes c[12], row-major lower-triangular a[12][12]
  * (zeros above the diagonal and where the method has none), weights b[12]. */
 void ora_dop853_tableau(double c[12], double a[144], double b[12]);
+/* Its error estimators: er[12] (eighth minus embedded fifth order) and the
+ * embedded third-order weights bhh[3] on stages 1, 9 and 12. */
+void ora_dop853_error_weights(double er[12], double bhh[3]);
 /* One fixed DOP853 step of size dt of the state x[2N], m tangent vectors
  * w[m][2N] and, if do_ld, the LD M-function *ld (integrand sum |dx_i/dt|^p). */
 void ora_dop853_step(int kind, int ndof, const double *params, double dt, double *x,
@@ -116,6 +121,18 @@ int ora_advance_with(int kind, int ndof, const double *params, double *state, in
                      int64_t s_end, int64_t n_total, int K, double ld_p,
                      double sali_threshold, int early_exit, double escape_r2,
                      int integrator);
+/* The same schedule with the adaptive DOP8(5) step-size control between
+ * checkpoints (relative and absolute tolerances rtol, atol; first step dt).
+ * The error of each attempted step is measured on the state and the
+ * deviation vectors. */
+int ora_advance_adaptive(int kind, int ndof, const double *params, double *state,
+                         int64_t n, int m_s, int n_l, uint32_t indicators, double dt,
+                         int64_t s_begin, int64_t s_end, int64_t n_total, int K,
+                         double ld_p, double sali_threshold, int early_exit,
+                         double escape_r2, double rtol, double atol);
+/* Accepted and rejected step counts of the adaptive driver. */
+void ora_step_counts(int ndof, const double *state, int64_t n, int m_s, int n_l,
+                     int64_t *accepted, int64_t *rejected);
 /* Outputs (any may be NULL): x_final[n][2N], t_end[n], status[n], label[n],
  * sali_final[n], sali_min[n], t_chaos[n], gali[n][kmax-1], lyap[n][n_l],
  * ld[n], energy_err[n], ln_growth[n][m_s]. */

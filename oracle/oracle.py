@@ -29,10 +29,11 @@ IND_LYAP = 4
 IND_LD = 8
 IND_ENERGY = 16
 
-ST_OK, ST_MASKED, ST_ESCAPED, ST_NONFINITE, ST_EXITED = 0, 1, 2, 3, 4
+ST_OK, ST_MASKED, ST_ESCAPED, ST_NONFINITE, ST_EXITED, ST_STEPFAIL = 0, 1, 2, 3, 4, 5
 
 INT_YOSHIDA4 = 0
 INT_DOP853 = 1
+INT_DOP853_ADAPTIVE = 2
 
 _lib = None
 
@@ -65,6 +66,10 @@ def lib():
         L.ora_advance_with.restype = i
         L.ora_advance_with.argtypes = L.ora_advance.argtypes + [i]
         L.ora_dop853_tableau.argtypes = [P, P, P]
+        L.ora_dop853_error_weights.argtypes = [P, P]
+        L.ora_advance_adaptive.restype = i
+        L.ora_advance_adaptive.argtypes = L.ora_advance.argtypes + [d, d]
+        L.ora_step_counts.argtypes = [i, P, i64, i, i, P, P]
         L.ora_dop853_step.argtypes = [i, i, P, d, P, P, i, i, d, P]
         L.ora_finalize.restype = i
         L.ora_finalize.argtypes = [i, P, i64, i, i, u32, i, d] + [P] * 12
@@ -164,6 +169,14 @@ def dop853_tableau():
     return c, a, b
 
 
+def dop853_error_weights():
+    """er[12] (eighth- minus fifth-order weights) and bhh[3] (third-order
+    weights on stages 1, 9, 12) of DOP853's error estimate."""
+    er, bhh = np.zeros(12), np.zeros(3)
+    lib().ora_dop853_error_weights(_p(er), _p(bhh))
+    return er, bhh
+
+
 def dop853_step(sys, dt, x, w=None, nsteps=1, ld=None, ld_p=0.5):
     """Apply nsteps fixed DOP853 steps to a copy of x[2N] (and w[m][2N]; and
     the LD M-function when ld is a number).  Returns x, (x, w), (x, ld) or
@@ -222,6 +235,8 @@ class Run:
     escape_r2: float = 0.0
     m_s: int = field(default=-1)
     integrator: int = INT_YOSHIDA4
+    rtol: float = 1e-10   # adaptive DOP8(5) only
+    atol: float = 1e-10
 
     def __post_init__(self):
         if self.m_s < 0:
@@ -266,6 +281,14 @@ class State:
         def work(lo, hi):
             sub = self.buf[lo:hi]
             assert sub.flags.c_contiguous
+            if run.integrator == INT_DOP853_ADAPTIVE:
+                rc = lib().ora_advance_adaptive(
+                    sys.kind, sys.ndof, _p(pr), _p(sub), hi - lo, run.m_s, run.n_lyap,
+                    run.indicators, run.dt, self.s_done, s_end, self.n_total, run.K, run.ld_p,
+                    run.sali_threshold, int(run.early_exit), run.escape_r2, run.rtol, run.atol)
+                if rc:
+                    raise RuntimeError("ora_advance_adaptive failed (%d)" % rc)
+                return
             rc = lib().ora_advance_with(sys.kind, sys.ndof, _p(pr), _p(sub), hi - lo,
                                         run.m_s, run.n_lyap, run.indicators, run.dt,
                                         self.s_done, s_end, self.n_total, run.K, run.ld_p,
@@ -276,6 +299,14 @@ class State:
 
         _parallel(work, self.n, threads)
         self.s_done = s_end
+
+    def step_counts(self):
+        """Accepted and rejected steps per orbit (adaptive driver)."""
+        acc = np.zeros(self.n, np.int64)
+        rej = np.zeros(self.n, np.int64)
+        lib().ora_step_counts(self.sys.ndof, _p(self.buf), self.n, self.run.m_s,
+                              self.run.n_lyap, _p(acc), _p(rej))
+        return acc, rej
 
     def finalize(self):
         run, sys, n, N2 = self.run, self.sys, self.n, 2 * self.sys.ndof
@@ -310,7 +341,10 @@ def _parallel(fn, n, threads):
 def integrate(sys, x0, run, w0=None, mask=None, threads=1):
     st = State(sys, run, x0, w0, mask)
     st.advance(st.n_total, threads=threads)
-    return st.finalize()
+    out = st.finalize()
+    if run.integrator == INT_DOP853_ADAPTIVE:
+        out["steps_accepted"], out["steps_rejected"] = st.step_counts()
+    return out
 
 
 # --- inputs ----------------------------------------------------------------

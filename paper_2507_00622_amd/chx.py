@@ -20,9 +20,11 @@ OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_INTERNA
 SYS_HENON_HEILES, SYS_FPUT, SYS_QUARTIC, SYS_HARMONIC = 1, 2, 3, 4
 IND_SALI, IND_GALI, IND_LYAP, IND_LD, IND_ENERGY = 1, 2, 4, 8, 16
 PTR_DEVICE = 1
-INT_YOSHIDA4, INT_DOP853 = 0, 1
-_INTEGRATORS = {"yoshida4": INT_YOSHIDA4, "dop853": INT_DOP853}
-ORBIT_OK, ORBIT_MASKED, ORBIT_ESCAPED, ORBIT_NONFINITE, ORBIT_EXITED = range(5)
+INT_YOSHIDA4, INT_DOP853, INT_DOP853_ADAPTIVE = 0, 1, 2
+_INTEGRATORS = {"yoshida4": INT_YOSHIDA4, "dop853": INT_DOP853,
+                "dop853_adaptive": INT_DOP853_ADAPTIVE}
+(ORBIT_OK, ORBIT_MASKED, ORBIT_ESCAPED, ORBIT_NONFINITE, ORBIT_EXITED,
+ ORBIT_STEP_FAILED) = range(6)
 
 # Every function include/chx.h declares.
 EXPORTS = [
@@ -56,11 +58,11 @@ class _Options(C.Structure):
                 ("early_exit", C.c_int32), ("steps_per_launch", C.c_int32),
                 ("seed", C.c_uint64), ("w0", C.c_void_p), ("escape_r2", C.c_double),
                 ("flags", C.c_uint32), ("block_size", C.c_int32), ("stream", C.c_void_p),
-                ("integrator", C.c_int32)]
+                ("integrator", C.c_int32), ("rtol", C.c_double), ("atol", C.c_double)]
 
 
 RESULT_FIELDS = ["x_final", "t_end", "status", "label", "sali_final", "sali_min", "t_chaos",
-                 "gali", "lyap", "ld", "energy_err", "ln_growth"]
+                 "gali", "lyap", "ld", "energy_err", "ln_growth", "steps"]
 
 
 class _Result(C.Structure):
@@ -229,7 +231,7 @@ class _Arrays:
         if self.device:
             tdt = {np.float64: self.torch.float64, np.int32: self.torch.int32,
                    np.int8: self.torch.int8, np.uint8: self.torch.uint8,
-                   np.float32: self.torch.float32}[dtype]
+                   np.float32: self.torch.float32, np.int64: self.torch.int64}[dtype]
             t = self.torch.empty(shape, dtype=tdt, device=self.dev)
             return t, C.c_void_p(t.data_ptr())
         arr = np.empty(shape, dtype=dtype)
@@ -238,8 +240,10 @@ class _Arrays:
 
 def make_options(dt, T, indicators, renorm_every=10, n_lyap=0, gali_kmax=0, ld_p=0.5,
                  sali_threshold=1e-8, early_exit=False, steps_per_launch=0, seed=0,
-                 escape_r2=0.0, block_size=0, integrator=INT_YOSHIDA4):
-    """integrator: INT_YOSHIDA4 / INT_DOP853, or "yoshida4" / "dop853"."""
+                 escape_r2=0.0, block_size=0, integrator=INT_YOSHIDA4, rtol=0.0, atol=0.0):
+    """integrator: INT_YOSHIDA4 / INT_DOP853 / INT_DOP853_ADAPTIVE, or
+    "yoshida4" / "dop853" / "dop853_adaptive"; rtol, atol: tolerances of
+    the adaptive solver (0 and 0: 1e-10 each)."""
     o = _Options()
     lib().chx_options_default(C.byref(o))
     o.dt, o.T, o.indicators = float(dt), float(T), int(indicators)
@@ -248,6 +252,7 @@ def make_options(dt, T, indicators, renorm_every=10, n_lyap=0, gali_kmax=0, ld_p
     o.early_exit, o.steps_per_launch = int(bool(early_exit)), int(steps_per_launch)
     o.seed, o.escape_r2, o.block_size = int(seed) & (2**64 - 1), float(escape_r2), int(block_size)
     o.integrator = _INTEGRATORS[integrator] if isinstance(integrator, str) else int(integrator)
+    o.rtol, o.atol = float(rtol), float(atol)
     return o
 
 
@@ -267,7 +272,8 @@ def _alloc_results(arr, sys, o, n, want):
             "sali_final": ((n,), np.float64), "sali_min": ((n,), np.float64),
             "t_chaos": ((n,), np.float64), "gali": ((n, max(kmax - 1, 0)), np.float64),
             "lyap": ((n, n_l), np.float64), "ld": ((n,), np.float64),
-            "energy_err": ((n,), np.float64), "ln_growth": ((n, m_s), np.float64)}
+            "energy_err": ((n,), np.float64), "ln_growth": ((n, m_s), np.float64),
+            "steps": ((n, 2), np.int64)}
     ind = o.indicators
     avail = {"x_final", "t_end", "status"}
     if ind & IND_SALI:
@@ -282,6 +288,8 @@ def _alloc_results(arr, sys, o, n, want):
         avail.add("energy_err")
     if m_s:
         avail.add("ln_growth")
+    if o.integrator == INT_DOP853_ADAPTIVE:
+        avail.add("steps")
     want = avail if want is None else (set(want) & avail)
     res = _Result()
     out = {}

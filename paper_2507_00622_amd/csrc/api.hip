@@ -113,10 +113,16 @@ chx_status make_plan(const chx_system *sys, const chx_options *opt, Plan *p) {
   if (!(o.block_size == 0 || o.block_size == 64 || o.block_size == 128 || o.block_size == 256))
     return fail(CHX_ERR_INVALID_ARG, "block_size must be 0, 64, 128 or 256");
   if (o.flags & ~1u) return fail(CHX_ERR_INVALID_ARG, "unknown flags 0x%x", o.flags);
-  if (o.integrator != CHX_INT_YOSHIDA4 && o.integrator != CHX_INT_DOP853)
+  if (o.integrator != CHX_INT_YOSHIDA4 && o.integrator != CHX_INT_DOP853 &&
+      o.integrator != CHX_INT_DOP853_ADAPTIVE)
     return fail(CHX_ERR_INVALID_ARG, "unknown integrator %d", o.integrator);
-  if (o.integrator == CHX_INT_DOP853 && sys->kind == CHX_SYS_FPUT)
+  if (o.integrator != CHX_INT_YOSHIDA4 && sys->kind == CHX_SYS_FPUT)
     return fail(CHX_ERR_UNSUPPORTED, "DOP853 is available for the lane-per-orbit systems (Henon-Heiles, quartic, harmonic), not FPUT");
+  if (o.integrator == CHX_INT_DOP853_ADAPTIVE) {
+    if (o.rtol == 0.0 && o.atol == 0.0) o.rtol = o.atol = 1e-10;
+    if (!(o.rtol >= 0.0) || !(o.atol >= 0.0) || !isfinite(o.rtol) || !isfinite(o.atol))
+      return fail(CHX_ERR_INVALID_ARG, "rtol and atol must be finite and >= 0");
+  }
   int m_s = 0;
   if (o.indicators & CHX_IND_SALI) m_s = 2;
   if (kmax > m_s) m_s = kmax;
@@ -242,6 +248,8 @@ chx_status create(const chx_system *sys, const double *x0, const uint8_t *mask, 
   a.thr2 = pl.o.sali_threshold * pl.o.sali_threshold;
   a.escape_r2 = pl.o.escape_r2;
   a.ld_p = pl.o.ld_p;
+  a.rtol = pl.o.rtol;
+  a.atol = pl.o.atol;
   memcpy(a.prm, e->prm, sizeof a.prm);
   if (na > 0) {
     InitArgs ia{};
@@ -294,8 +302,10 @@ chx_status advance(chx_ensemble *e, int64_t s_end) {
     if (a.n > 0) {
       hipError_t he = (e->kind == CHX_SYS_FPUT)
                           ? launch_fput_row(pl.N, pl.M, a, e->stream)
-                      : (pl.o.integrator == CHX_INT_DOP853)
-                          ? launch_lane_rk(e->kind, pl.N, pl.M, a, e->block, e->stream)
+                      : (pl.o.integrator != CHX_INT_YOSHIDA4)
+                          ? launch_lane_rk(e->kind, pl.N, pl.M,
+                                           pl.o.integrator == CHX_INT_DOP853_ADAPTIVE, a,
+                                           e->block, e->stream)
                           : launch_lane(e->kind, pl.N, pl.M, a, e->block, e->stream);
       if (he != hipSuccess) return dev_fail(he, "integration kernel");
     }
@@ -348,7 +358,8 @@ chx_status results(chx_ensemble *e, chx_result *res) {
             {r.lyap, (void **)&d.lyap, sizeof(double) * n * pl.n_l},
             {r.ld, (void **)&d.ld, sizeof(double) * n},
             {r.energy_err, (void **)&d.energy_err, sizeof(double) * n},
-            {r.ln_growth, (void **)&d.ln_growth, sizeof(double) * n * pl.m_s}};
+            {r.ln_growth, (void **)&d.ln_growth, sizeof(double) * n * pl.m_s},
+            {r.steps, (void **)&d.steps, sizeof(int64_t) * n * 2}};
     for (auto &o : outs) {
       *o.dev = nullptr;
       if (o.host && o.bytes) {

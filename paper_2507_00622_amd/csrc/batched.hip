@@ -169,7 +169,15 @@ __device__ int64_t run_crow_pool(const Pool &pl, int64_t left) {
 // Three wavefronts per SIMD: the union of the four pool paths would take 180
 // VGPRs (two wavefronts); held to 168 the compiler spills 6 dwords, all
 // outside the step loops.
+// Orbit states, step counts and queue slots written in one launch are read
+// in the next by wavefronts on other XCDs, whose L2 caches are not coherent
+// with each other.  Each thread therefore starts with an agent-scope fence
+// (stale L2 lines are dropped) and ends with one (its writes reach memory
+// before the launch completes).  Without them, 15 of 40 runs of a mixed
+// ensemble at 50 steps per launch differed from the plain results; with
+// them none of 50 did.
 __global__ void __launch_bounds__(256, 3) batched_kernel(const BatchArgs b) {
+  __threadfence();
   const int wave = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   int p = 0;
   while (p + 1 < b.npool && wave >= b.split[p + 1]) ++p;
@@ -185,6 +193,7 @@ __global__ void __launch_bounds__(256, 3) batched_kernel(const BatchArgs b) {
     case POOL_FPUT8_2: left = run_crow_pool<8>(pl, left); break;
     }
   }
+  __threadfence();
 }
 
 // Between launches: claims past tail0 return to it, and what was pushed in
@@ -196,6 +205,7 @@ __global__ void flip_kernel(const BatchArgs b) {
   const unsigned long long t0 = c[2];
   if (c[0] > t0) c[0] = t0;
   c[2] = c[1];
+  __threadfence();
 }
 
 // Queue of all orbits 0..n-1; head = tail0 = 0, tail = n.

@@ -29,6 +29,10 @@ enum Sc {
   SC_EERR,       // max |H - H0|
   SC_H0,         // H at t = 0
   SC_T_END,      // time of the last checkpoint reached
+  SC_H,          // adaptive: the step the controller proposes next (0: dt)
+  SC_REJ,        // adaptive: 1 if the last attempt was rejected
+  SC_NACC,       // adaptive: accepted steps
+  SC_NREJ,       // adaptive: rejected steps
   NSC
 };
 
@@ -56,6 +60,7 @@ struct StepArgs {
   double thr2;      // SALI threshold squared
   double escape_r2; // 0 = off
   double ld_p;      // LD exponent
+  double rtol, atol; // adaptive DOP8(5) tolerances
   double prm[16];   // system parameters
 };
 
@@ -63,8 +68,8 @@ struct StepArgs {
 hipError_t launch_lane(int sys, int ndof, int M, const StepArgs &a, int block,
                        hipStream_t s);
 bool lane_supported(int sys, int ndof, int M);
-hipError_t launch_lane_rk(int sys, int ndof, int M, const StepArgs &a, int block,
-                          hipStream_t s);
+hipError_t launch_lane_rk(int sys, int ndof, int M, bool adaptive, const StepArgs &a,
+                          int block, hipStream_t s);
 hipError_t launch_fput_row(int ndof, int M, const StepArgs &a, hipStream_t s);
 bool fput_row_supported(int ndof, int M, int n_l, bool sali);
 

@@ -10,13 +10,20 @@ hipError_t launch_lane_harmonic1(int M, const StepArgs &a, int block, hipStream_
 hipError_t launch_lane_harmonic2(int M, const StepArgs &a, int block, hipStream_t s);
 hipError_t launch_lane_harmonic3(int M, const StepArgs &a, int block, hipStream_t s);
 
-hipError_t launch_lane_rk_hh(int M, const StepArgs &a, int block, hipStream_t s);
-hipError_t launch_lane_rk_quartic1(int M, const StepArgs &a, int block, hipStream_t s);
-hipError_t launch_lane_rk_quartic2(int M, const StepArgs &a, int block, hipStream_t s);
-hipError_t launch_lane_rk_quartic3(int M, const StepArgs &a, int block, hipStream_t s);
-hipError_t launch_lane_rk_harmonic1(int M, const StepArgs &a, int block, hipStream_t s);
-hipError_t launch_lane_rk_harmonic2(int M, const StepArgs &a, int block, hipStream_t s);
-hipError_t launch_lane_rk_harmonic3(int M, const StepArgs &a, int block, hipStream_t s);
+hipError_t launch_lane_rk_hh(int M, bool adaptive, const StepArgs &a, int block,
+                            hipStream_t s);
+hipError_t launch_lane_rk_quartic1(int M, bool adaptive, const StepArgs &a, int block,
+                            hipStream_t s);
+hipError_t launch_lane_rk_quartic2(int M, bool adaptive, const StepArgs &a, int block,
+                            hipStream_t s);
+hipError_t launch_lane_rk_quartic3(int M, bool adaptive, const StepArgs &a, int block,
+                            hipStream_t s);
+hipError_t launch_lane_rk_harmonic1(int M, bool adaptive, const StepArgs &a, int block,
+                            hipStream_t s);
+hipError_t launch_lane_rk_harmonic2(int M, bool adaptive, const StepArgs &a, int block,
+                            hipStream_t s);
+hipError_t launch_lane_rk_harmonic3(int M, bool adaptive, const StepArgs &a, int block,
+                            hipStream_t s);
 
 bool lane_supported(int sys, int ndof, int M) {
   if (M < 0 || M > 4 * ndof) return false;
@@ -46,21 +53,21 @@ hipError_t launch_lane(int sys, int ndof, int M, const StepArgs &a, int block,
   return hipErrorInvalidValue;
 }
 
-// The same systems with the DOP853 kernels.
-hipError_t launch_lane_rk(int sys, int ndof, int M, const StepArgs &a, int block,
-                          hipStream_t s) {
+// The same systems with the DOP853 kernels (fixed step or adaptive).
+hipError_t launch_lane_rk(int sys, int ndof, int M, bool adaptive, const StepArgs &a,
+                          int block, hipStream_t s) {
   if (!lane_supported(sys, ndof, M)) return hipErrorInvalidValue;
   if (a.n == 0) return hipSuccess;
   switch (sys) {
-  case SYS_HH: return launch_lane_rk_hh(M, a, block, s);
+  case SYS_HH: return launch_lane_rk_hh(M, adaptive, a, block, s);
   case SYS_QUARTIC:
-    return ndof == 1 ? launch_lane_rk_quartic1(M, a, block, s)
-         : ndof == 2 ? launch_lane_rk_quartic2(M, a, block, s)
-                     : launch_lane_rk_quartic3(M, a, block, s);
+    return ndof == 1 ? launch_lane_rk_quartic1(M, adaptive, a, block, s)
+         : ndof == 2 ? launch_lane_rk_quartic2(M, adaptive, a, block, s)
+                     : launch_lane_rk_quartic3(M, adaptive, a, block, s);
   case SYS_HARMONIC:
-    return ndof == 1 ? launch_lane_rk_harmonic1(M, a, block, s)
-         : ndof == 2 ? launch_lane_rk_harmonic2(M, a, block, s)
-                     : launch_lane_rk_harmonic3(M, a, block, s);
+    return ndof == 1 ? launch_lane_rk_harmonic1(M, adaptive, a, block, s)
+         : ndof == 2 ? launch_lane_rk_harmonic2(M, adaptive, a, block, s)
+                     : launch_lane_rk_harmonic3(M, adaptive, a, block, s);
   }
   return hipErrorInvalidValue;
 }

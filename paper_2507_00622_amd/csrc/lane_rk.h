@@ -74,6 +74,29 @@ constexpr double B[12] = {5.42937341165687622380535766363e-2, 0.0, 0.0, 0.0, 0.0
                           2.01365400804030348374776537501e-1,
                           4.47106157277725905176885569043e-2};
 
+// Error estimators (same sources): ER = eighth-order weights minus those of
+// an embedded fifth-order solution; BHH = weights of an embedded third-order
+// solution on stages 1, 9 and 12.
+constexpr double ER[12] = {0.1312004499419488073250102996e-01, 0.0, 0.0, 0.0, 0.0,
+                           -0.1225156446376204440720569753e+01,
+                           -0.4957589496572501915214079952,
+                           0.1664377182454986536961530415e+01,
+                           -0.3503288487499736816886487290,
+                           0.3341791187130174790297318841,
+                           0.8192320648511571246570742613e-01,
+                           -0.2235530786388629525884427845e-01};
+constexpr double BHH1 = 0.244094488188976377952755905512;
+constexpr double BHH2 = 0.733846688281611857341361741547;
+constexpr double BHH3 = 0.220588235294117647058823529412e-01;
+
+// Step-size controller of Hairer, Norsett and Wanner's DOP853 code with its
+// defaults: safety factor, bounds of h_old / h_new, at most 100000
+// attempts between two checkpoints.
+constexpr double SAFE = 0.9;
+constexpr double FACC1 = 1.0 / 0.333;
+constexpr double FACC2 = 1.0 / 6.0;
+constexpr int MAX_ATTEMPTS = 100000;
+
 template <int I, int E, class Fn>
 __device__ __forceinline__ void static_for(Fn &&f) {
   if constexpr (I < E) {
@@ -89,6 +112,15 @@ __device__ __forceinline__ double stage_sum(const double (&k)[12][D], int c) {
   static_for<0, I>([&](auto jc) {
     constexpr int J = decltype(jc)::value;
     if constexpr (A[I][J] != 0.0) s = __builtin_fma(A[I][J], k[J][c], s);
+  });
+  return s;
+}
+template <int D>
+__device__ __forceinline__ double err5_sum(const double (&k)[12][D], int c) {
+  double s = 0.0;
+  static_for<0, 12>([&](auto jc) {
+    constexpr int J = decltype(jc)::value;
+    if constexpr (ER[J] != 0.0) s = __builtin_fma(ER[J], k[J][c], s);
   });
   return s;
 }
@@ -176,6 +208,105 @@ struct RKOrbit : LaneOrbit<S, M, GP, -1> {
       __builtin_amdgcn_sched_barrier(0);
     }
   }
+
+  // Error terms of one component: k holds h-scaled stage derivatives, y the
+  // start value, yn the end value.  e5 += (sum_i er_i k_i / sk)^2,
+  // e3 += ((sum_i b_i k_i - bhh . k_{1,9,12}) / sk)^2 with
+  // sk = atol + rtol max(|y|, |yn|).
+  template <int D2>
+  __device__ __forceinline__ static void err_terms(const double (&k)[12][D2], int c, double y,
+                                                   double yn, double sb, double rtol,
+                                                   double atol, double &e5, double &e3) {
+    const double sk = __builtin_fma(rtol, __builtin_fmax(__builtin_fabs(y), __builtin_fabs(yn)),
+                                    atol);
+    const double r5 = dop853::err5_sum(k, c) / sk;
+    const double s3 = sb - dop853::BHH1 * k[0][c] - dop853::BHH2 * k[8][c] -
+                      dop853::BHH3 * k[11][c];
+    const double r3 = s3 / sk;
+    e5 = __builtin_fma(r5, r5, e5);
+    e3 = __builtin_fma(r3, r3, e3);
+  }
+
+  // One attempted step of size h for the adaptive solver: the new state in
+  // xn, the new LD in ldn, the new vectors in LDS (component c of vector v at
+  // wn[(v D + c) * stride]); returns DOP853's scaled error estimate over the
+  // state and the vectors (the LD is left out of it):
+  //   err = e5 / sqrt(n (e5 + 0.01 e3)) with the sums of err_terms over the
+  //   n = 2N (1 + M) components, which equals |h| e5' / sqrt(n (e5' +
+  //   0.01 e3')) for the sums e5', e3' of unscaled derivatives.
+  __device__ __forceinline__ double rk_attempt(const StepArgs &a, double h, bool do_ld,
+                                               double *qs, double *wn, int stride,
+                                               double (&xn)[D], double &ldn) {
+    double e5 = 0.0, e3 = 0.0;
+    {
+      double k[12][D];
+      double g = 0.0;
+      dop853::static_for<0, 12>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        double Y[D], F[N];
+#pragma unroll
+        for (int c = 0; c < D; ++c) Y[c] = x[c] + dop853::stage_sum<I>(k, c);
+        if constexpr (M > 0) {
+#pragma unroll
+          for (int r = 0; r < N; ++r) qs[(I * N + r) * stride] = Y[r];
+        }
+        S::force(Y, F, a.prm);
+        if constexpr (dop853::B[I] != 0.0) {
+          if (do_ld) {
+            double gi = 0.0;
+#pragma unroll
+            for (int r = 0; r < N; ++r) gi += this->ld_term(a, Y[N + r]) + this->ld_term(a, F[r]);
+            g = __builtin_fma(dop853::B[I], gi, g);
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+          k[I][r] = h * Y[N + r];
+          k[I][N + r] = -h * F[r];
+        }
+      });
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const double sb = dop853::final_sum(k, c);
+        xn[c] = x[c] + sb;
+        err_terms(k, c, x[c], xn[c], sb, a.rtol, a.atol, e5, e3);
+      }
+      ldn = do_ld ? __builtin_fma(h, g, ld) : ld;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+      double k[12][D];
+      dop853::static_for<0, 12>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        double Y[D], Hs[S::NH], q[N];
+#pragma unroll
+        for (int r = 0; r < N; ++r) q[r] = qs[(I * N + r) * stride];
+#pragma unroll
+        for (int c = 0; c < D; ++c) Y[c] = w[v][c] + dop853::stage_sum<I>(k, c);
+        S::hess_scaled(q, h, Hs, a.prm);
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+          double s = 0.0;
+#pragma unroll
+          for (int j = 0; j < N; ++j) s = __builtin_fma(Hs[hidx(N, r, j)], Y[j], s);
+          k[I][r] = h * Y[N + r];
+          k[I][N + r] = -s;
+        }
+      });
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const double sb = dop853::final_sum(k, c);
+        const double yn = w[v][c] + sb;
+        wn[(v * D + c) * stride] = yn;
+        err_terms(k, c, w[v][c], yn, sb, a.rtol, a.atol, e5, e3);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    const double deno = __builtin_fma(0.01, e3, e5);
+    if (!(deno > 0.0)) return deno == 0.0 ? 0.0 : deno;  // NaN stays NaN
+    return e5 / sqrt((double)(D * (1 + M)) * deno);
+  }
 };
 
 // Dynamic LDS of the DOP853 lane kernels: 12 N doubles per thread.
@@ -205,17 +336,126 @@ __global__ void __launch_bounds__(256) lane_rk_kernel(const StepArgs a) {
   o.store(a, ob);
 }
 
-template <class S, int M>
+// The adaptive DOP8(5) solver: the checkpoint schedule of the fixed-step
+// kernels (t = s dt for s a multiple of K or the last step); between two
+// checkpoints each lane takes its own steps, sized by the error estimate of
+// rk_attempt and the controller of Hairer-Norsett-Wanner's DOP853 (accept
+// iff err <= 1; q = err^(1/8) by three square roots; accepted:
+// h /= max(1/6, min(1/0.333, q / 0.9)), not growing right after a
+// rejection; rejected: h /= min(1/0.333, q / 0.9)).  A step that would end
+// within 1.01 h of the checkpoint ends on it exactly.  The lanes of a
+// wavefront run their step loops independently (exec-masked) and meet at
+// each checkpoint.  Dynamic LDS per thread: the 12 N stage positions, then
+// the M D components of the attempted vectors.
+template <class S, int M, bool GP>
+__global__ void __launch_bounds__(256) lane_rka_kernel(const StepArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  if (a.st[i] != CHX_ORBIT_OK) return;
+  constexpr int N = S::N, D = 2 * N;
+  RKOrbit<S, M, GP> o;
+  o.load(a, i);
+  const int64_t P = a.pitch;
+  double h = a.sc[SC_H * P + i];
+  if (!(h > 0.0)) h = a.dt;  // the first step
+  bool rej = a.sc[SC_REJ * P + i] != 0.0;
+  double nacc = a.sc[SC_NACC * P + i], nrej = a.sc[SC_NREJ * P + i];
+  const int stride = blockDim.x;
+  double *qs = lane_rk_lds + threadIdx.x;
+  double *wn = lane_rk_lds + (size_t)12 * N * stride + threadIdx.x;
+  const bool do_ld = (a.ind & CHX_IND_LD) != 0;
+  int64_t s = a.s_begin;
+  const int64_t K = a.K;
+  while (s < a.s_end) {
+    int64_t next = (s / K + 1) * K;
+    if (next > a.n_total) next = a.n_total;
+    double t = (double)s * a.dt;
+    const double tb = (double)next * a.dt;
+    int attempts = 0, fail = CHX_ORBIT_OK;
+    while (t < tb) {
+      double hh = h;
+      bool last = false;
+      if (t + 1.01 * hh >= tb) {
+        hh = tb - t;
+        last = true;
+      }
+      double xn[D], ldn;
+      const double err = o.rk_attempt(a, hh, do_ld, qs, wn, stride, xn, ldn);
+      bool finite = __builtin_isfinite(err) && __builtin_isfinite(ldn);
+#pragma unroll
+      for (int c = 0; c < D; ++c) finite = finite && __builtin_isfinite(xn[c]);
+      if (!finite) {
+        fail = CHX_ORBIT_NONFINITE;
+        break;
+      }
+      if (++attempts > dop853::MAX_ATTEMPTS) {
+        fail = CHX_ORBIT_STEP_FAILED;
+        break;
+      }
+      const double q = sqrt(sqrt(sqrt(err)));
+      double fac = q / dop853::SAFE;
+      if (fac > dop853::FACC1) fac = dop853::FACC1;
+      if (err <= 1.0) {
+        if (fac < dop853::FACC2) fac = dop853::FACC2;
+        double hnew = hh / fac;
+        if (rej && hnew > hh) hnew = hh;
+        rej = false;
+        h = hnew;
+        nacc += 1.0;
+#pragma unroll
+        for (int c = 0; c < D; ++c) o.x[c] = xn[c];
+#pragma unroll
+        for (int v = 0; v < M; ++v)
+#pragma unroll
+          for (int c = 0; c < D; ++c) o.w[v][c] = wn[(v * D + c) * stride];
+        o.ld = ldn;
+        t = last ? tb : t + hh;
+      } else {
+        h = hh / fac;
+        rej = true;
+        nrej += 1.0;
+      }
+    }
+    if (fail != CHX_ORBIT_OK) {
+      o.st = fail;
+      break;
+    }
+    s = next;
+    if (!o.checkpoint(a, tb)) break;
+  }
+  int64_t ob = i;
+  asm volatile("" : "+v"(ob));
+  o.store(a, ob);
+  a.sc[SC_H * P + ob] = h;
+  a.sc[SC_REJ * P + ob] = rej ? 1.0 : 0.0;
+  a.sc[SC_NACC * P + ob] = nacc;
+  a.sc[SC_NREJ * P + ob] = nrej;
+}
+
+// Launch the fixed-step (ADAPT = false) or adaptive (true) kernel with M
+// vectors; the two families are instantiated in separate source files.
+template <class S, int M, bool ADAPT>
 struct LaneRKDispatch {
   static hipError_t go(int m, const StepArgs &a, int block, hipStream_t s) {
+    constexpr bool adaptive = ADAPT;
     if (m == M) {
       const bool gp = (a.ind & CHX_IND_LD) && a.ld_p != 0.5;
-      // at most 64 KB of stage positions per block (the 3-dof kernels run
-      // 128-thread blocks)
-      if (M > 0)
-        while (block > 64 && sizeof(double) * 12 * S::N * (size_t)block > 65536) block /= 2;
+      // LDS per thread: stage positions, and for the adaptive solver the
+      // attempted vectors; at most 64 KB per block (smaller blocks where
+      // needed)
+      const size_t per = M > 0 ? sizeof(double) * (12 * S::N + (adaptive ? M * 2 * S::N : 0)) : 0;
+      while (block > 64 && per * (size_t)block > 65536) block /= 2;
       const int64_t grid = (a.n + block - 1) / block;
-      const size_t lds = M > 0 ? sizeof(double) * 12 * S::N * (size_t)block : 0;
+      const size_t lds = per * (size_t)block;
+      if constexpr (ADAPT) {
+        if (gp)
+          hipLaunchKernelGGL((lane_rka_kernel<S, M, true>), dim3((unsigned)grid), dim3(block),
+                             lds, s, a);
+        else
+          hipLaunchKernelGGL((lane_rka_kernel<S, M, false>), dim3((unsigned)grid), dim3(block),
+                             lds, s, a);
+        return hipGetLastError();
+      }
       if (gp)
         hipLaunchKernelGGL((lane_rk_kernel<S, M, true>), dim3((unsigned)grid), dim3(block), lds,
                            s, a);
@@ -224,11 +464,11 @@ struct LaneRKDispatch {
                            s, a);
       return hipGetLastError();
     }
-    return LaneRKDispatch<S, M - 1>::go(m, a, block, s);
+    return LaneRKDispatch<S, M - 1, ADAPT>::go(m, a, block, s);
   }
 };
-template <class S>
-struct LaneRKDispatch<S, -1> {
+template <class S, bool ADAPT>
+struct LaneRKDispatch<S, -1, ADAPT> {
   static hipError_t go(int, const StepArgs &, int, hipStream_t) { return hipErrorInvalidValue; }
 };
 

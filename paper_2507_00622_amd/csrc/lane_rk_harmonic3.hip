@@ -1,9 +1,13 @@
-// DOP853 lane-per-orbit kernels for 3 uncoupled harmonic oscillator(s):
-// up to 12 deviation vectors.
+// DOP853 lane-per-orbit kernels (fixed step) for 3 uncoupled harmonic
+// oscillator(s): up to 12 deviation vectors.
 #include "lane_rk.h"
 
 namespace chx {
-hipError_t launch_lane_rk_harmonic3(int M, const StepArgs &a, int block, hipStream_t s) {
-  return LaneRKDispatch<SysHarmonic<3>, 12>::go(M, a, block, s);
+hipError_t launch_lane_rka_harmonic3(int M, const StepArgs &a, int block, hipStream_t s);
+
+hipError_t launch_lane_rk_harmonic3(int M, bool adaptive, const StepArgs &a, int block,
+                                    hipStream_t s) {
+  return adaptive ? launch_lane_rka_harmonic3(M, a, block, s)
+                  : LaneRKDispatch<SysHarmonic<3>, 12, false>::go(M, a, block, s);
 }
 }  // namespace chx

@@ -133,6 +133,10 @@ __global__ void init_kernel(StepArgs a, InitArgs ia) {
   a.sc[SC_EERR * P + i] = 0.0;
   a.sc[SC_H0 * P + i] = H0;
   a.sc[SC_T_END * P + i] = 0.0;
+  a.sc[SC_H * P + i] = 0.0;
+  a.sc[SC_REJ * P + i] = 0.0;
+  a.sc[SC_NACC * P + i] = 0.0;
+  a.sc[SC_NREJ * P + i] = 0.0;
   a.st[i] = finite ? CHX_ORBIT_OK : CHX_ORBIT_NONFINITE;
 }
 
@@ -143,7 +147,7 @@ __global__ void finalize_kernel(StepArgs a, OutArgs o, int N, double *gscratch) 
   const int D = 2 * N;
   const int64_t P = a.pitch, j = o.idx[i];
   const int st = a.st[i];
-  const bool bad = (st == CHX_ORBIT_NONFINITE);
+  const bool bad = (st == CHX_ORBIT_NONFINITE || st == CHX_ORBIT_STEP_FAILED);
   const double te = a.sc[SC_T_END * P + i];
   const chx_result &r = o.r;
   if (r.x_final)
@@ -153,7 +157,7 @@ __global__ void finalize_kernel(StepArgs a, OutArgs o, int N, double *gscratch) 
   const double smin = sqrt(a.sc[SC_SALI_MIN2 * P + i]);
   if (r.label) {
     int8_t lb;
-    if (st == CHX_ORBIT_NONFINITE) lb = 3;
+    if (st == CHX_ORBIT_NONFINITE || st == CHX_ORBIT_STEP_FAILED) lb = 3;
     else if (st == CHX_ORBIT_ESCAPED) lb = 2;
     else lb = (o.sali && smin < o.thr) ? 1 : 0;
     r.label[j] = lb;
@@ -163,6 +167,10 @@ __global__ void finalize_kernel(StepArgs a, OutArgs o, int N, double *gscratch) 
   if (r.t_chaos) r.t_chaos[j] = bad ? NAN : a.sc[SC_T_CHAOS * P + i];
   if (r.ld) r.ld[j] = bad ? NAN : a.sc[SC_LD * P + i];
   if (r.energy_err) r.energy_err[j] = bad ? NAN : a.sc[SC_EERR * P + i];
+  if (r.steps) {
+    r.steps[2 * j] = (int64_t)a.sc[SC_NACC * P + i];
+    r.steps[2 * j + 1] = (int64_t)a.sc[SC_NREJ * P + i];
+  }
   const double LN2 = 0.69314718055994530942;
   if (r.ln_growth)
     for (int v = 0; v < a.m_s; ++v)
@@ -225,6 +233,7 @@ __global__ void masked_fill_kernel(const double *x0, const uint8_t *mask, int64_
   if (r.t_chaos) r.t_chaos[j] = NAN;
   if (r.ld) r.ld[j] = NAN;
   if (r.energy_err) r.energy_err[j] = NAN;
+  if (r.steps) r.steps[2 * j] = r.steps[2 * j + 1] = 0;
   if (r.ln_growth)
     for (int v = 0; v < m_s; ++v) r.ln_growth[j * m_s + v] = NAN;
   if (r.lyap)

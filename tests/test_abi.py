@@ -32,8 +32,8 @@ def test_exports_every_declared_function():
 def test_struct_layouts_match_header():
     L = chx.lib()
     assert L.chx_struct_size(0) == C.sizeof(chx._System) == 24
-    assert L.chx_struct_size(1) == C.sizeof(chx._Options) == 104
-    assert L.chx_struct_size(2) == C.sizeof(chx._Result) == 12 * 8
+    assert L.chx_struct_size(1) == C.sizeof(chx._Options) == 120
+    assert L.chx_struct_size(2) == C.sizeof(chx._Result) == 13 * 8
     assert L.chx_struct_size(3) == C.sizeof(chx._BatchItem) == 64
     assert L.chx_struct_size(4) == C.sizeof(chx._BatchStats)
     assert L.chx_struct_size(5) == C.sizeof(chx._GateTrainCfg) == 40
@@ -87,6 +87,8 @@ def test_bad_systems():
     (dict(indicators=chx.IND_SALI, escape_r2=-1.0), "escape_r2"),
     (dict(indicators=chx.IND_SALI, sali_threshold=-1.0), "sali_threshold"),
     (dict(indicators=chx.IND_SALI, integrator=7), "integrator"),
+    (dict(indicators=chx.IND_SALI, integrator="dop853_adaptive", rtol=-1.0), "rtol"),
+    (dict(indicators=chx.IND_SALI, integrator="dop853_adaptive", atol=float("inf")), "atol"),
 ])
 def test_bad_options(kw, msg):
     with pytest.raises(chx.ChxError) as e:
@@ -95,10 +97,11 @@ def test_bad_options(kw, msg):
 
 
 def test_dop853_is_for_lane_systems_only():
-    with pytest.raises(chx.ChxError) as e:
-        chx.integrate_ensemble(P.fput(4), np.zeros((2, 8)), dt=0.01, T=1.0,
-                               indicators=chx.IND_SALI, integrator="dop853")
-    assert e.value.status == chx.ERR_UNSUPPORTED and "DOP853" in str(e.value)
+    for integ in ("dop853", "dop853_adaptive"):
+        with pytest.raises(chx.ChxError) as e:
+            chx.integrate_ensemble(P.fput(4), np.zeros((2, 8)), dt=0.01, T=1.0,
+                                   indicators=chx.IND_SALI, integrator=integ)
+        assert e.value.status == chx.ERR_UNSUPPORTED and "DOP853" in str(e.value)
     with pytest.raises(chx.ChxError) as e:
         chx.integrate_batched([dict(sys=P.henon_heiles(), x0=hh_x0(4), dt=0.01, T=1.0)],
                               indicators=chx.IND_SALI, integrator="dop853")

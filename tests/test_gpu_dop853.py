@@ -268,3 +268,157 @@ def test_dop853_full_hh_grid_sampled(env):
     assert np.max(np.abs(g["lyap"][idx] - o["lyap"])) < 1e-9
     assert log_err(g["sali_min"][idx], o["sali_min"]) < 1e-9
     assert np.all(g["status"][act] == 0)
+
+
+# --- adaptive DOP8(5) ----------------------------------------------------------
+#
+# Both sides choose their own step sequences.  Where an orbit's accepted and
+# rejected step counts agree the two took the same decisions (the controller
+# works on the same error estimate up to rounding; the step sizes themselves
+# differ in low-order bits, because the error estimate is a sum with heavy
+# cancellation) and the tolerances above apply, except for the LD (below);
+# a decision can flip only where an error estimate lands within rounding of
+# 1, which the tests require to be rare.
+
+def run_adaptive(env, sys_, x0, mask=None, w0=None, **kw):
+    return run_gpu_int(env, sys_, x0, mask, w0, integrator="dop853_adaptive", **kw)
+
+
+def run_gpu_int(env, sys_, x0, mask=None, w0=None, **kw):
+    torch, P, _ = env
+    dev = torch.device("cuda:0")
+    t = lambda a: None if a is None else torch.as_tensor(a, device=dev)
+    out = P.integrate_ensemble(sys_, t(x0), mask=t(mask), w0=t(w0), **kw)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def adaptive_oracle(O, **kw):
+    tol = kw.pop("rtol")
+    kw.pop("atol", None)
+    K = kw.pop("renorm_every", 10)
+    return O.Run(integrator=O.INT_DOP853_ADAPTIVE, rtol=tol, atol=tol, K=K, **kw)
+
+
+def test_adaptive_hh_against_oracle(env):
+    torch, P, O = env
+    for E, T in ((0.125, 100.0), (1.0 / 6.0, 50.0)):
+        say(f"case: adaptive HH E={E:.6f} 24x24, all indicators, T={T}, tol 1e-10")
+        x0, mask = O.hh_grid(E, 24, 24)
+        w0 = S.deviation_vectors(7, len(x0), 2, 4)
+        kw = dict(dt=0.1, T=T, indicators=ALL, gali_kmax=2, n_lyap=4, escape_r2=4.0,
+                  rtol=1e-10, atol=1e-10)
+        g = run_adaptive(env, P.henon_heiles(), x0, mask, w0, **kw)
+        o = O.integrate(O.henon_heiles(), x0, adaptive_oracle(O, **kw), w0=w0, mask=mask,
+                        threads=8)
+        act = mask == 1
+        assert np.array_equal(g["status"], o["status"])
+        ok = act & (o["status"] == 0)
+        same = ok & (g["steps"][:, 0] == o["steps_accepted"]) & (g["steps"][:, 1] == o["steps_rejected"])
+        say("  orbits", ok.sum(), "same step counts", same.sum(), "steps/orbit",
+            g["steps"][ok, 0].mean(), "rejected", g["steps"][ok, 1].sum())
+        assert same.sum() >= 0.99 * ok.sum()
+        assert np.array_equal(g["t_end"][act], o["t_end"][act])
+        le = np.max(np.abs(g["lyap"][same] - o["lyap"][same]))
+        say("  sali", log_err(g["sali_min"][same], o["sali_min"][same]), "lyap", le)
+        assert log_err(g["sali_min"][same], o["sali_min"][same]) < 1e-6
+        assert log_err(g["gali"][same, 0], o["gali"][same, 0], floor=1e-8) < 1e-6
+        assert le < 1e-6
+        # The LD component is outside the error control, and its integrand's
+        # square-root cusps make the quadrature depend on where the stages
+        # fall: on the oracle alone, changing rtol by a relative 1e-9 moves
+        # the LD of this grid by up to 1.1e-4 (relative).  Compared at 1e-3.
+        assert np.max(np.abs(g["ld"][same] / o["ld"][same] - 1)) < 1e-3
+        assert np.max(np.abs(g["energy_err"][same] - o["energy_err"][same])) < 1e-12
+
+
+def test_adaptive_regular_state_T200(env):
+    torch, P, O = env
+    say("case: adaptive HH E=0.125 32x32, SALI+LD+energy, T=200, tol 1e-11")
+    x0, mask = O.hh_grid(0.125, 32, 32)
+    w0 = S.deviation_vectors(1001, len(x0), 2, 4)
+    kw = dict(dt=0.1, T=200.0, indicators=O.IND_SALI | O.IND_LD | O.IND_ENERGY,
+              rtol=1e-11, atol=1e-11)
+    g = run_adaptive(env, P.henon_heiles(), x0, mask, w0, **kw)
+    o = O.integrate(O.henon_heiles(), x0, adaptive_oracle(O, **kw), w0=w0, mask=mask,
+                    threads=8)
+    reg = golden_labels() == 0
+    same = reg & (g["steps"][:, 0] == o["steps_accepted"]) & (g["steps"][:, 1] == o["steps_rejected"])
+    assert same.sum() >= 0.99 * reg.sum()
+    err = state_err(g["x_final"][same], o["x_final"][same])
+    say("  max regular-orbit state error:", err.max())
+    assert err.max() < 1e-9
+    assert np.array_equal(g["label"][reg], o["label"][reg])
+
+
+def test_adaptive_edges(env):
+    torch, P, O = env
+    say("case: adaptive ragged n, K=7, T not a multiple of K dt, status codes")
+    rng = np.random.default_rng(5)
+    n = 333
+    x0, mask = O.hh_points(0.125, rng.uniform(-0.4, 0.7, n), rng.uniform(-0.45, 0.45, n))
+    x0[3] = [np.nan, 0, 0, 0]
+    mask[3] = 1
+    w0 = S.deviation_vectors(3, n, 2, 4)
+    kw = dict(dt=0.01, T=2.53, indicators=ALL, gali_kmax=2, n_lyap=4, renorm_every=7,
+              rtol=1e-9, atol=1e-12)
+    g = run_adaptive(env, P.henon_heiles(), x0, mask, w0, **kw)
+    run = O.Run(dt=0.01, T=2.53, indicators=ALL, gali_kmax=2, n_lyap=4, K=7,
+                integrator=O.INT_DOP853_ADAPTIVE, rtol=1e-9, atol=1e-12)
+    o = O.integrate(O.henon_heiles(), x0, run, w0=w0, mask=mask)
+    act = mask == 1
+    assert g["status"][3] == 3 and o["status"][3] == 3
+    assert np.array_equal(g["status"], o["status"])
+    assert np.array_equal(g["t_end"][act], o["t_end"][act])
+    ok = act & (o["status"] == 0)
+    same = ok & (g["steps"][:, 0] == o["steps_accepted"]) & (g["steps"][:, 1] == o["steps_rejected"])
+    assert same.sum() >= 0.99 * ok.sum()
+    assert np.max(state_err(g["x_final"][same], o["x_final"][same])) < 1e-11
+    assert np.all(g["steps"][~act] == 0)
+    # an impossible tolerance: the attempt limit stops the orbit (status 5)
+    hs = P.harmonic([1.0])
+    gs = run_adaptive(env, hs, np.array([[1.0, 0.0], [0.5, 0.2]]), None, None, dt=0.1, T=1.0,
+                      indicators=O.IND_ENERGY, rtol=1e-40, atol=1e-40)
+    assert list(gs["status"]) == [5, 5]
+
+
+def test_adaptive_resume_bitwise_and_block_sizes(env):
+    torch, P, O = env
+    say("case: adaptive resume and block sizes")
+    x0, mask = O.hh_grid(0.125, 16, 16)
+    w0 = S.deviation_vectors(5, len(x0), 2, 4)
+    dev = torch.device("cuda:0")
+    kw = dict(dt=0.05, T=30.0, indicators=ALL, gali_kmax=2, n_lyap=4, renorm_every=20,
+              integrator="dop853_adaptive", rtol=1e-9, atol=1e-9)
+    ref = run_gpu_int(env, P.henon_heiles(), x0, mask, w0, **kw)
+    e = P.Ensemble(P.henon_heiles(), torch.as_tensor(x0, device=dev),
+                   mask=torch.as_tensor(mask, device=dev), w0=torch.as_tensor(w0, device=dev),
+                   steps_per_launch=60, **kw)
+    for s in (200, 420, 600):
+        e.advance(s)
+    r = {k: v.cpu().numpy() for k, v in e.results().items()}
+    e.close()
+    for k in ref:
+        assert np.array_equal(ref[k], r[k], equal_nan=True), k
+    for block in (64, 128):
+        b = run_gpu_int(env, P.henon_heiles(), x0, mask, w0, block_size=block, **kw)
+        for k in ref:
+            assert np.array_equal(ref[k], b[k], equal_nan=True), (block, k)
+
+
+@pytest.mark.parametrize("N", [2, 3])
+def test_adaptive_quartic(env, N):
+    torch, P, O = env
+    say(f"case: adaptive quartic N={N}")
+    so, sg = O.quartic(N, 0.1), P.quartic(N, 0.1)
+    x0 = O.quartic_ic(so, S.quartic_draws(31, 200, N))
+    w0 = S.deviation_vectors(4, len(x0), 2, 2 * N)
+    kw = dict(dt=0.1, T=50.0, indicators=ALL, gali_kmax=2, n_lyap=2 * N, rtol=1e-10,
+              atol=1e-10)
+    g = run_adaptive(env, sg, x0, None, w0, **kw)
+    o = O.integrate(so, x0, adaptive_oracle(O, **kw), w0=w0)
+    same = (g["steps"][:, 0] == o["steps_accepted"]) & (g["steps"][:, 1] == o["steps_rejected"])
+    say("  same step counts", same.sum(), "of", len(same))
+    assert same.sum() >= 0.99 * len(same)
+    assert np.max(state_err(g["x_final"][same], o["x_final"][same])) < 1e-9
+    assert np.max(np.abs(g["lyap"][same] - o["lyap"][same])) < 1e-6

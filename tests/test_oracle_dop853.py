@@ -220,3 +220,126 @@ def test_lyapunov_sum_and_energy(O):
     # method's local truncation error
     assert abs(o["lyap"][0].sum()) < 1e-10
     assert o["energy_err"][0] < 1e-12
+
+
+# --- the adaptive DOP8(5) driver ---------------------------------------------
+
+def plain_residuals(weights, a, pmax):
+    """sum_i w_i Phi_i(t) for every rooted tree t up to pmax nodes."""
+    mp.mp.dps = 60
+    s = len(weights)
+    A = [[mp.mpf(float(a[i][j])) for j in range(s)] for i in range(s)]
+    W = [mp.mpf(float(v)) for v in weights]
+    memo = {}
+
+    def phi(t):
+        if t in memo:
+            return memo[t]
+        v = [mp.mpf(1)] * s
+        for u in t:
+            pu = phi(u)
+            for i in range(s):
+                v[i] *= mp.fsum(A[i][j] * pu[j] for j in range(i))
+        memo[t] = v
+        return v
+
+    out = []
+    for n in range(1, pmax + 1):
+        for t in rooted_trees(n):
+            out.append((n, t, mp.fsum(W[i] * phi(t)[i] for i in range(s))))
+    return out
+
+
+def test_error_estimators_are_embedded_fifth_and_third_order(O):
+    c, a, b = O.dop853_tableau()
+    er, bhh = O.dop853_error_weights()
+    # er = b - bhat5 of a fifth-order solution: it annihilates every tree up
+    # to order 5 and not all trees of order 6
+    res = plain_residuals(er, a, 6)
+    assert max(abs(float(r)) for n, _, r in res if n <= 5) < 1e-13
+    assert max(abs(float(r)) for n, _, r in res if n == 6) > 1e-5
+    # bhh on stages 1, 9, 12 is a third-order solution: order conditions up
+    # to 3 hold, some of order 4 do not
+    w3 = np.zeros(12)
+    w3[0], w3[8], w3[11] = bhh
+    res = plain_residuals(w3, a, 4)
+    assert max(abs(float(r) - 1.0 / density(t)) for n, t, r in res if n <= 3) < 1e-14
+    assert max(abs(float(r) - 1.0 / density(t)) for n, t, r in res if n == 4) > 1e-3
+    # the error weights use the solution's stages only
+    assert np.all((er != 0) == (b != 0))
+
+
+def adaptive_run(O, T, tol, dt=0.1, K=10, ind=None, n_lyap=0):
+    return O.Run(dt=dt, T=T, indicators=O.IND_ENERGY if ind is None else ind, K=K,
+                 n_lyap=n_lyap, integrator=O.INT_DOP853_ADAPTIVE, rtol=tol, atol=tol)
+
+
+def test_adaptive_error_follows_the_tolerance(O):
+    s = O.henon_heiles()
+    x0 = np.array([[0.0, 0.1, 0.45, 0.05], [0.0, -0.25, 0.4330127018922193, 0.0]])
+    ref = np.array([solve_ivp(hh_rhs, (0, 100.0), x, method="DOP853", rtol=1e-13,
+                              atol=1e-13).y[:, -1] for x in x0])
+    errs, steps = [], []
+    for tol in (1e-6, 1e-8, 1e-10):
+        o = O.integrate(s, x0, adaptive_run(O, 100.0, tol))
+        assert np.all(o["status"] == 0) and np.all(o["t_end"] == 100.0)
+        errs.append(np.max(np.abs(o["x_final"] - ref)))
+        steps.append(o["steps_accepted"].sum())
+        assert errs[-1] < 1e3 * tol
+    assert errs[0] > errs[1] > errs[2]
+    assert steps[0] < steps[1] < steps[2]
+
+
+def test_adaptive_step_count_scales_like_tol_to_minus_one_eighth(O):
+    # one checkpoint interval over the whole run, so the controller alone
+    # sets the steps: N(tol) ~ tol^(-1/8)
+    s = O.harmonic([1.0])
+    x0 = np.array([[1.0, 0.0]])
+    n = []
+    for tol in (1e-6, 1e-10, 1e-14):
+        o = O.integrate(s, x0, adaptive_run(O, 200.0, tol, dt=0.1, K=2000))
+        n.append(o["steps_accepted"][0])
+        exact = np.array([math.cos(200.0), -math.sin(200.0)])
+        assert np.max(np.abs(o["x_final"][0] - exact)) < 1e3 * max(tol, 1e-15)
+    r1, r2 = n[1] / n[0], n[2] / n[1]
+    assert 2.4 < r1 < 4.0 and 2.4 < r2 < 4.0, n  # (1e4)^(1/8) = 3.16
+
+
+def test_adaptive_rejections_recover(O):
+    # a first step of 4 time units on a unit-frequency oscillator is
+    # rejected until the controller has shrunk it; the run is still accurate
+    s = O.harmonic([1.0])
+    x0 = np.array([[0.3, 0.8]])
+    o = O.integrate(s, x0, adaptive_run(O, 40.0, 1e-10, dt=4.0, K=1))
+    assert o["steps_rejected"][0] >= 1
+    t = 40.0
+    exact = np.array([0.3 * math.cos(t) + 0.8 * math.sin(t), -0.3 * math.sin(t) + 0.8 * math.cos(t)])
+    assert np.max(np.abs(o["x_final"][0] - exact)) < 1e-7
+
+
+def test_adaptive_resume_and_checkpoint_times(O):
+    s = O.henon_heiles()
+    x0 = np.array([[0.0, 0.1, 0.45, 0.05], [0.0, -0.3, 0.2, 0.1]])
+    w0 = np.array([[[1.0, 0.2, -0.1, 0.3], [0.1, 1.0, 0.2, -0.4]]] * 2)
+    ind = O.IND_SALI | O.IND_LD | O.IND_LYAP | O.IND_ENERGY
+    run = adaptive_run(O, 30.0, 1e-9, dt=0.05, K=20, ind=ind, n_lyap=4)
+    full = O.integrate(s, x0, run, w0=w0)
+    st = O.State(s, run, x0, w0=w0)
+    st.advance(200)
+    st.advance(600)
+    part = st.finalize()
+    acc, rej = st.step_counts()
+    for k in ("x_final", "sali_min", "lyap", "ld", "energy_err", "t_end"):
+        assert np.array_equal(full[k], part[k]), k
+    assert np.array_equal(acc, full["steps_accepted"])
+    assert np.all(full["t_end"] == 30.0)
+    assert np.max(np.abs(full["lyap"].sum(axis=1))) < 1e-8
+
+
+def test_adaptive_gives_up_on_an_impossible_tolerance(O):
+    # tolerance 1e-40 needs steps near 1e-5: more than 100000 attempts in a
+    # checkpoint interval of 1 stop the orbit
+    s = O.harmonic([1.0])
+    o = O.integrate(s, np.array([[1.0, 0.0]]), adaptive_run(O, 1.0, 1e-40, dt=0.1, K=10))
+    assert o["status"][0] == O.ST_STEPFAIL and o["label"][0] == 3
+    assert np.isnan(o["energy_err"][0])
