@@ -48,7 +48,7 @@ __device__ int64_t pop(const Pool &pl, unsigned long long t0, bool need) {
   if (!need) return -1;
   const unsigned long long slot = base + __popcll(m & ((1ull << lane) - 1ull));
   if (slot >= t0) return -1;
-  return pl.queue[slot % (unsigned long long)pl.qcap];
+  return gld<true>(&pl.queue[slot % (unsigned long long)pl.qcap]);
 }
 
 // Wave-aggregated push of unfinished orbits.
@@ -62,7 +62,7 @@ __device__ void push(const Pool &pl, bool want, int64_t idx) {
   base = __shfl(base, leader);
   if (want) {
     const unsigned long long slot = base + __popcll(m & ((1ull << lane) - 1ull));
-    pl.queue[slot % (unsigned long long)pl.qcap] = idx;
+    gst<true>(&pl.queue[slot % (unsigned long long)pl.qcap], idx);
   }
 }
 
@@ -72,7 +72,7 @@ __device__ int64_t run_lane_pool(const Pool &pl, int64_t left) {
   const unsigned long long t0 = tail0_of(pl);
   const StepCoef k(a.dt);
   const int K = a.K;
-  LaneOrbit<S, 2, false, 2> o;
+  LaneOrbit<S, 2, false, 2, true> o;
   int64_t idx = -1, s = 0;
   bool have = false;
   auto refill = [&]() {
@@ -85,7 +85,7 @@ __device__ int64_t run_lane_pool(const Pool &pl, int64_t left) {
         o.load(a, got);
         if (o.st == CHX_ORBIT_OK) {
           idx = got;
-          s = pl.sdone[got];
+          s = gld<true>(&pl.sdone[got]);
           have = true;
         }
       }
@@ -99,7 +99,7 @@ __device__ int64_t run_lane_pool(const Pool &pl, int64_t left) {
       const bool cont = o.checkpoint(a, (double)s * a.dt);
       if (!cont || s >= a.n_total) {
         o.store(a, idx);
-        pl.sdone[idx] = s;
+        gst<true>(&pl.sdone[idx], s);
         have = false;
       }
     }
@@ -108,7 +108,7 @@ __device__ int64_t run_lane_pool(const Pool &pl, int64_t left) {
   }
   if (have) {
     o.store(a, idx);
-    pl.sdone[idx] = s;
+    gst<true>(&pl.sdone[idx], s);
   }
   push(pl, have, idx);
   return left;
@@ -120,7 +120,7 @@ __device__ int64_t run_crow_pool(const Pool &pl, int64_t left) {
   const unsigned long long t0 = tail0_of(pl);
   const StepCoef k(a.dt);
   const int K = a.K;
-  CRowOrbit<N, 2> r;
+  CRowOrbit<N, 2, true> r;
   r.init_lane();
   const int lane = threadIdx.x & 63, head_lane = lane & ~15;
   int64_t idx = -1, s = 0;
@@ -137,7 +137,7 @@ __device__ int64_t run_crow_pool(const Pool &pl, int64_t left) {
         r.load(a, got);
         if (r.st == CHX_ORBIT_OK) {
           idx = got;
-          s = pl.sdone[got];
+          s = gld<true>(&pl.sdone[got]);
           have = true;
         }
       }
@@ -151,7 +151,7 @@ __device__ int64_t run_crow_pool(const Pool &pl, int64_t left) {
       const bool cont = r.checkpoint(a, (double)s * a.dt);
       if (!cont || s >= a.n_total) {
         r.store(a, idx);
-        if ((lane & 15) == 0) pl.sdone[idx] = s;
+        if ((lane & 15) == 0) gst<true>(&pl.sdone[idx], s);
         have = false;
       }
     }
@@ -160,7 +160,7 @@ __device__ int64_t run_crow_pool(const Pool &pl, int64_t left) {
   }
   if (have) {
     r.store(a, idx);
-    if ((lane & 15) == 0) pl.sdone[idx] = s;
+    if ((lane & 15) == 0) gst<true>(&pl.sdone[idx], s);
   }
   push(pl, have && (lane & 15) == 0, idx);
   return left;
@@ -171,11 +171,12 @@ __device__ int64_t run_crow_pool(const Pool &pl, int64_t left) {
 // outside the step loops.
 // Orbit states, step counts and queue slots written in one launch are read
 // in the next by wavefronts on other XCDs, whose L2 caches are not coherent
-// with each other.  Each thread therefore starts with an agent-scope fence
-// (stale L2 lines are dropped) and ends with one (its writes reach memory
-// before the launch completes).  Without them, 15 of 40 runs of a mixed
-// ensemble at 50 steps per launch differed from the plain results; with
-// them none of 50 did.
+// with each other, and neighbouring orbits of one cache line are held by
+// wavefronts on different XCDs at once.  All of them are therefore read and
+// written with agent-scope (coherent) accesses, gld/gst, and each thread
+// also starts and ends with an agent-scope fence.  With plain accesses and
+// no fences, 15 of 40 runs of a mixed ensemble at 50 steps per launch
+// differed from the plain results; with the fences alone none of 50 did.
 __global__ void __launch_bounds__(256, 3) batched_kernel(const BatchArgs b) {
   __threadfence();
   const int wave = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);

@@ -55,4 +55,23 @@ __device__ __forceinline__ void grow(double &m, int &e, double f) {
   e += k;
 }
 
+// Loads and stores of orbit state that a wavefront on another XCD may read
+// or write in another launch (the persistent kernel moves orbits between
+// wavefronts): with CO they are agent-scope relaxed atomics, which the
+// XCDs' L2 caches keep coherent; otherwise plain accesses.
+template <bool CO, class T>
+__device__ __forceinline__ T gld(const T *p) {
+  if constexpr (CO)
+    return __hip_atomic_load(const_cast<T *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else
+    return *p;
+}
+template <bool CO, class T>
+__device__ __forceinline__ void gst(T *p, T v) {
+  if constexpr (CO)
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else
+    *p = v;
+}
+
 }  // namespace chx

@@ -21,7 +21,9 @@
 
 namespace chx {
 
-template <int N, int M>
+// CO: coherent loads and stores of the orbit's state (gld/gst), for the
+// persistent kernel.
+template <int N, int M, bool CO = false>
 struct CRowOrbit {
   static constexpr int MM = (M > 0 ? M : 1);
   double q, p, F, kl, kr;
@@ -41,52 +43,52 @@ struct CRowOrbit {
   __device__ void load(const StepArgs &a, int64_t o) {
     init_lane();
     const int64_t P = a.pitch;
-    q = mass ? a.x[lane * P + o] : 0.0;
-    p = mass ? a.x[(N + lane) * P + o] : 0.0;
+    q = mass ? gld<CO>(&a.x[lane * P + o]) : 0.0;
+    p = mass ? gld<CO>(&a.x[(N + lane) * P + o]) : 0.0;
 #pragma unroll
     for (int v = 0; v < M; ++v) {
-      dq[v] = mass ? a.w[((int64_t)v * 2 * N + lane) * P + o] : 0.0;
-      dp[v] = mass ? a.w[((int64_t)v * 2 * N + N + lane) * P + o] : 0.0;
-      gm[v] = a.gm[v * P + o];
-      ge[v] = a.ge[v * P + o];
+      dq[v] = mass ? gld<CO>(&a.w[((int64_t)v * 2 * N + lane) * P + o]) : 0.0;
+      dp[v] = mass ? gld<CO>(&a.w[((int64_t)v * 2 * N + N + lane) * P + o]) : 0.0;
+      gm[v] = gld<CO>(&a.gm[v * P + o]);
+      ge[v] = gld<CO>(&a.ge[v * P + o]);
     }
-    ld = a.sc[SC_LD * P + o];
-    gprev = a.sc[SC_GPREV * P + o];
-    smin2 = a.sc[SC_SALI_MIN2 * P + o];
-    slast2 = a.sc[SC_SALI_LAST2 * P + o];
-    tch = a.sc[SC_T_CHAOS * P + o];
-    eerr = a.sc[SC_EERR * P + o];
-    H0 = a.sc[SC_H0 * P + o];
-    tend = a.sc[SC_T_END * P + o];
-    st = a.st[o];
+    ld = gld<CO>(&a.sc[SC_LD * P + o]);
+    gprev = gld<CO>(&a.sc[SC_GPREV * P + o]);
+    smin2 = gld<CO>(&a.sc[SC_SALI_MIN2 * P + o]);
+    slast2 = gld<CO>(&a.sc[SC_SALI_LAST2 * P + o]);
+    tch = gld<CO>(&a.sc[SC_T_CHAOS * P + o]);
+    eerr = gld<CO>(&a.sc[SC_EERR * P + o]);
+    H0 = gld<CO>(&a.sc[SC_H0 * P + o]);
+    tend = gld<CO>(&a.sc[SC_T_END * P + o]);
+    st = gld<CO>(&a.st[o]);
     springs(a);
   }
 
   __device__ void store(const StepArgs &a, int64_t o) const {
     const int64_t P = a.pitch;
     if (mass) {
-      a.x[lane * P + o] = q;
-      a.x[(N + lane) * P + o] = p;
+      gst<CO>(&a.x[lane * P + o], q);
+      gst<CO>(&a.x[(N + lane) * P + o], p);
 #pragma unroll
       for (int v = 0; v < M; ++v) {
-        a.w[((int64_t)v * 2 * N + lane) * P + o] = dq[v];
-        a.w[((int64_t)v * 2 * N + N + lane) * P + o] = dp[v];
+        gst<CO>(&a.w[((int64_t)v * 2 * N + lane) * P + o], dq[v]);
+        gst<CO>(&a.w[((int64_t)v * 2 * N + N + lane) * P + o], dp[v]);
       }
     }
     if (lane == 0) {
 #pragma unroll
       for (int v = 0; v < M; ++v) {
-        a.gm[v * P + o] = gm[v];
-        a.ge[v * P + o] = ge[v];
+        gst<CO>(&a.gm[v * P + o], gm[v]);
+        gst<CO>(&a.ge[v * P + o], ge[v]);
       }
-      a.sc[SC_LD * P + o] = ld;
-      a.sc[SC_GPREV * P + o] = gprev;
-      a.sc[SC_SALI_MIN2 * P + o] = smin2;
-      a.sc[SC_SALI_LAST2 * P + o] = slast2;
-      a.sc[SC_T_CHAOS * P + o] = tch;
-      a.sc[SC_EERR * P + o] = eerr;
-      a.sc[SC_T_END * P + o] = tend;
-      a.st[o] = st;
+      gst<CO>(&a.sc[SC_LD * P + o], ld);
+      gst<CO>(&a.sc[SC_GPREV * P + o], gprev);
+      gst<CO>(&a.sc[SC_SALI_MIN2 * P + o], smin2);
+      gst<CO>(&a.sc[SC_SALI_LAST2 * P + o], slast2);
+      gst<CO>(&a.sc[SC_T_CHAOS * P + o], tch);
+      gst<CO>(&a.sc[SC_EERR * P + o], eerr);
+      gst<CO>(&a.sc[SC_T_END * P + o], tend);
+      gst<CO>(&a.st[o], st);
     }
   }
 

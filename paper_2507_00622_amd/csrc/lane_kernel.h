@@ -34,7 +34,9 @@ namespace chx {
 // MS >= 0 fixes the size of the SALI/GALI set at compile time (the rest of
 // the M vectors are the Lyapunov set), so the checkpoint has no branches on
 // it; MS = -1 reads it from the launch arguments.
-template <class S, int M, bool GP, int MS = -1>
+// CO: coherent loads and stores of the orbit's state (gld/gst), for the
+// persistent kernel.
+template <class S, int M, bool GP, int MS = -1, bool CO = false>
 struct LaneOrbit {
   static constexpr int N = S::N, D = 2 * N, MM = (M > 0 ? M : 1);
   static constexpr int UNROLL = (N == 2 && M >= 4) ? 2 : 1;
@@ -47,45 +49,45 @@ struct LaneOrbit {
   __device__ void load(const StepArgs &a, int64_t i) {
     const int64_t P = a.pitch;
 #pragma unroll
-    for (int c = 0; c < D; ++c) x[c] = a.x[c * P + i];
+    for (int c = 0; c < D; ++c) x[c] = gld<CO>(&a.x[c * P + i]);
 #pragma unroll
     for (int v = 0; v < M; ++v) {
 #pragma unroll
-      for (int c = 0; c < D; ++c) w[v][c] = a.w[((int64_t)v * D + c) * P + i];
-      gm[v] = a.gm[v * P + i];
-      ge[v] = a.ge[v * P + i];
+      for (int c = 0; c < D; ++c) w[v][c] = gld<CO>(&a.w[((int64_t)v * D + c) * P + i]);
+      gm[v] = gld<CO>(&a.gm[v * P + i]);
+      ge[v] = gld<CO>(&a.ge[v * P + i]);
     }
-    ld = a.sc[SC_LD * P + i];
-    gprev = a.sc[SC_GPREV * P + i];
-    smin2 = a.sc[SC_SALI_MIN2 * P + i];
-    slast2 = a.sc[SC_SALI_LAST2 * P + i];
-    tch = a.sc[SC_T_CHAOS * P + i];
-    eerr = a.sc[SC_EERR * P + i];
-    H0 = a.sc[SC_H0 * P + i];
-    tend = a.sc[SC_T_END * P + i];
-    st = a.st[i];
+    ld = gld<CO>(&a.sc[SC_LD * P + i]);
+    gprev = gld<CO>(&a.sc[SC_GPREV * P + i]);
+    smin2 = gld<CO>(&a.sc[SC_SALI_MIN2 * P + i]);
+    slast2 = gld<CO>(&a.sc[SC_SALI_LAST2 * P + i]);
+    tch = gld<CO>(&a.sc[SC_T_CHAOS * P + i]);
+    eerr = gld<CO>(&a.sc[SC_EERR * P + i]);
+    H0 = gld<CO>(&a.sc[SC_H0 * P + i]);
+    tend = gld<CO>(&a.sc[SC_T_END * P + i]);
+    st = gld<CO>(&a.st[i]);
     S::force(x, F, a.prm);
   }
 
   __device__ void store(const StepArgs &a, int64_t i) const {
     const int64_t P = a.pitch;
 #pragma unroll
-    for (int c = 0; c < D; ++c) a.x[c * P + i] = x[c];
+    for (int c = 0; c < D; ++c) gst<CO>(&a.x[c * P + i], x[c]);
 #pragma unroll
     for (int v = 0; v < M; ++v) {
 #pragma unroll
-      for (int c = 0; c < D; ++c) a.w[((int64_t)v * D + c) * P + i] = w[v][c];
-      a.gm[v * P + i] = gm[v];
-      a.ge[v * P + i] = ge[v];
+      for (int c = 0; c < D; ++c) gst<CO>(&a.w[((int64_t)v * D + c) * P + i], w[v][c]);
+      gst<CO>(&a.gm[v * P + i], gm[v]);
+      gst<CO>(&a.ge[v * P + i], ge[v]);
     }
-    a.sc[SC_LD * P + i] = ld;
-    a.sc[SC_GPREV * P + i] = gprev;
-    a.sc[SC_SALI_MIN2 * P + i] = smin2;
-    a.sc[SC_SALI_LAST2 * P + i] = slast2;
-    a.sc[SC_T_CHAOS * P + i] = tch;
-    a.sc[SC_EERR * P + i] = eerr;
-    a.sc[SC_T_END * P + i] = tend;
-    a.st[i] = st;
+    gst<CO>(&a.sc[SC_LD * P + i], ld);
+    gst<CO>(&a.sc[SC_GPREV * P + i], gprev);
+    gst<CO>(&a.sc[SC_SALI_MIN2 * P + i], smin2);
+    gst<CO>(&a.sc[SC_SALI_LAST2 * P + i], slast2);
+    gst<CO>(&a.sc[SC_T_CHAOS * P + i], tch);
+    gst<CO>(&a.sc[SC_EERR * P + i], eerr);
+    gst<CO>(&a.sc[SC_T_END * P + i], tend);
+    gst<CO>(&a.st[i], st);
   }
 
   __device__ __forceinline__ void kick_vectors(const StepArgs &a, double hk) {
