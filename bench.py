@@ -118,6 +118,21 @@ def flops_per_step_dop853(N, m_s, n_l, ld, energy, sali, K, system="hh"):
     return per + checkpoint_flops_hh(N, m_s, n_l, energy, sali) / K
 
 
+def flops_per_attempt_dop853(N, m_s, n_l, ld, system="hh"):
+    """Algorithmic FP64 flops of one attempted step of the adaptive DOP8(5)
+    kernel for Henon-Heiles: the fixed step's work (flops_per_step_dop853
+    without checkpoints) plus the error estimate -- per component of the
+    state and the vectors, the fifth-order difference (one FMA per weighted
+    stage), the third-order difference (3 FMA), the scale
+    atol + rtol max(|y|, |y_new|) (FMA) and two squared ratios (FMA each) --
+    and the controller (a handful of operations, counted as 8)."""
+    assert system == "hh" and N == 2
+    D = 2 * N
+    comps = D * (1 + m_s + n_l)
+    err = comps * (2 * DOP853_B_NNZ + 2 * 3 + 2 + 2 * 2)
+    return flops_per_step_dop853(N, m_s, n_l, ld, False, False, 1 << 62) + err + 8
+
+
 def checkpoint_flops_hh(N, m_s, n_l, energy, sali):
     """Flops of one Henon-Heiles checkpoint: renormalisation of the
     SALI/GALI set, SALI, modified Gram-Schmidt of the Lyapunov set, energy."""
@@ -378,6 +393,96 @@ def bench_dop853(args, P, chx, torch, dev):
                  "launch_ms": ms_avg, "launches_timed": len(full)}, cpu)
 
 
+def bench_dop853_adaptive(args, P, chx, torch, dev):
+    """The adaptive DOP8(5) solver on the Henon-Heiles 1024^2 section grid at
+    E = 0.125 (850,874 orbits): two deviation vectors (SALI), LD and energy,
+    rtol = atol = 1e-10, first step and checkpoint unit dt = 0.1 (checkpoints
+    every K dt = 1), T = 1e4 by default.  Reports labelled ICs/s, the
+    accepted and rejected steps, and the same grid with fixed-step Yoshida-4
+    at dt = 0.01 for comparison (labels and time)."""
+    import numpy as np
+
+    T = args.T or 1e4
+    dt, K, tol = 0.1, 10, 1e-10
+    ind = chx.IND_SALI | chx.IND_LD | chx.IND_ENERGY
+    x0, mask = P.grid_hh_section(0.125, args.grid, args.grid, device=dev)
+    n_steps = int(round(T / dt))
+    spl = min(args.steps_per_launch or 2000, n_steps)
+    stream = torch.cuda.current_stream()
+    log = []
+    res = {}
+
+    def one_pass(record):
+        progress(f"dop853 adaptive: {args.grid}^2 grid, T={T:g}, tol {tol:g}")
+        e = P.Ensemble(P.henon_heiles(), x0, mask=mask, steps_per_launch=spl, dt=dt, T=T,
+                       indicators=ind, renorm_every=K, seed=1002, integrator="dop853_adaptive",
+                       rtol=tol, atol=tol, outputs=("status", "label", "steps", "energy_err"))
+        advance_timed(e, n_steps, spl, stream, torch, log if record else None)
+        out = e.results()
+        res["n_active"] = e.info()[2]
+        e.close()
+        return out
+
+    for _ in range(args.warmup):
+        one_pass(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = one_pass(True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    n_active = res["n_active"]
+    value = n_active * args.steps / elapsed
+    m = mask.cpu().numpy().astype(bool)
+    steps = out["steps"].cpu().numpy()[m]
+    lab = out["label"].cpu().numpy()[m]
+    acc, rej = int(steps[:, 0].sum()), int(steps[:, 1].sum())
+    kernel_s = sum(a.elapsed_time(b) for a, b, _ in log) * 1e-3 / args.steps
+    fpa = flops_per_attempt_dop853(2, 2, 0, True)
+    ck = n_active * (n_steps // K) * checkpoint_flops_hh(2, 2, 0, True, True)
+    achieved = ((acc + rej) * fpa + ck) / kernel_s
+    # the same grid with fixed-step Yoshida-4 at dt = 0.01
+    progress("fixed-step Yoshida-4 on the same grid for comparison")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ref = P.integrate_ensemble(P.henon_heiles(), x0, mask=mask, dt=0.01, T=T, indicators=ind,
+                               seed=1002, outputs=("label",))
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t1
+    rlab = ref["label"].cpu().numpy()[m]
+    cpu = None
+    if not args.no_cpu_baseline:
+        import seeded_inputs as S
+        from oracle import oracle as O
+        threads = max(1, min(16, len(os.sched_getaffinity(0))))
+        xg, mg = O.hh_grid(0.125, args.grid, args.grid)
+        act = np.flatnonzero(mg)
+        ns, cT = 2048, 2000.0
+        idx = act[np.linspace(0, len(act) - 1, ns).astype(int)]
+        w0 = np.concatenate([S.deviation_vectors(1002, 1, 2, 4, first_ic=int(i)) for i in idx])
+        run = O.Run(dt=dt, T=cT, indicators=ind, K=K, integrator=O.INT_DOP853_ADAPTIVE,
+                    rtol=tol, atol=tol)
+        t2 = time.perf_counter()
+        O.integrate(O.henon_heiles(), xg[idx], run, w0=w0, threads=threads)
+        el = time.perf_counter() - t2
+        cpu = {"value": ns * (cT / T) / el, "unit": "ICs/s", "cores": threads, "kind": "oracle",
+               "sample": f"{ns} strided grid orbits to T={cT:g} ({el:.1f} s), scaled to T={T:g}"}
+    return emit(args, "labelled ICs/s (adaptive DOP8(5))", value, "ICs/s", elapsed, "f64", {
+        "workload": f"henon-heiles {args.grid}x{args.grid} section grid at E=0.125, adaptive "
+                    f"DOP8(5) rtol=atol={tol:g}, first step {dt}, checkpoints every {K * dt:g}, "
+                    f"T={T:g}, SALI (2 vectors)+LD+energy",
+        "orbits": int(n_active), "accepted_steps_per_orbit": acc / n_active,
+        "rejected_steps_per_orbit": rej / n_active,
+        "max_energy_error": float(out["energy_err"].cpu().numpy()[m].max()),
+        "kernel_s": kernel_s, "chaotic_fraction": float(np.mean(lab == 1)),
+        "yoshida4_dt0.01_s": plain_s, "yoshida4_ICs_per_s": n_active / plain_s,
+        "label_agreement_vs_yoshida4": float(np.mean(lab == rlab))},
+        {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+         "frac": achieved / PEAK_FP64, "traffic": None,
+         "kernel": "chx::lane_rka_kernel<SysHH, 2, false>", "flops_per_attempt": fpa,
+         "launch_ms": None, "launches_timed": len(log)}, cpu)
+
+
 def bench_batched(args, P, chx, torch, dev):
     """The persistent batched form: 2^20 Henon-Heiles orbits (seeded uniform
     accessible section points, E = 0.125), 2^18 coupled-quartic orbits
@@ -599,13 +704,16 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=("hh", "fput", "batched", "gate", "sweep", "dop853"),
+    ap.add_argument("--workload", choices=("hh", "fput", "batched", "gate", "sweep", "dop853",
+                                           "dop853_adaptive"),
                     default="hh",
                     help="hh: the headline Henon-Heiles grids (default); fput: FPU-beta "
                          "chains with 3N deviation vectors; batched: the persistent mixed "
                          "form with early exit; gate: the learned gate against the plain "
                          "form; sweep: time per orbit against the ensemble size; dop853: "
-                         "the headline grids with the fixed-step DOP853 integrator")
+                         "the headline grids with the fixed-step DOP853 integrator; "
+                         "dop853_adaptive: the adaptive DOP8(5) solver on the E=0.125 grid "
+                         "against fixed-step Yoshida-4")
     ap.add_argument("--grid", type=int, default=1024, help="grid side per energy")
     ap.add_argument("--T", type=float, default=None,
                     help="final time (default: 1e4 for hh, gate and batched, 2e3 for fput, "
@@ -649,7 +757,8 @@ def main():
         return
     if args.workload != "hh":
         fn = {"fput": bench_fput, "batched": bench_batched, "gate": bench_gate,
-              "sweep": bench_sweep, "dop853": bench_dop853}[args.workload]
+              "sweep": bench_sweep, "dop853": bench_dop853,
+              "dop853_adaptive": bench_dop853_adaptive}[args.workload]
         print(json.dumps(fn(args, P, chx, torch, dev)), flush=True)
         return
     if args.T is None:
