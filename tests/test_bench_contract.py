@@ -45,6 +45,15 @@ def test_dop853_flop_model():
     assert bench.DOP853_ROW_NNZ == (0, 1, 2, 2, 3, 3, 4, 5, 6, 7, 8, 9)
 
 
+def test_adaptive_attempt_flop_model():
+    # the fixed step with LD and 2 vectors (state 632 + 2 x 692 + LD 42) plus,
+    # for each of the 12 components, the fifth-order difference (8 FMA), the
+    # third-order difference (3 FMA), the scale (FMA) and two squared ratios
+    # (FMA), plus 8 for the controller
+    assert bench.flops_per_attempt_dop853(2, 2, 0, True) == pytest.approx(
+        632 + 2 * 692 + 42 + 12 * (16 + 6 + 2 + 4) + 8)
+
+
 def test_dop853_tableau_pattern_matches_the_oracle():
     from oracle import oracle as O
     c, a, b = O.dop853_tableau()
