@@ -132,6 +132,79 @@ static void harm_hess(int N, const double *pr, const double *q, double *h) {
     for (int j = 0; j < N; ++j) h[i * N + j] = (i == j) ? pr[i] * pr[i] : 0.0;
 }
 
+/* Dimensionless double pendulum (Examples section: its Hamiltonian in matrix
+ * form and Hamilton's equations).  x = (theta_1, theta_2, p_1, p_2),
+ * params {alpha, sigma} (length and mass ratios):
+ *   H = p^T B^{-1}(c) p / 2 - alpha (1 + sigma) cos theta_1 - cos theta_2,
+ *   c = cos(theta_1 - theta_2),
+ *   B^{-1}(c) = [[1/alpha^2, -c/alpha], [-c/alpha, 1 + sigma]] / (1 + sigma - c^2).
+ * The kinetic part is T = Q / (2 D) with D = 1 + sigma - c^2 and
+ * Q = p_1^2/alpha^2 - 2 c p_1 p_2 / alpha + (1 + sigma) p_2^2, so
+ *   theta' = dH/dp = B^{-1} p,
+ *   p_1' = -dH/dtheta_1 = s dT/dc - alpha (1 + sigma) sin theta_1,
+ *   p_2' = -dH/dtheta_2 = -s dT/dc - sin theta_2,
+ * with s = sin(theta_1 - theta_2) and dT/dc = (c Q - p_1 p_2 D / alpha) / D^2
+ * (the printed equations' (sin/2) p^T C p, C = dB^{-1}/dc).  H is not
+ * separable, so only the Runge-Kutta integrators apply.  The variational
+ * equations d(dx)/dt = Df(x) dx take the directional derivative Df(x) dx
+ * exactly, by evaluating the same formulas on dual numbers a + b e with
+ * e^2 = 0 (forward-mode differentiation). */
+typedef struct {
+  double v, d; /* value and derivative part */
+} dual;
+static dual dl(double v, double d) {
+  dual r;
+  r.v = v;
+  r.d = d;
+  return r;
+}
+static dual dadd(dual a, dual b) { return dl(a.v + b.v, a.d + b.d); }
+static dual dsub(dual a, dual b) { return dl(a.v - b.v, a.d - b.d); }
+static dual dmul(dual a, dual b) { return dl(a.v * b.v, a.v * b.d + a.d * b.v); }
+static dual ddiv(dual a, dual b) { return dl(a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v)); }
+static dual dscale(double k, dual a) { return dl(k * a.v, k * a.d); }
+static dual dsin(dual a) { return dl(sin(a.v), cos(a.v) * a.d); }
+static dual dcos(dual a) { return dl(cos(a.v), -sin(a.v) * a.d); }
+
+static void dp_rhs_dual(const double *pr, const dual *x, dual *f) {
+  const double al = pr[0], sg = pr[1];
+  dual del = dsub(x[0], x[1]);
+  dual c = dcos(del), s = dsin(del);
+  dual p1 = x[2], p2 = x[3];
+  dual D = dsub(dl(1.0 + sg, 0.0), dmul(c, c));
+  /* theta' = B^{-1}(c) p */
+  dual u1 = ddiv(dsub(dscale(1.0 / (al * al), p1), dscale(1.0 / al, dmul(c, p2))), D);
+  dual u2 = ddiv(dadd(dscale(-1.0 / al, dmul(c, p1)), dscale(1.0 + sg, p2)), D);
+  dual Q = dadd(dsub(dscale(1.0 / (al * al), dmul(p1, p1)),
+                     dscale(2.0 / al, dmul(c, dmul(p1, p2)))),
+                dscale(1.0 + sg, dmul(p2, p2)));
+  dual dTdc = ddiv(dsub(dmul(c, Q), dscale(1.0 / al, dmul(dmul(p1, p2), D))), dmul(D, D));
+  f[0] = u1;
+  f[1] = u2;
+  f[2] = dsub(dmul(s, dTdc), dscale(al * (1.0 + sg), dsin(x[0])));
+  f[3] = dsub(dscale(-1.0, dmul(s, dTdc)), dsin(x[1]));
+}
+
+static double dp_H(const double *pr, const double *x) {
+  const double al = pr[0], sg = pr[1];
+  double c = cos(x[0] - x[1]);
+  double D = 1.0 + sg - c * c;
+  double p1 = x[2], p2 = x[3];
+  double Q = p1 * p1 / (al * al) - 2.0 * c * p1 * p2 / al + (1.0 + sg) * p2 * p2;
+  return Q / (2.0 * D) - al * (1.0 + sg) * cos(x[0]) - cos(x[1]);
+}
+
+/* f(x) and, if dx is given, Df(x) dx, for the double pendulum. */
+void ora_dp_rhs(const double *pr, const double *x, const double *dx, double *f, double *df) {
+  dual xd[4], fd[4];
+  for (int i = 0; i < 4; ++i) xd[i] = dl(x[i], dx ? dx[i] : 0.0);
+  dp_rhs_dual(pr, xd, fd);
+  for (int i = 0; i < 4; ++i) {
+    f[i] = fd[i].v;
+    if (df) df[i] = fd[i].d;
+  }
+}
+
 double ora_potential(int kind, int N, const double *pr, const double *q) {
   switch (kind) {
   case ORA_SYS_HENON_HEILES: return hh_V(q);
@@ -158,6 +231,7 @@ void ora_hess(int kind, int N, const double *pr, const double *q, double *h) {
   }
 }
 double ora_hamiltonian(int kind, int N, const double *pr, const double *x) {
+  if (kind == ORA_SYS_DOUBLE_PENDULUM) return dp_H(pr, x);
   double t = 0.0;
   for (int i = 0; i < N; ++i) t += x[N + i] * x[N + i];
   return t / 2.0 + ora_potential(kind, N, pr, x);
@@ -349,6 +423,23 @@ void ora_dop853_error_weights(double er[12], double bhh[3]) {
  * M is present (the last component) when do_ld is set. */
 static void ext_rhs(int kind, int N, const double *pr, int m, int do_ld, double ldp,
                     const double *y, double *f, double *g, double *h) {
+  if (kind == ORA_SYS_DOUBLE_PENDULUM) {
+    /* general Hamiltonian: f and Df dx by dual numbers */
+    ora_dp_rhs(pr, y, NULL, f, NULL);
+    for (int v = 0; v < m; ++v) {
+      double tmp[4];
+      ora_dp_rhs(pr, y, y + 4 + (int64_t)v * 4, tmp, f + 4 + (int64_t)v * 4);
+    }
+    if (do_ld) {
+      double s = 0.0;
+      for (int i = 0; i < 4; ++i) {
+        double a = fabs(f[i]);
+        s += (ldp == 0.5) ? sqrt(a) : pow(a, ldp);
+      }
+      f[4 + (int64_t)m * 4] = s;
+    }
+    return;
+  }
   const double *q = y, *p = y + N;
   ora_grad(kind, N, pr, q, g);
   ora_hess(kind, N, pr, q, h);
@@ -565,6 +656,15 @@ static ora_view view(double *st, int N, int m_s, int n_l) {
 static double ld_integrand(int kind, int N, const double *pr, const double *x,
                            double ldp) {
   double g[ORA_MAX_DOF], s = 0.0;
+  if (kind == ORA_SYS_DOUBLE_PENDULUM) {
+    double f[4];
+    ora_dp_rhs(pr, x, NULL, f, NULL);
+    for (int i = 0; i < 4; ++i) {
+      double a = fabs(f[i]);
+      s += (ldp == 0.5) ? sqrt(a) : pow(a, ldp);
+    }
+    return s;
+  }
   ora_grad(kind, N, pr, x, g);
   for (int i = 0; i < N; ++i) {
     double a = fabs(x[N + i]);
@@ -679,6 +779,7 @@ int ora_advance_with(int kind, int N, const double *pr, double *state, int64_t n
   int64_t L = ora_state_len(N, m_s, n_l);
   if (K < 1 || s_begin < 0 || s_end > n_total || s_begin > s_end) return 1;
   if (integrator != ORA_INT_YOSHIDA4 && integrator != ORA_INT_DOP853) return 3;
+  if (integrator == ORA_INT_YOSHIDA4 && kind == ORA_SYS_DOUBLE_PENDULUM) return 4;
   const int m = m_s + n_l, do_ld = (ind & ORA_IND_LD) != 0;
   double *ws = NULL, *y = NULL;
   const int64_t ny = (int64_t)2 * N * (1 + m) + (do_ld ? 1 : 0);

@@ -46,6 +46,8 @@ extern "C" {
 #define ORA_SYS_FPUT 2         /* params {k, alpha, beta}; N+1 springs         */
 #define ORA_SYS_QUARTIC 3      /* params {eps}; V = sum q^4/4 + eps sum q_i^2 q_j^2 */
 #define ORA_SYS_HARMONIC 4     /* params {omega_1..omega_N}; V = sum w^2 q^2/2 */
+#define ORA_SYS_DOUBLE_PENDULUM 5 /* ndof == 2, params {alpha, sigma}; not separable:
+                                     Runge-Kutta integrators only */
 
 /* Indicator bits (the oracle's own numbering). */
 #define ORA_IND_SALI 1
@@ -71,7 +73,12 @@ extern "C" {
 double ora_potential(int kind, int ndof, const double *params, const double *q);
 void ora_grad(int kind, int ndof, const double *params, const double *q, double *g);
 void ora_hess(int kind, int ndof, const double *params, const double *q, double *h);
-/* H(q, p) = |p|^2 / 2 + V(q); x = (q_1..q_N, p_1..p_N). */
+/* Double pendulum: f(x) = (dH/dp, -dH/dtheta) and, if dx != NULL, the
+ * directional derivative Df(x) dx (x, dx, f, df of length 4). */
+void ora_dp_rhs(const double *params, const double *x, const double *dx, double *f,
+                double *df);
+/* H(q, p) = |p|^2 / 2 + V(q); x = (q_1..q_N, p_1..p_N); the double pendulum's
+ * own H. */
 double ora_hamiltonian(int kind, int ndof, const double *params, const double *x);
 
 /* The drift and kick coefficients of one Yoshida-4 KDK step. */

@@ -22,6 +22,7 @@ SYS_HENON_HEILES = 1
 SYS_FPUT = 2
 SYS_QUARTIC = 3
 SYS_HARMONIC = 4
+SYS_DOUBLE_PENDULUM = 5
 
 IND_SALI = 1
 IND_GALI = 2
@@ -66,6 +67,7 @@ def lib():
         L.ora_advance_with.restype = i
         L.ora_advance_with.argtypes = L.ora_advance.argtypes + [i]
         L.ora_dop853_tableau.argtypes = [P, P, P]
+        L.ora_dp_rhs.argtypes = [P, P, P, P, P]
         L.ora_dop853_error_weights.argtypes = [P, P]
         L.ora_advance_adaptive.restype = i
         L.ora_advance_adaptive.argtypes = L.ora_advance.argtypes + [d, d]
@@ -112,6 +114,20 @@ def quartic(N=3, eps=0.1):
 
 def harmonic(omegas):
     return System(SYS_HARMONIC, len(omegas), tuple(float(w) for w in omegas))
+
+
+def double_pendulum(alpha=1.0, sigma=1.0):
+    """The dimensionless double pendulum; x = (theta_1, theta_2, p_1, p_2)."""
+    return System(SYS_DOUBLE_PENDULUM, 2, (float(alpha), float(sigma)))
+
+
+def dp_rhs(sys, x, dx=None):
+    """f(x) of the double pendulum, and Df(x) dx when dx is given."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    f, df = np.zeros(4), np.zeros(4)
+    d = None if dx is None else np.ascontiguousarray(dx, dtype=np.float64)
+    lib().ora_dp_rhs(_p(sys.parr()), _p(x), _p(d), _p(f), _p(df) if d is not None else None)
+    return f if dx is None else (f, df)
 
 
 # --- systems ---------------------------------------------------------------

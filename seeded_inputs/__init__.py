@@ -103,3 +103,13 @@ def quartic_draws(seed, n, ndof=3):
     out[:, 2 * ndof] = uniform_open(seed, STREAM_IC, np.uint64(2) * e[:, 2 * ndof])
     return out
 
+
+
+def dp_states(seed, n, theta_max=np.pi, p_max=0.0):
+    """n double-pendulum states (theta_1, theta_2, p_1, p_2): angles uniform
+    in [-theta_max, theta_max], momenta uniform in [-p_max, p_max];
+    element e = 4 i + j."""
+    k = np.arange(4 * n, dtype=np.uint64)
+    u = uniform(seed, STREAM_IC, k).reshape(n, 4)
+    half = np.array([theta_max, theta_max, p_max, p_max])
+    return (2.0 * u - 1.0) * half
