@@ -53,7 +53,8 @@ typedef enum {
   CHX_ERR_INTERNAL = 5
 } chx_status;
 
-/* Built-in systems (separable, H = |p|^2/2 + V(q)). */
+/* Built-in systems.  Kinds 1-4 are separable, H = |p|^2/2 + V(q); kind 5
+   is not and takes the DOP853 integrators only. */
 enum {
   CHX_SYS_HENON_HEILES = 1, /* Examples section, Henon-Heiles Hamiltonian:
                                V = (x^2+y^2)/2 + x^2 y - y^3/3; ndof = 2, no params */
@@ -64,8 +65,19 @@ enum {
                                ndof 2..16 */
   CHX_SYS_QUARTIC = 3,      /* V = sum q_i^4/4 + eps sum_{i<j} q_i^2 q_j^2;
                                params {eps}; ndof 1..3 */
-  CHX_SYS_HARMONIC = 4      /* V = sum omega_i^2 q_i^2 / 2; params {omega_i};
+  CHX_SYS_HARMONIC = 4,     /* V = sum omega_i^2 q_i^2 / 2; params {omega_i};
                                ndof 1..3 */
+  CHX_SYS_DOUBLE_PENDULUM = 5 /* Examples section, dimensionless double pendulum:
+                               x = (theta_1, theta_2, p_1, p_2),
+                               H = p^T B^{-1}(c) p / 2 - alpha (1+sigma) cos theta_1
+                                   - cos theta_2, c = cos(theta_1 - theta_2),
+                               B^{-1}(c) = [[1/alpha^2, -c/alpha],
+                                            [-c/alpha, 1+sigma]] / (1+sigma-c^2);
+                               params {alpha (length ratio) > 0, sigma (mass
+                               ratio) > 0}; ndof = 2; integrator CHX_INT_DOP853
+                               or CHX_INT_DOP853_ADAPTIVE (else
+                               CHX_ERR_UNSUPPORTED); the LD integrand is
+                               sum_c |dx_c/dt|^p over the four components */
 };
 
 typedef struct {

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libchx.so")
 
 # --- constants mirrored from include/chx.h -----------------------------------
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_INTERNAL = range(6)
-SYS_HENON_HEILES, SYS_FPUT, SYS_QUARTIC, SYS_HARMONIC = 1, 2, 3, 4
+SYS_HENON_HEILES, SYS_FPUT, SYS_QUARTIC, SYS_HARMONIC, SYS_DOUBLE_PENDULUM = 1, 2, 3, 4, 5
 IND_SALI, IND_GALI, IND_LYAP, IND_LD, IND_ENERGY = 1, 2, 4, 8, 16
 PTR_DEVICE = 1
 INT_YOSHIDA4, INT_DOP853, INT_DOP853_ADAPTIVE = 0, 1, 2
@@ -188,6 +188,12 @@ def quartic(N=3, eps=0.1):
 
 def harmonic(omegas):
     return System(SYS_HARMONIC, len(omegas), tuple(float(w) for w in omegas))
+
+
+def double_pendulum(alpha=1.0, sigma=1.0):
+    """x = (theta_1, theta_2, p_1, p_2); alpha the length ratio, sigma the
+    mass ratio; integrated with "dop853" or "dop853_adaptive" only."""
+    return System(SYS_DOUBLE_PENDULUM, 2, (float(alpha), float(sigma)))
 
 
 # --- array marshalling -----------------------------------------------------------

@@ -46,6 +46,7 @@ int required_params(int kind, int ndof) {
   case CHX_SYS_FPUT: return 3;
   case CHX_SYS_QUARTIC: return 1;
   case CHX_SYS_HARMONIC: return ndof;
+  case CHX_SYS_DOUBLE_PENDULUM: return 2;
   }
   return -1;
 }
@@ -64,6 +65,9 @@ chx_status check_system(const chx_system *sys) {
   case CHX_SYS_HARMONIC:
     if (N < 1 || N > 3) return fail(CHX_ERR_INVALID_ARG, "ndof must be 1..3 (got %d)", N);
     break;
+  case CHX_SYS_DOUBLE_PENDULUM:
+    if (N != 2) return fail(CHX_ERR_INVALID_ARG, "the double pendulum needs ndof == 2 (got %d)", N);
+    break;
   default: return fail(CHX_ERR_INVALID_ARG, "unknown system kind %d", k);
   }
   const int np = required_params(k, N);
@@ -71,6 +75,8 @@ chx_status check_system(const chx_system *sys) {
   if (np > 0 && !sys->params) return fail(CHX_ERR_INVALID_ARG, "system params is NULL");
   for (int i = 0; i < np; ++i)
     if (!isfinite(sys->params[i])) return fail(CHX_ERR_INVALID_ARG, "system param %d is not finite", i);
+  if (k == CHX_SYS_DOUBLE_PENDULUM && !(sys->params[0] > 0.0 && sys->params[1] > 0.0))
+    return fail(CHX_ERR_INVALID_ARG, "the double pendulum needs alpha > 0 and sigma > 0");
   return CHX_OK;
 }
 
@@ -117,7 +123,9 @@ chx_status make_plan(const chx_system *sys, const chx_options *opt, Plan *p) {
       o.integrator != CHX_INT_DOP853_ADAPTIVE)
     return fail(CHX_ERR_INVALID_ARG, "unknown integrator %d", o.integrator);
   if (o.integrator != CHX_INT_YOSHIDA4 && sys->kind == CHX_SYS_FPUT)
-    return fail(CHX_ERR_UNSUPPORTED, "DOP853 is available for the lane-per-orbit systems (Henon-Heiles, quartic, harmonic), not FPUT");
+    return fail(CHX_ERR_UNSUPPORTED, "DOP853 is available for the lane-per-orbit systems (Henon-Heiles, quartic, harmonic, double pendulum), not FPUT");
+  if (o.integrator == CHX_INT_YOSHIDA4 && sys->kind == CHX_SYS_DOUBLE_PENDULUM)
+    return fail(CHX_ERR_UNSUPPORTED, "the double pendulum is not separable: integrate it with DOP853 (fixed or adaptive)");
   if (o.integrator == CHX_INT_DOP853_ADAPTIVE) {
     if (o.rtol == 0.0 && o.atol == 0.0) o.rtol = o.atol = 1e-10;
     if (!(o.rtol >= 0.0) || !(o.atol >= 0.0) || !isfinite(o.rtol) || !isfinite(o.atol))

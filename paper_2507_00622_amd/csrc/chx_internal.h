@@ -36,7 +36,7 @@ enum Sc {
   NSC
 };
 
-enum SysKind { SYS_HH = 1, SYS_FPUT = 2, SYS_QUARTIC = 3, SYS_HARMONIC = 4 };
+enum SysKind { SYS_HH = 1, SYS_FPUT = 2, SYS_QUARTIC = 3, SYS_HARMONIC = 4, SYS_DP = 5 };
 
 // Everything one integration launch needs (passed by value).
 struct StepArgs {

@@ -24,6 +24,7 @@ hipError_t launch_lane_rk_harmonic2(int M, bool adaptive, const StepArgs &a, int
                             hipStream_t s);
 hipError_t launch_lane_rk_harmonic3(int M, bool adaptive, const StepArgs &a, int block,
                             hipStream_t s);
+hipError_t launch_lane_rk_dp(int M, bool adaptive, const StepArgs &a, int block, hipStream_t s);
 
 bool lane_supported(int sys, int ndof, int M) {
   if (M < 0 || M > 4 * ndof) return false;
@@ -31,13 +32,14 @@ bool lane_supported(int sys, int ndof, int M) {
   case SYS_HH: return ndof == 2;
   case SYS_QUARTIC:
   case SYS_HARMONIC: return ndof >= 1 && ndof <= 3;
+  case SYS_DP: return ndof == 2;  // DOP853 kernels only
   }
   return false;
 }
 
 hipError_t launch_lane(int sys, int ndof, int M, const StepArgs &a, int block,
                        hipStream_t s) {
-  if (!lane_supported(sys, ndof, M)) return hipErrorInvalidValue;
+  if (!lane_supported(sys, ndof, M) || sys == SYS_DP) return hipErrorInvalidValue;
   if (a.n == 0) return hipSuccess;
   switch (sys) {
   case SYS_HH: return launch_lane_hh(M, a, block, s);
@@ -53,7 +55,8 @@ hipError_t launch_lane(int sys, int ndof, int M, const StepArgs &a, int block,
   return hipErrorInvalidValue;
 }
 
-// The same systems with the DOP853 kernels (fixed step or adaptive).
+// The same systems and the double pendulum with the DOP853 kernels (fixed
+// step or adaptive).
 hipError_t launch_lane_rk(int sys, int ndof, int M, bool adaptive, const StepArgs &a,
                           int block, hipStream_t s) {
   if (!lane_supported(sys, ndof, M)) return hipErrorInvalidValue;
@@ -68,6 +71,7 @@ hipError_t launch_lane_rk(int sys, int ndof, int M, bool adaptive, const StepArg
     return ndof == 1 ? launch_lane_rk_harmonic1(M, adaptive, a, block, s)
          : ndof == 2 ? launch_lane_rk_harmonic2(M, adaptive, a, block, s)
                      : launch_lane_rk_harmonic3(M, adaptive, a, block, s);
+  case SYS_DP: return launch_lane_rk_dp(M, adaptive, a, block, s);
   }
   return hipErrorInvalidValue;
 }

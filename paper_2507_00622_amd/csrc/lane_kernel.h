@@ -25,11 +25,21 @@
 // The per-orbit work lives in LaneOrbit so that the plain kernel below and
 // the persistent batched kernel run the same arithmetic.
 #pragma once
+#include <type_traits>
+
 #include "chx_internal.h"
 #include "device_math.h"
 #include "systems.h"
 
 namespace chx {
+
+// Systems whose Hamiltonian is not of the form |p|^2/2 + V(q) provide
+// hamiltonian(x, prm) and a general right-hand side (systems_dp.h); only
+// the Runge-Kutta kernels integrate them.
+template <class S, class = void>
+struct has_hamiltonian : std::false_type {};
+template <class S>
+struct has_hamiltonian<S, std::void_t<decltype(&S::hamiltonian)>> : std::true_type {};
 
 // MS >= 0 fixes the size of the SALI/GALI set at compile time (the rest of
 // the M vectors are the Lyapunov set), so the checkpoint has no branches on
@@ -66,7 +76,7 @@ struct LaneOrbit {
     H0 = gld<CO>(&a.sc[SC_H0 * P + i]);
     tend = gld<CO>(&a.sc[SC_T_END * P + i]);
     st = gld<CO>(&a.st[i]);
-    S::force(x, F, a.prm);
+    if constexpr (!has_hamiltonian<S>::value) S::force(x, F, a.prm);
   }
 
   __device__ void store(const StepArgs &a, int64_t i) const {
@@ -240,10 +250,15 @@ struct LaneOrbit {
       }
     }
     if (a.ind & CHX_IND_ENERGY) {
-      double kin = 0.0;
+      double e;
+      if constexpr (has_hamiltonian<S>::value) {
+        e = __builtin_fabs(S::hamiltonian(x, a.prm) - H0);
+      } else {
+        double kin = 0.0;
 #pragma unroll
-      for (int r = 0; r < N; ++r) kin = __builtin_fma(x[N + r], x[N + r], kin);
-      const double e = __builtin_fabs(__builtin_fma(0.5, kin, S::potential(x, a.prm)) - H0);
+        for (int r = 0; r < N; ++r) kin = __builtin_fma(x[N + r], x[N + r], kin);
+        e = __builtin_fabs(__builtin_fma(0.5, kin, S::potential(x, a.prm)) - H0);
+      }
       eerr = __builtin_fmax(eerr, e);
     }
     if (escaped) {

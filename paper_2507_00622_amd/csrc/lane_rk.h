@@ -14,13 +14,16 @@
 // A step k_i = dt f(y + sum_{j<i} a_ij k_j), y <- y + sum_i b_i k_i is done
 // in two passes to keep the live registers few: first the state (12 stages;
 // the stage positions go to LDS), then each deviation vector on its own,
-// whose stages need only the Hessian at those positions.  The stage
+// whose stages need only the Hessian at those positions.  For a Hamiltonian
+// that is not |p|^2/2 + V(q) (the double pendulum) the whole stage state is
+// kept and a vector's stage derivative is the directional derivative of the
+// vector field there, by dual numbers.  The stage
 // derivatives a pass still needs are held in registers; with the method's
 // zero pattern (stages 2 and 3 feed only stages 3..5, and the solution
 // does not use stages 2..5) at most nine are live at once.  The stage
-// positions (12 N doubles per orbit) live in dynamic LDS, field-major
-// (position component f of thread t at f * blockDim + t), so the vectors'
-// registers stay below the three-wavefronts-per-SIMD budget.
+// records (12 N doubles per orbit, 12 2N for a general Hamiltonian) live in
+// dynamic LDS, field-major (component f of thread t at f * blockDim + t), so
+// the vectors' registers stay below the three-wavefronts-per-SIMD budget.
 //
 // Load, store and the checkpoints (renormalisation, SALI, Gram-Schmidt,
 // energy, escape, early exit) are those of the Yoshida-4 lane kernel.
@@ -28,6 +31,7 @@
 #include <type_traits>
 
 #include "lane_kernel.h"
+#include "systems_dp.h"
 
 namespace chx {
 
@@ -136,6 +140,15 @@ __device__ __forceinline__ double final_sum(const double (&k)[12][D], int c) {
 
 }  // namespace dop853
 
+// LDS doubles per stage record: a general system's record, else the positions
+template <class S, bool GEN>
+constexpr int rec_width() {
+  if constexpr (GEN)
+    return S::NREC;
+  else
+    return S::N;
+}
+
 template <class S, int M, bool GP>
 struct RKOrbit : LaneOrbit<S, M, GP, -1> {
   using Base = LaneOrbit<S, M, GP, -1>;
@@ -144,69 +157,125 @@ struct RKOrbit : LaneOrbit<S, M, GP, -1> {
   using Base::x;
   using Base::w;
   using Base::ld;
+  // A general Hamiltonian (not |p|^2/2 + V(q)) gives its vector field with
+  // a stage record and, from that record, its directional derivative
+  // (dual numbers); its stages keep the records in LDS, a separable one's
+  // the positions.
+  static constexpr bool GEN = has_hamiltonian<S>::value;
+  static constexpr int QW = rec_width<S, GEN>();  // LDS doubles per stage and thread
+
+  // Stage I of the state: Y = x + sum_j a_Ij k_j; its LDS record; the LD
+  // integrand sum |dY/dt|^p at weighted stages into g; k_I = h f(Y).
+  template <int I>
+  __device__ __forceinline__ void state_stage(const StepArgs &a, double h, bool do_ld,
+                                              double *qs, int stride, double (&k)[12][D],
+                                              double &g) {
+    double Y[D], f[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) Y[c] = x[c] + dop853::stage_sum<I>(k, c);
+    if constexpr (GEN) {
+      double rec[QW];
+      S::rhs_rec(Y, f, rec, a.prm);
+      if constexpr (M > 0) {
+#pragma unroll
+        for (int r = 0; r < QW; ++r) qs[(I * QW + r) * stride] = rec[r];
+      }
+    } else {
+      if constexpr (M > 0) {
+#pragma unroll
+        for (int r = 0; r < QW; ++r) qs[(I * QW + r) * stride] = Y[r];
+      }
+      double F[N];
+      S::force(Y, F, a.prm);
+#pragma unroll
+      for (int r = 0; r < N; ++r) {
+        f[r] = Y[N + r];
+        f[N + r] = -F[r];
+      }
+    }
+    if constexpr (dop853::B[I] != 0.0) {
+      if (do_ld) {
+        double gi = 0.0;
+        if constexpr (GEN) {
+#pragma unroll
+          for (int c = 0; c < D; ++c) gi += this->ld_term(a, f[c]);
+        } else {
+#pragma unroll
+          for (int r = 0; r < N; ++r) gi += this->ld_term(a, f[r]) + this->ld_term(a, f[N + r]);
+        }
+        g = __builtin_fma(dop853::B[I], gi, g);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < D; ++c) k[I][c] = h * f[c];
+  }
+
+  // Stage I of a deviation vector starting at w0: dY = w0 + sum_j a_Ij k_j,
+  // k_I = h Df(Y_I) dY with Y_I the state's stage (from LDS).
+  template <int I>
+  __device__ __forceinline__ void vector_stage(const StepArgs &a, double h, const double *w0,
+                                               const double *qs, int stride,
+                                               double (&k)[12][D]) {
+    double Y[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) Y[c] = w0[c] + dop853::stage_sum<I>(k, c);
+    if constexpr (GEN) {
+      // the records do not depend on the vector: with a plain LDS offset the
+      // optimiser loads each stage's record once for all vectors and keeps
+      // the twelve live; an offset it cannot see through keeps the loads in
+      // each vector pass
+      int off = I * QW * stride;
+      asm volatile("" : "+v"(off));
+      double rec[QW], f[D];
+#pragma unroll
+      for (int r = 0; r < QW; ++r) rec[r] = qs[off + r * stride];
+      S::jvp(rec, Y, f, a.prm);
+#pragma unroll
+      for (int c = 0; c < D; ++c) k[I][c] = h * f[c];
+    } else {
+      double Hs[S::NH], q[N];
+#pragma unroll
+      for (int r = 0; r < N; ++r) q[r] = qs[(I * N + r) * stride];
+      S::hess_scaled(q, h, Hs, a.prm);
+#pragma unroll
+      for (int r = 0; r < N; ++r) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) s = __builtin_fma(Hs[hidx(N, r, j)], Y[j], s);
+        k[I][r] = h * Y[N + r];
+        k[I][N + r] = -s;
+      }
+    }
+  }
 
   // one fixed DOP853 step of size h of the state, the M vectors and the LD;
-  // qs: this thread's stage positions in LDS, component f at qs[f * stride]
+  // qs: this thread's stage records in LDS, component f at qs[f * stride]
   __device__ __forceinline__ void rk_step(const StepArgs &a, double h, bool do_ld, double *qs,
                                           int stride) {
     {
       double k[12][D];  // h f(Y_i) of the state
       double g = 0.0;   // sum_i b_i (LD integrand at stage i)
       dop853::static_for<0, 12>([&](auto ic) {
-        constexpr int I = decltype(ic)::value;
-        double Y[D], F[N];
-#pragma unroll
-        for (int c = 0; c < D; ++c) Y[c] = x[c] + dop853::stage_sum<I>(k, c);
-        if constexpr (M > 0) {
-#pragma unroll
-          for (int r = 0; r < N; ++r) qs[(I * N + r) * stride] = Y[r];
-        }
-        S::force(Y, F, a.prm);
-        if constexpr (dop853::B[I] != 0.0) {
-          if (do_ld) {
-            double gi = 0.0;
-#pragma unroll
-            for (int r = 0; r < N; ++r) gi += this->ld_term(a, Y[N + r]) + this->ld_term(a, F[r]);
-            g = __builtin_fma(dop853::B[I], gi, g);
-          }
-        }
-#pragma unroll
-        for (int r = 0; r < N; ++r) {
-          k[I][r] = h * Y[N + r];
-          k[I][N + r] = -h * F[r];
-        }
+        state_stage<decltype(ic)::value>(a, h, do_ld, qs, stride, k, g);
       });
 #pragma unroll
       for (int c = 0; c < D; ++c) x[c] += dop853::final_sum(k, c);
       if (do_ld) ld = __builtin_fma(h, g, ld);
     }
     __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int v = 0; v < M; ++v) {
+    // (a compile-time loop: the vectors must stay in registers)
+    dop853::static_for<0, M>([&](auto vc) {
+      constexpr int v = decltype(vc)::value;
       double k[12][D];  // h f(dY_i) of vector v
       dop853::static_for<0, 12>([&](auto ic) {
-        constexpr int I = decltype(ic)::value;
-        double Y[D], Hs[S::NH], q[N];
-#pragma unroll
-        for (int r = 0; r < N; ++r) q[r] = qs[(I * N + r) * stride];
-#pragma unroll
-        for (int c = 0; c < D; ++c) Y[c] = w[v][c] + dop853::stage_sum<I>(k, c);
-        S::hess_scaled(q, h, Hs, a.prm);
-#pragma unroll
-        for (int r = 0; r < N; ++r) {
-          double s = 0.0;
-#pragma unroll
-          for (int j = 0; j < N; ++j) s = __builtin_fma(Hs[hidx(N, r, j)], Y[j], s);
-          k[I][r] = h * Y[N + r];
-          k[I][N + r] = -s;
-        }
+        vector_stage<decltype(ic)::value>(a, h, w[v], qs, stride, k);
       });
 #pragma unroll
       for (int c = 0; c < D; ++c) w[v][c] += dop853::final_sum(k, c);
       // one vector pass at a time: overlapped by the scheduler, two passes'
       // stage derivatives would be live together
       __builtin_amdgcn_sched_barrier(0);
-    }
+    });
   }
 
   // Error terms of one component: k holds h-scaled stage derivatives, y the
@@ -242,28 +311,7 @@ struct RKOrbit : LaneOrbit<S, M, GP, -1> {
       double k[12][D];
       double g = 0.0;
       dop853::static_for<0, 12>([&](auto ic) {
-        constexpr int I = decltype(ic)::value;
-        double Y[D], F[N];
-#pragma unroll
-        for (int c = 0; c < D; ++c) Y[c] = x[c] + dop853::stage_sum<I>(k, c);
-        if constexpr (M > 0) {
-#pragma unroll
-          for (int r = 0; r < N; ++r) qs[(I * N + r) * stride] = Y[r];
-        }
-        S::force(Y, F, a.prm);
-        if constexpr (dop853::B[I] != 0.0) {
-          if (do_ld) {
-            double gi = 0.0;
-#pragma unroll
-            for (int r = 0; r < N; ++r) gi += this->ld_term(a, Y[N + r]) + this->ld_term(a, F[r]);
-            g = __builtin_fma(dop853::B[I], gi, g);
-          }
-        }
-#pragma unroll
-        for (int r = 0; r < N; ++r) {
-          k[I][r] = h * Y[N + r];
-          k[I][N + r] = -h * F[r];
-        }
+        state_stage<decltype(ic)::value>(a, h, do_ld, qs, stride, k, g);
       });
 #pragma unroll
       for (int c = 0; c < D; ++c) {
@@ -274,25 +322,11 @@ struct RKOrbit : LaneOrbit<S, M, GP, -1> {
       ldn = do_ld ? __builtin_fma(h, g, ld) : ld;
     }
     __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int v = 0; v < M; ++v) {
+    dop853::static_for<0, M>([&](auto vc) {
+      constexpr int v = decltype(vc)::value;
       double k[12][D];
       dop853::static_for<0, 12>([&](auto ic) {
-        constexpr int I = decltype(ic)::value;
-        double Y[D], Hs[S::NH], q[N];
-#pragma unroll
-        for (int r = 0; r < N; ++r) q[r] = qs[(I * N + r) * stride];
-#pragma unroll
-        for (int c = 0; c < D; ++c) Y[c] = w[v][c] + dop853::stage_sum<I>(k, c);
-        S::hess_scaled(q, h, Hs, a.prm);
-#pragma unroll
-        for (int r = 0; r < N; ++r) {
-          double s = 0.0;
-#pragma unroll
-          for (int j = 0; j < N; ++j) s = __builtin_fma(Hs[hidx(N, r, j)], Y[j], s);
-          k[I][r] = h * Y[N + r];
-          k[I][N + r] = -s;
-        }
+        vector_stage<decltype(ic)::value>(a, h, w[v], qs, stride, k);
       });
 #pragma unroll
       for (int c = 0; c < D; ++c) {
@@ -302,14 +336,15 @@ struct RKOrbit : LaneOrbit<S, M, GP, -1> {
         err_terms(k, c, w[v][c], yn, sb, a.rtol, a.atol, e5, e3);
       }
       __builtin_amdgcn_sched_barrier(0);
-    }
+    });
     const double deno = __builtin_fma(0.01, e3, e5);
     if (!(deno > 0.0)) return deno == 0.0 ? 0.0 : deno;  // NaN stays NaN
     return e5 / sqrt((double)(D * (1 + M)) * deno);
   }
 };
 
-// Dynamic LDS of the DOP853 lane kernels: 12 N doubles per thread.
+// Dynamic LDS of the DOP853 lane kernels: the stage records, 12 QW doubles
+// per thread.
 extern __shared__ double lane_rk_lds[];
 
 template <class S, int M, bool GP>
@@ -345,7 +380,7 @@ __global__ void __launch_bounds__(256) lane_rk_kernel(const StepArgs a) {
 // rejection; rejected: h /= min(1/0.333, q / 0.9)).  A step that would end
 // within 1.01 h of the checkpoint ends on it exactly.  The lanes of a
 // wavefront run their step loops independently (exec-masked) and meet at
-// each checkpoint.  Dynamic LDS per thread: the 12 N stage positions, then
+// each checkpoint.  Dynamic LDS per thread: the 12 QW stage records, then
 // the M D components of the attempted vectors.
 template <class S, int M, bool GP>
 __global__ void __launch_bounds__(256) lane_rka_kernel(const StepArgs a) {
@@ -362,7 +397,7 @@ __global__ void __launch_bounds__(256) lane_rka_kernel(const StepArgs a) {
   double nacc = a.sc[SC_NACC * P + i], nrej = a.sc[SC_NREJ * P + i];
   const int stride = blockDim.x;
   double *qs = lane_rk_lds + threadIdx.x;
-  double *wn = lane_rk_lds + (size_t)12 * N * stride + threadIdx.x;
+  double *wn = lane_rk_lds + (size_t)12 * RKOrbit<S, M, GP>::QW * stride + threadIdx.x;
   const bool do_ld = (a.ind & CHX_IND_LD) != 0;
   int64_t s = a.s_begin;
   const int64_t K = a.K;
@@ -440,10 +475,11 @@ struct LaneRKDispatch {
     constexpr bool adaptive = ADAPT;
     if (m == M) {
       const bool gp = (a.ind & CHX_IND_LD) && a.ld_p != 0.5;
-      // LDS per thread: stage positions, and for the adaptive solver the
+      // LDS per thread: stage records, and for the adaptive solver the
       // attempted vectors; at most 64 KB per block (smaller blocks where
       // needed)
-      const size_t per = M > 0 ? sizeof(double) * (12 * S::N + (adaptive ? M * 2 * S::N : 0)) : 0;
+      constexpr int QW = RKOrbit<S, M, false>::QW;
+      const size_t per = M > 0 ? sizeof(double) * (12 * QW + (adaptive ? M * 2 * S::N : 0)) : 0;
       while (block > 64 && per * (size_t)block > 65536) block /= 2;
       const int64_t grid = (a.n + block - 1) / block;
       const size_t lds = per * (size_t)block;
@@ -454,14 +490,14 @@ struct LaneRKDispatch {
         else
           hipLaunchKernelGGL((lane_rka_kernel<S, M, false>), dim3((unsigned)grid), dim3(block),
                              lds, s, a);
-        return hipGetLastError();
+      } else {
+        if (gp)
+          hipLaunchKernelGGL((lane_rk_kernel<S, M, true>), dim3((unsigned)grid), dim3(block),
+                             lds, s, a);
+        else
+          hipLaunchKernelGGL((lane_rk_kernel<S, M, false>), dim3((unsigned)grid), dim3(block),
+                             lds, s, a);
       }
-      if (gp)
-        hipLaunchKernelGGL((lane_rk_kernel<S, M, true>), dim3((unsigned)grid), dim3(block), lds,
-                           s, a);
-      else
-        hipLaunchKernelGGL((lane_rk_kernel<S, M, false>), dim3((unsigned)grid), dim3(block), lds,
-                           s, a);
       return hipGetLastError();
     }
     return LaneRKDispatch<S, M - 1, ADAPT>::go(m, a, block, s);

@@ -11,6 +11,7 @@
 #include "device_math.h"
 #include "fput_sys.h"
 #include "systems.h"
+#include "systems_dp.h"
 
 namespace chx {
 
@@ -112,7 +113,15 @@ __global__ void init_kernel(StepArgs a, InitArgs ia) {
     a.ge[v * P + i] = 0;
   }
   double gprev = 0.0, H0 = 0.0;
-  if (finite) {
+  if (finite && ia.sys == SYS_DP) {
+    // not separable: H from its own formula, the LD integrand from the field
+    double f[4], rec[SysDP::NREC];
+    SysDP::rhs_rec(x, f, rec, ia.prm);
+    H0 = SysDP::hamiltonian(x, ia.prm);
+    if (ia.ind & CHX_IND_LD)
+      for (int c = 0; c < 4; ++c)
+        gprev += (ia.ld_p == 0.5) ? sqrt(fabs(f[c])) : pow(fabs(f[c]), ia.ld_p);
+  } else if (finite) {
     double F[MAXD / 2];
     sys_force(ia.sys, N, x, ia.prm, F);
     double kin = 0.0;

@@ -108,6 +108,30 @@ def test_dop853_is_for_lane_systems_only():
     assert e.value.status == chx.ERR_UNSUPPORTED and "Yoshida-4" in str(e.value)
 
 
+def test_double_pendulum_validation():
+    dp0 = np.zeros((2, 4))
+    for integ in ("yoshida4",):
+        with pytest.raises(chx.ChxError) as e:
+            chx.integrate_ensemble(P.double_pendulum(), dp0, dt=0.01, T=1.0,
+                                   indicators=chx.IND_SALI, integrator=integ)
+        assert e.value.status == chx.ERR_UNSUPPORTED and "not separable" in str(e.value)
+    with pytest.raises(chx.ChxError) as e:
+        chx.integrate_batched([dict(sys=P.double_pendulum(), x0=dp0, dt=0.01, T=1.0)],
+                              indicators=chx.IND_SALI)
+    assert e.value.status == chx.ERR_UNSUPPORTED
+    for a, s in ((0.0, 1.0), (1.0, -0.5), (-1.0, 1.0)):
+        with pytest.raises(chx.ChxError, match="alpha > 0 and sigma > 0"):
+            chx.integrate_ensemble(P.double_pendulum(a, s), dp0, dt=0.01, T=1.0,
+                                   indicators=chx.IND_SALI, integrator="dop853")
+    with pytest.raises(chx.ChxError, match="ndof == 2"):
+        chx.integrate_ensemble(chx.System(chx.SYS_DOUBLE_PENDULUM, 3, (1.0, 1.0)),
+                               np.zeros((2, 6)), dt=0.01, T=1.0, indicators=chx.IND_SALI,
+                               integrator="dop853")
+    with pytest.raises(chx.ChxError, match="params"):
+        chx.integrate_ensemble(chx.System(chx.SYS_DOUBLE_PENDULUM, 2, (1.0,)), dp0, dt=0.01,
+                               T=1.0, indicators=chx.IND_SALI, integrator="dop853")
+
+
 def test_label_needs_sali():
     with pytest.raises(chx.ChxError, match="label"):
         o = chx.make_options(dt=0.01, T=1.0, indicators=chx.IND_LD)
