@@ -94,48 +94,66 @@ DOP853_ROW_NNZ = (0, 1, 2, 2, 3, 3, 4, 5, 6, 7, 8, 9)
 DOP853_B_NNZ = 8
 
 
+# The double pendulum's field (systems_dp.h), in flops with every add, mul
+# and division counted 1 (so an FMA 2), negations and selects free: the
+# field from the sines and cosines of the angles 39; the derivative parts of
+# its dual-number evaluation along one direction 77 (the value parts are the
+# state's); one sincos_cw 69 (the reduction with its two-sums 28, the two
+# Taylor polynomials 26, the combinations 15); the energy at a checkpoint 80
+# (three cosines at 20 and the quadratic form).
+DP_FIELD, DP_JVP, DP_SINCOS, DP_ENERGY = 39, 77, 69, 80
+
+
 def flops_per_step_dop853(N, m_s, n_l, ld, energy, sali, K, system="hh"):
     """Algorithmic FP64 flops of one orbit-step of the fixed-step DOP853
-    lane kernel for Henon-Heiles (same conventions as flops_per_step): per
-    stage the stage input (one FMA per non-zero a_ij and component, plus the
-    add to the step's start value), one force (state) or step-scaled Hessian
-    and its mat-vec (vectors), the h-scaling of the stage derivative; the
-    final combination (one FMA per non-zero b_i and component, one add);
-    the LD integrand at every stage with a weight; checkpoints as for
-    Yoshida-4, divided by K."""
-    assert system == "hh" and N == 2
+    lane kernel for Henon-Heiles or the double pendulum (same conventions
+    as flops_per_step): per stage the stage input (one FMA per non-zero a_ij
+    and component, plus the add to the step's start value), one force
+    (state) or step-scaled Hessian and its mat-vec (vectors) -- for the
+    double pendulum two sincos and the field (state) or the derivative
+    parts of the dual-number evaluation (vectors) -- the h-scaling of the stage
+    derivative; the final combination (one FMA per non-zero b_i and
+    component, one add); the LD integrand at every stage with a weight;
+    checkpoints as for Yoshida-4, divided by K."""
+    assert system in ("hh", "dp") and N == 2
     M = m_s + n_l
     D = 2 * N
-    force = 2 + 4
-    hess_scaled = 2 + 1 + 2
     sums = 2 * D * sum(DOP853_ROW_NNZ) + D * (len(DOP853_ROW_NNZ) - 1)
     final = 2 * D * DOP853_B_NNZ + D
-    state = sums + 12 * force + 12 * D + final
-    vec = sums + 12 * (hess_scaled + 2 * N * N + N) + final
+    if system == "hh":
+        force = 2 + 4
+        hess_scaled = 2 + 1 + 2
+        state = sums + 12 * force + 12 * D + final
+        vec = sums + 12 * (hess_scaled + 2 * N * N + N) + final
+        e_cost = 14
+    else:
+        state = sums + 12 * (2 * DP_SINCOS + DP_FIELD + D) + final
+        vec = sums + 12 * (DP_JVP + D) + final
+        e_cost = DP_ENERGY
     per = state + M * vec
     if ld:
         per += DOP853_B_NNZ * ((2 * N - 1) + 2) + 2
-    return per + checkpoint_flops_hh(N, m_s, n_l, energy, sali) / K
+    return per + checkpoint_flops_hh(N, m_s, n_l, energy, sali, e_cost) / K
 
 
 def flops_per_attempt_dop853(N, m_s, n_l, ld, system="hh"):
     """Algorithmic FP64 flops of one attempted step of the adaptive DOP8(5)
-    kernel for Henon-Heiles: the fixed step's work (flops_per_step_dop853
-    without checkpoints) plus the error estimate -- per component of the
-    state and the vectors, the fifth-order difference (one FMA per weighted
-    stage), the third-order difference (3 FMA), the scale
+    kernel: the fixed step's work (flops_per_step_dop853 without
+    checkpoints) plus the error estimate -- per component of the state and
+    the vectors, the fifth-order difference (one FMA per weighted stage),
+    the third-order difference (3 FMA), the scale
     atol + rtol max(|y|, |y_new|) (FMA) and two squared ratios (FMA each) --
     and the controller (a handful of operations, counted as 8)."""
-    assert system == "hh" and N == 2
+    assert system in ("hh", "dp") and N == 2
     D = 2 * N
     comps = D * (1 + m_s + n_l)
     err = comps * (2 * DOP853_B_NNZ + 2 * 3 + 2 + 2 * 2)
-    return flops_per_step_dop853(N, m_s, n_l, ld, False, False, 1 << 62) + err + 8
+    return flops_per_step_dop853(N, m_s, n_l, ld, False, False, 1 << 62, system) + err + 8
 
 
-def checkpoint_flops_hh(N, m_s, n_l, energy, sali):
-    """Flops of one Henon-Heiles checkpoint: renormalisation of the
-    SALI/GALI set, SALI, modified Gram-Schmidt of the Lyapunov set, energy."""
+def checkpoint_flops_hh(N, m_s, n_l, energy, sali, energy_cost=14):
+    """Flops of one checkpoint: renormalisation of the SALI/GALI set, SALI,
+    modified Gram-Schmidt of the Lyapunov set, energy (Henon-Heiles: 14)."""
     D = 2 * N
     ck = 0
     norm = 2 * D - 1 + D + 1  # |w|^2, rescale, growth product
@@ -145,7 +163,7 @@ def checkpoint_flops_hh(N, m_s, n_l, energy, sali):
     for j in range(n_l):
         ck += j * ((2 * D - 1) + 2 * D) + norm  # projections + normalisation
     if energy:
-        ck += 14  # H (kinetic 2 FMA, potential 5 ops) and |H - H0|
+        ck += energy_cost  # Henon-Heiles: kinetic 2 FMA, potential 5 ops, |H - H0|
     return ck
 
 
@@ -699,13 +717,115 @@ def bench_sweep(args, P, chx, torch, dev):
                  "launch_ms": None, "launches_timed": None}, None)
 
 
+def dp_angle_grid(k):
+    """2^k double-pendulum states from rest: cell centres of a
+    2^ceil(k/2) x 2^floor(k/2) grid of (theta_1, theta_2) over (-pi, pi)^2."""
+    import numpy as np
+    n1, n2 = 1 << ((k + 1) // 2), 1 << (k // 2)
+    t1 = -np.pi + (np.arange(n1) + 0.5) * (2 * np.pi / n1)
+    t2 = -np.pi + (np.arange(n2) + 0.5) * (2 * np.pi / n2)
+    a, b = np.meshgrid(t1, t2, indexing="ij")
+    z = np.zeros(a.size)
+    return np.stack([a.ravel(), b.ravel(), z, z], axis=1)
+
+
+def bench_dp(args, P, chx, torch, dev):
+    """The double-pendulum timing figure: alpha = sigma = 1, states from rest
+    on a grid of angles over (-pi, pi)^2, SALI (two vectors) + energy, final
+    time 1e3; time per initial condition against the number integrated
+    together (2^8 .. 2^19), with the fixed-step DOP853 (dt = 0.02) and the
+    adaptive DOP8(5) (rtol = atol = 1e-11, first step 0.1, checkpoints every
+    1): both hold the energy error near 1e-9.  Each point is one whole call (set-up, integration, results).  The
+    value is the largest ensemble's fixed-step ICs/s; the roofline is that
+    run's integration kernel, timed launch by launch."""
+    import numpy as np
+
+    T = args.T or 1e3
+    ind = chx.IND_SALI | chx.IND_ENERGY
+    legs = {"dop853": dict(dt=0.02, integrator="dop853"),
+            "dop853_adaptive": dict(dt=0.1, integrator="dop853_adaptive", rtol=1e-11,
+                                    atol=1e-11)}
+    sizes = (8, 10, 12, 14, 16, 17, 18, 19)
+    sysd = P.double_pendulum(1.0, 1.0)
+    stream = torch.cuda.current_stream()
+    rows = {k: [] for k in legs}
+    extra = {}
+    for _ in range(args.warmup):
+        x = torch.as_tensor(dp_angle_grid(8), device=dev)
+        for leg in legs.values():
+            P.integrate_ensemble(sysd, x, T=T, indicators=ind, seed=7, outputs=("label",), **leg)
+    torch.cuda.synchronize()
+    log = []
+    t_all = time.perf_counter()
+    for name, leg in legs.items():
+        for k in sizes:
+            x = torch.as_tensor(dp_angle_grid(k), device=dev)
+            n = x.shape[0]
+            n_steps = int(round(T / leg["dt"]))
+            spl = min(10000, n_steps)
+            last = (k == sizes[-1]) and name == "dop853"
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e = P.Ensemble(sysd, x, steps_per_launch=spl, T=T, indicators=ind, seed=7,
+                           outputs=("label", "energy_err", "steps") if name != "dop853"
+                           else ("label", "energy_err"), **leg)
+            advance_timed(e, n_steps, spl, stream, torch, log if last else None)
+            out = e.results()
+            e.close()
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            lab = out["label"].cpu().numpy()
+            row = {"ics": n, "s": sec, "us_per_ic": sec * 1e6 / n, "ics_per_s": n / sec,
+                   "max_energy_error": float(out["energy_err"].cpu().numpy().max()),
+                   "chaotic_fraction": float(np.mean(lab == 1))}
+            if "steps" in out:
+                st = out["steps"].cpu().numpy()
+                row["accepted_steps_per_ic"] = float(st[:, 0].mean())
+                row["rejected_steps_per_ic"] = float(st[:, 1].mean())
+            rows[name].append(row)
+            progress(f"dp {name}: {n} ICs, {sec:.3f} s, {row['us_per_ic']:.3f} us per IC")
+    elapsed = time.perf_counter() - t_all
+    big = rows["dop853"][-1]
+    n_big = big["ics"]
+    kernel_s = sum(a.elapsed_time(b) for a, b, _ in log) * 1e-3
+    fps = flops_per_step_dop853(2, 2, 0, False, True, True, 10, system="dp")
+    achieved = fps * n_big * int(round(T / legs["dop853"]["dt"])) / kernel_s
+    cpu = None
+    if not args.no_cpu_baseline:
+        import seeded_inputs as S
+        from oracle import oracle as O
+        threads = max(1, min(16, len(os.sched_getaffinity(0))))
+        xg = dp_angle_grid(sizes[-1])
+        ns = 48
+        idx = np.linspace(0, len(xg) - 1, ns).astype(int)
+        w0 = S.deviation_vectors(7, ns, 2, 4)
+        run = O.Run(dt=legs["dop853"]["dt"], T=T, indicators=ind, integrator=O.INT_DOP853)
+        t2 = time.perf_counter()
+        O.integrate(O.double_pendulum(1.0, 1.0), xg[idx], run, w0=w0, threads=threads)
+        el = time.perf_counter() - t2
+        cpu = {"value": ns / el, "unit": "ICs/s", "cores": threads, "kind": "oracle",
+               "sample": f"{ns} strided grid states, fixed-step DOP853 to T={T:g} ({el:.1f} s)"}
+    return emit(args, "double-pendulum ICs/s (fixed-step DOP853)", big["ics_per_s"], "ICs/s",
+                elapsed, "f64", {
+                    "workload": f"double pendulum alpha=sigma=1 from rest on (theta_1, theta_2) "
+                                f"grids over (-pi, pi)^2, SALI (2 vectors)+energy, T={T:g}; "
+                                "fixed-step DOP853 dt=0.02 and adaptive DOP8(5) rtol=atol=1e-11; "
+                                "2^8..2^19 ICs per call (set-up and results included)",
+                    "sweep": rows, "kernel_s_largest_fixed": kernel_s},
+                {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
+                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
+                 "kernel": "chx::lane_rk_kernel<SysDP, 2, false>", "flops_per_orbit_step": fps,
+                 "launch_ms": kernel_s * 1e3 / max(len(log), 1), "launches_timed": len(log)},
+                cpu)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", choices=("hh", "fput", "batched", "gate", "sweep", "dop853",
-                                           "dop853_adaptive"),
+                                           "dop853_adaptive", "dp"),
                     default="hh",
                     help="hh: the headline Henon-Heiles grids (default); fput: FPU-beta "
                          "chains with 3N deviation vectors; batched: the persistent mixed "
@@ -713,7 +833,8 @@ def parse():
                          "form; sweep: time per orbit against the ensemble size; dop853: "
                          "the headline grids with the fixed-step DOP853 integrator; "
                          "dop853_adaptive: the adaptive DOP8(5) solver on the E=0.125 grid "
-                         "against fixed-step Yoshida-4")
+                         "against fixed-step Yoshida-4; dp: the double pendulum's time per "
+                         "IC against the ensemble size, fixed and adaptive")
     ap.add_argument("--grid", type=int, default=1024, help="grid side per energy")
     ap.add_argument("--T", type=float, default=None,
                     help="final time (default: 1e4 for hh, gate and batched, 2e3 for fput, "
@@ -758,7 +879,7 @@ def main():
     if args.workload != "hh":
         fn = {"fput": bench_fput, "batched": bench_batched, "gate": bench_gate,
               "sweep": bench_sweep, "dop853": bench_dop853,
-              "dop853_adaptive": bench_dop853_adaptive}[args.workload]
+              "dop853_adaptive": bench_dop853_adaptive, "dp": bench_dp}[args.workload]
         print(json.dumps(fn(args, P, chx, torch, dev)), flush=True)
         return
     if args.T is None:

@@ -163,6 +163,56 @@ struct RKOrbit : LaneOrbit<S, M, GP, -1> {
   // the positions.
   static constexpr bool GEN = has_hamiltonian<S>::value;
   static constexpr int QW = rec_width<S, GEN>();  // LDS doubles per stage and thread
+  // With one or two vectors a general system integrates the state and the
+  // vectors stage by stage in one pass: one evaluation on multi-dual
+  // numbers gives the field and every vector's derivative (the values
+  // shared), all stage derivatives stay in registers and no record goes
+  // through LDS.  (The records' LDS would hold the kernel to one wavefront
+  // per SIMD anyway, which leaves the register file to the pass.)
+  static constexpr bool FUSED = GEN && M >= 1 && M <= 2;
+  static constexpr int LDS_STAGE = FUSED ? 0 : QW;  // LDS doubles per stage and thread
+
+  // Stage I of the state and the vectors together (FUSED): Y = x +
+  // sum_j a_Ij k_j, dY_v = w_v + sum_j a_Ij kv_vj; k_I = h f(Y),
+  // kv_vI = h Df(Y) dY_v; the LD integrand at weighted stages into g.
+  template <int I>
+  __device__ __forceinline__ void fused_stage(const StepArgs &a, double h, bool do_ld,
+                                              double (&k)[12][D], double (&kv)[M][12][D],
+                                              double &g) {
+    double Y[D], dY[M][D], f[D], df[M][D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) Y[c] = x[c] + dop853::stage_sum<I>(k, c);
+#pragma unroll
+    for (int v = 0; v < M; ++v)
+#pragma unroll
+      for (int c = 0; c < D; ++c) dY[v][c] = w[v][c] + dop853::stage_sum<I>(kv[v], c);
+    S::template rhs_multi<M>(Y, dY, f, df, a.prm);
+    if constexpr (dop853::B[I] != 0.0) {
+      if (do_ld) {
+        double gi = 0.0;
+#pragma unroll
+        for (int c = 0; c < D; ++c) gi += this->ld_term(a, f[c]);
+        g = __builtin_fma(dop853::B[I], gi, g);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < D; ++c) k[I][c] = h * f[c];
+#pragma unroll
+    for (int v = 0; v < M; ++v)
+#pragma unroll
+      for (int c = 0; c < D; ++c) kv[v][I][c] = h * df[v][c];
+    // each stage's derivative parts finish inside the stage: left free, the
+    // scheduler runs the value chain ahead through all twelve stages and
+    // keeps every stage's dual-number intermediates live for the deferred
+    // derivative parts, far beyond the register file
+#pragma unroll
+    for (int v = 0; v < M; ++v)
+#pragma unroll
+      for (int c = 0; c < D; ++c) asm volatile("" : "+v"(kv[v][I][c]));
+#pragma unroll
+    for (int c = 0; c < D; ++c) asm volatile("" : "+v"(k[I][c]));
+    __builtin_amdgcn_sched_barrier(0);
+  }
 
   // Stage I of the state: Y = x + sum_j a_Ij k_j; its LDS record; the LD
   // integrand sum |dY/dt|^p at weighted stages into g; k_I = h f(Y).
@@ -252,6 +302,21 @@ struct RKOrbit : LaneOrbit<S, M, GP, -1> {
   // qs: this thread's stage records in LDS, component f at qs[f * stride]
   __device__ __forceinline__ void rk_step(const StepArgs &a, double h, bool do_ld, double *qs,
                                           int stride) {
+    if constexpr (FUSED) {
+      double k[12][D], kv[M][12][D];
+      double g = 0.0;
+      dop853::static_for<0, 12>([&](auto ic) {
+        fused_stage<decltype(ic)::value>(a, h, do_ld, k, kv, g);
+      });
+#pragma unroll
+      for (int c = 0; c < D; ++c) x[c] += dop853::final_sum(k, c);
+#pragma unroll
+      for (int v = 0; v < M; ++v)
+#pragma unroll
+        for (int c = 0; c < D; ++c) w[v][c] += dop853::final_sum(kv[v], c);
+      if (do_ld) ld = __builtin_fma(h, g, ld);
+      return;
+    }
     {
       double k[12][D];  // h f(Y_i) of the state
       double g = 0.0;   // sum_i b_i (LD integrand at stage i)
@@ -307,11 +372,11 @@ struct RKOrbit : LaneOrbit<S, M, GP, -1> {
                                                double *qs, double *wn, int stride,
                                                double (&xn)[D], double &ldn) {
     double e5 = 0.0, e3 = 0.0;
-    {
-      double k[12][D];
+    if constexpr (FUSED) {
+      double k[12][D], kv[M][12][D];
       double g = 0.0;
       dop853::static_for<0, 12>([&](auto ic) {
-        state_stage<decltype(ic)::value>(a, h, do_ld, qs, stride, k, g);
+        fused_stage<decltype(ic)::value>(a, h, do_ld, k, kv, g);
       });
 #pragma unroll
       for (int c = 0; c < D; ++c) {
@@ -320,23 +385,47 @@ struct RKOrbit : LaneOrbit<S, M, GP, -1> {
         err_terms(k, c, x[c], xn[c], sb, a.rtol, a.atol, e5, e3);
       }
       ldn = do_ld ? __builtin_fma(h, g, ld) : ld;
-    }
-    __builtin_amdgcn_sched_barrier(0);
-    dop853::static_for<0, M>([&](auto vc) {
-      constexpr int v = decltype(vc)::value;
-      double k[12][D];
-      dop853::static_for<0, 12>([&](auto ic) {
-        vector_stage<decltype(ic)::value>(a, h, w[v], qs, stride, k);
-      });
 #pragma unroll
-      for (int c = 0; c < D; ++c) {
-        const double sb = dop853::final_sum(k, c);
-        const double yn = w[v][c] + sb;
-        wn[(v * D + c) * stride] = yn;
-        err_terms(k, c, w[v][c], yn, sb, a.rtol, a.atol, e5, e3);
+      for (int v = 0; v < M; ++v)
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          const double sb = dop853::final_sum(kv[v], c);
+          const double yn = w[v][c] + sb;
+          wn[(v * D + c) * stride] = yn;
+          err_terms(kv[v], c, w[v][c], yn, sb, a.rtol, a.atol, e5, e3);
+        }
+    } else {
+      {
+        double k[12][D];
+        double g = 0.0;
+        dop853::static_for<0, 12>([&](auto ic) {
+          state_stage<decltype(ic)::value>(a, h, do_ld, qs, stride, k, g);
+        });
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          const double sb = dop853::final_sum(k, c);
+          xn[c] = x[c] + sb;
+          err_terms(k, c, x[c], xn[c], sb, a.rtol, a.atol, e5, e3);
+        }
+        ldn = do_ld ? __builtin_fma(h, g, ld) : ld;
       }
       __builtin_amdgcn_sched_barrier(0);
-    });
+      dop853::static_for<0, M>([&](auto vc) {
+        constexpr int v = decltype(vc)::value;
+        double k[12][D];
+        dop853::static_for<0, 12>([&](auto ic) {
+          vector_stage<decltype(ic)::value>(a, h, w[v], qs, stride, k);
+        });
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          const double sb = dop853::final_sum(k, c);
+          const double yn = w[v][c] + sb;
+          wn[(v * D + c) * stride] = yn;
+          err_terms(k, c, w[v][c], yn, sb, a.rtol, a.atol, e5, e3);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      });
+    }
     const double deno = __builtin_fma(0.01, e3, e5);
     if (!(deno > 0.0)) return deno == 0.0 ? 0.0 : deno;  // NaN stays NaN
     return e5 / sqrt((double)(D * (1 + M)) * deno);
@@ -397,7 +486,7 @@ __global__ void __launch_bounds__(256) lane_rka_kernel(const StepArgs a) {
   double nacc = a.sc[SC_NACC * P + i], nrej = a.sc[SC_NREJ * P + i];
   const int stride = blockDim.x;
   double *qs = lane_rk_lds + threadIdx.x;
-  double *wn = lane_rk_lds + (size_t)12 * RKOrbit<S, M, GP>::QW * stride + threadIdx.x;
+  double *wn = lane_rk_lds + (size_t)12 * RKOrbit<S, M, GP>::LDS_STAGE * stride + threadIdx.x;
   const bool do_ld = (a.ind & CHX_IND_LD) != 0;
   int64_t s = a.s_begin;
   const int64_t K = a.K;
@@ -478,7 +567,7 @@ struct LaneRKDispatch {
       // LDS per thread: stage records, and for the adaptive solver the
       // attempted vectors; at most 64 KB per block (smaller blocks where
       // needed)
-      constexpr int QW = RKOrbit<S, M, false>::QW;
+      constexpr int QW = RKOrbit<S, M, false>::LDS_STAGE;
       const size_t per = M > 0 ? sizeof(double) * (12 * QW + (adaptive ? M * 2 * S::N : 0)) : 0;
       while (block > 64 && per * (size_t)block > 65536) block /= 2;
       const int64_t grid = (a.n + block - 1) / block;
