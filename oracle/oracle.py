@@ -397,3 +397,99 @@ def quartic_ic(sys, draws):
     lib().ora_quartic_ic(sys.ndof, _p(pr), _p(draws), len(draws), _p(x0))
     return x0
 
+
+
+# --- chaos indicators from the LDs of neighbouring orbits ------------------
+#
+# Functionalities section: chaos indicators based on Lagrangian descriptors,
+# with the generation of neighbouring trajectories for them; the paper
+# defers their definitions to the works it cites.  Reading taken here:
+#   * L(x) = M+(x) + M-(x), the p-norm M-function over [-T, T] (forward and
+#     backward parts; forward only when two_sided is False);
+#   * the backward part of an orbit of a Hamiltonian even in the momenta is
+#     the forward part of its momentum-reversed state: x(-t) = R y(t) with
+#     y the orbit of R x, R(q, p) = (q, -p), and |dx/dt| has the same
+#     components along both, so M-(x) = M+(R x);
+#   * neighbours y_i^(+/-) = x +/- sigma e_{d_i} along the chosen phase-space
+#     coordinates d_1..d_n;
+#   * D = (1/2n) sum_i (|L(x) - L(y_i^+)| + |L(x) - L(y_i^-)|) / L(x),
+#     R = |1 - (1/2n) sum_i (L(y_i^+) + L(y_i^-)) / L(x)|,
+#     S = (1/n) sum_i |L(y_i^+) - 2 L(x) + L(y_i^-)| / L(x)
+#     (difference, ratio and second derivative of the LDs of neighbouring
+#     orbits);
+#   * an initial condition whose own orbit or any neighbour's (forward or
+#     backward) stops early reports the worst status (non-finite over
+#     step failure over escape) and NaN indicators; masked ones status 1.
+
+def ldn_members(x0, dirs, sigma, two_sided=True):
+    """The orbits an indicator needs, [n][nb][nm][2N]: b = 0 forward
+    states, b = 1 momentum-reversed ones (two_sided); m = 0 the state
+    itself, m = 2i+1 and 2i+2 the neighbours +sigma e_{dirs[i]} and
+    -sigma e_{dirs[i]}."""
+    x0 = np.asarray(x0, dtype=np.float64)
+    n, D = x0.shape
+    N = D // 2
+    nb, nm = (2 if two_sided else 1), 1 + 2 * len(dirs)
+    out = np.zeros((n, nb, nm, D))
+    for j in range(n):
+        for m in range(nm):
+            y = x0[j].copy()
+            if m > 0:
+                c = dirs[(m - 1) // 2]
+                y[c] = y[c] + (sigma if m % 2 == 1 else -sigma)
+            out[j, 0, m] = y
+            if two_sided:
+                r = y.copy()
+                r[N:] = -r[N:]
+                out[j, 1, m] = r
+    return out
+
+
+def ldn_combine(ld, status):
+    """Indicators from the members' LDs [n][nb][nm] and statuses."""
+    n, nb, nm = ld.shape
+    k = (nm - 1) // 2
+    L = ld.sum(axis=1)
+    res = {"ld": np.full(n, np.nan), "D": np.full(n, np.nan), "R": np.full(n, np.nan),
+           "S": np.full(n, np.nan), "status": np.zeros(n, np.int32)}
+    rank = {ST_OK: 0, ST_ESCAPED: 1, ST_STEPFAIL: 2, ST_NONFINITE: 3}
+    for j in range(n):
+        worst = ST_OK
+        for s in status[j].ravel():
+            if rank[int(s)] > rank[worst]:
+                worst = int(s)
+        res["status"][j] = worst
+        if worst != ST_OK:
+            continue
+        c = L[j, 0]
+        d = r = s2 = 0.0
+        for i in range(k):
+            lp, lm = L[j, 2 * i + 1], L[j, 2 * i + 2]
+            d += abs(c - lp) + abs(c - lm)
+            r += lp + lm
+            s2 += abs(lp - 2.0 * c + lm)
+        res["ld"][j] = c
+        res["D"][j] = d / (2 * k) / c
+        res["R"][j] = abs(1.0 - r / (2 * k) / c)
+        res["S"][j] = s2 / k / c
+    return res
+
+
+def ld_indicators(sys, x0, run, dirs, sigma, two_sided=True, mask=None, threads=1):
+    """D, R, S and L of each initial condition (reading above); run gives
+    the integrator, dt, T, ld_p and escape radius (its indicators are
+    replaced by the LD alone)."""
+    x0 = np.ascontiguousarray(x0, dtype=np.float64).reshape(-1, 2 * sys.ndof)
+    n = len(x0)
+    mem = ldn_members(x0, dirs, sigma, two_sided)
+    nb, nm = mem.shape[1], mem.shape[2]
+    r2 = Run(dt=run.dt, T=run.T, indicators=IND_LD, K=run.K, ld_p=run.ld_p,
+             escape_r2=run.escape_r2, integrator=run.integrator, rtol=run.rtol, atol=run.atol)
+    out = integrate(sys, mem.reshape(-1, 2 * sys.ndof), r2, threads=threads)
+    res = ldn_combine(out["ld"].reshape(n, nb, nm), out["status"].reshape(n, nb, nm))
+    if mask is not None:
+        off = np.asarray(mask) == 0
+        for k in ("ld", "D", "R", "S"):
+            res[k][off] = np.nan
+        res["status"][off] = ST_MASKED
+    return res
