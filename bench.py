@@ -819,13 +819,117 @@ def bench_dp(args, P, chx, torch, dev):
                 cpu)
 
 
+def auc(score, label):
+    """Area under the ROC curve of score for label 1 against label 0 (ties
+    counted half): the probability that a random chaotic orbit scores above
+    a random regular one."""
+    import numpy as np
+    s1, s0 = np.sort(score[label == 1]), np.sort(score[label == 0])
+    if len(s1) == 0 or len(s0) == 0:
+        return None
+    lo = np.searchsorted(s0, s1, side="left")
+    hi = np.searchsorted(s0, s1, side="right")
+    return float((lo.sum() + 0.5 * (hi - lo).sum()) / (len(s1) * len(s0)))
+
+
+def bench_ldn(args, P, chx, torch, dev):
+    """Chaos indicators from the two-sided LDs of neighbouring orbits on the
+    Henon-Heiles section grid at E = 0.125 (1024^2, 850,874 accessible ICs):
+    neighbours at +/- 1e-3 along y and p_y, T = 200 forward and backward
+    (ten member orbits per IC, LD only, Yoshida-4 at dt = 0.01).  Value =
+    ICs/s of the whole call; the indicators are scored against SALI labels
+    of the same grid at T = 1e4 (the headline's ground truth, integrated in
+    the same run) by the area under the ROC curve and the best single
+    threshold's agreement."""
+    import numpy as np
+
+    T = args.T or 200.0
+    dt, sigma, E = 0.01, 1e-3, 0.125
+    n_side = args.grid
+    x0, mask = P.grid_hh_section(E, n_side, n_side, device=dev)
+    m = mask.cpu().numpy().astype(bool)
+    stream = torch.cuda.current_stream()
+    kw = dict(dt=dt, T=T, block_size=args.block)
+
+    def one():
+        return P.ld_indicators(P.henon_heiles(), x0, sigma, dirs=[1, 3], mask=mask, **kw)
+
+    for _ in range(args.warmup):
+        one()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        out = one()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    gpu_s = e0.elapsed_time(e1) * 1e-3 / args.steps
+    n_act = int(m.sum())
+    value = n_act * args.steps / elapsed
+    progress(f"ldn: {n_act} ICs x 10 member orbits, T={T:g}: {elapsed / args.steps:.3f} s per call")
+    # ground truth: SALI labels at T = 1e4 on the same grid
+    ref = P.integrate_ensemble(P.henon_heiles(), x0, mask=mask, dt=0.01, T=1e4,
+                               indicators=chx.IND_SALI, seed=1002, outputs=("label",))
+    lab = ref["label"].cpu().numpy()[m]
+    st = out["status"].cpu().numpy()[m]
+    ok = (st == 0) & (lab >= 0) & (lab <= 1)
+    scores = {}
+    for k in ("D", "R", "S"):
+        v = out[k].cpu().numpy()[m][ok]
+        lv = np.log10(np.maximum(v, 1e-300))
+        a = auc(lv, lab[ok])
+        order = np.argsort(lv)
+        ls = lab[ok][order]
+        # best threshold: chaotic iff score > t; agreement over all cut points
+        chaotic_above = np.concatenate([[0], np.cumsum(ls[::-1])])[::-1]
+        regular_below = np.concatenate([[0], np.cumsum(1 - ls)])
+        agree = (chaotic_above + regular_below) / len(ls)
+        scores[k] = {"auc": a, "best_threshold_agreement": float(agree.max())}
+    n_orbits = n_act * 10
+    n_steps = int(round(T / dt))
+    fps = flops_per_step(2, 0, 0, True, False, False, 10)
+    achieved = fps * n_orbits * n_steps / gpu_s
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        threads = max(1, min(16, len(os.sched_getaffinity(0))))
+        xg, mg = O.hh_grid(E, n_side, n_side)
+        act = np.flatnonzero(mg)
+        ns = 512
+        idx = act[np.linspace(0, len(act) - 1, ns).astype(int)]
+        t2 = time.perf_counter()
+        O.ld_indicators(O.henon_heiles(), xg[idx], O.Run(dt=dt, T=T, indicators=O.IND_LD),
+                        [1, 3], sigma, threads=threads)
+        el = time.perf_counter() - t2
+        cpu = {"value": ns / el, "unit": "ICs/s", "cores": threads, "kind": "oracle",
+               "sample": f"{ns} strided grid ICs, the same indicators ({el:.1f} s)"}
+    return emit(args, "ICs/s (LD indicators from neighbouring orbits)", value, "ICs/s", elapsed,
+                "f64", {
+                    "workload": f"henon-heiles {n_side}x{n_side} section grid at E=0.125, "
+                                f"neighbours +/-{sigma:g} along y and p_y, two-sided LD over "
+                                f"[-{T:g}, {T:g}] (10 member orbits per IC, Yoshida-4 dt={dt}); "
+                                "D, R, S scored against SALI labels at T=1e4",
+                    "ics": n_act, "member_orbits": n_orbits, "gpu_s_per_call": gpu_s,
+                    "chaotic_fraction_sali": float(np.mean(lab[ok] == 1)),
+                    "scores_log10": scores,
+                    "statuses": {int(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))}},
+                {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
+                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
+                 "kernel": "chx::lane_kernel<SysHH, 0, false> (whole call, set-up included)",
+                 "flops_per_orbit_step": fps, "launch_ms": None, "launches_timed": None},
+                cpu)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", choices=("hh", "fput", "batched", "gate", "sweep", "dop853",
-                                           "dop853_adaptive", "dp"),
+                                           "dop853_adaptive", "dp", "ldn"),
                     default="hh",
                     help="hh: the headline Henon-Heiles grids (default); fput: FPU-beta "
                          "chains with 3N deviation vectors; batched: the persistent mixed "
@@ -834,7 +938,8 @@ def parse():
                          "the headline grids with the fixed-step DOP853 integrator; "
                          "dop853_adaptive: the adaptive DOP8(5) solver on the E=0.125 grid "
                          "against fixed-step Yoshida-4; dp: the double pendulum's time per "
-                         "IC against the ensemble size, fixed and adaptive")
+                         "IC against the ensemble size, fixed and adaptive; ldn: chaos "
+                         "indicators from the LDs of neighbouring orbits against SALI labels")
     ap.add_argument("--grid", type=int, default=1024, help="grid side per energy")
     ap.add_argument("--T", type=float, default=None,
                     help="final time (default: 1e4 for hh, gate and batched, 2e3 for fput, "
@@ -879,7 +984,8 @@ def main():
     if args.workload != "hh":
         fn = {"fput": bench_fput, "batched": bench_batched, "gate": bench_gate,
               "sweep": bench_sweep, "dop853": bench_dop853,
-              "dop853_adaptive": bench_dop853_adaptive, "dp": bench_dp}[args.workload]
+              "dop853_adaptive": bench_dop853_adaptive, "dp": bench_dp,
+              "ldn": bench_ldn}[args.workload]
         print(json.dumps(fn(args, P, chx, torch, dev)), flush=True)
         return
     if args.T is None:

@@ -213,6 +213,49 @@ chx_status chx_lyap_spectrum(const chx_system *sys, const double *x0, int64_t n,
 chx_status chx_ld(const chx_system *sys, const double *x0, int64_t n, double dt,
                   double T, double p, double *ld_out /* [n] */);
 
+/* Chaos indicators from the Lagrangian descriptors of neighbouring orbits
+ * (Functionalities section: chaos indicators based on Lagrangian
+ * descriptors, and the generation of neighbouring trajectories for them;
+ * the paper defers their definitions to the works it cites, and these are
+ * the forms used here).  For each initial condition x:
+ *   L(x) = M+(x) + M-(x): the M-function of chx_ld over [0, T] plus the
+ *     same over [-T, 0] (two_sided; M+ alone otherwise).  M- is computed as
+ *     M+ of the momentum-reversed state (q, -p): every built-in Hamiltonian
+ *     is even in the momenta, so the backward orbit is the reflection of
+ *     that forward orbit and |dx/dt| has the same components;
+ *   neighbours y_i^(+/-) = x +/- sigma e_c for each coordinate c of the 2N
+ *     phase-space coordinates whose bit is set in dirs (n of them);
+ *   D = (1/2n) sum_i (|L(x) - L(y_i^+)| + |L(x) - L(y_i^-)|) / L(x)
+ *     (difference), R = |1 - (1/2n) sum_i (L(y_i^+) + L(y_i^-)) / L(x)|
+ *     (ratio), S = (1/n) sum_i |L(y_i^+) - 2 L(x) + L(y_i^-)| / L(x)
+ *     (second derivative).
+ * The (1 + 2n) x (2 if two_sided) orbits per initial condition are built on
+ * the device and integrated as one ensemble with the LD alone (no
+ * variational equations); opt gives dt, T, ld_p, the integrator (and
+ * rtol/atol), escape_r2, steps_per_launch, block_size, flags and stream;
+ * opt->indicators must be 0 or CHX_IND_LD, opt->w0 NULL, early_exit 0.
+ * x0 [n][2N], mask [n] or NULL; all pointers host or device per
+ * opt->flags.  Output status[i]: CHX_ORBIT_MASKED for masked initial
+ * conditions; otherwise the worst over the member orbits (NONFINITE over
+ * STEP_FAILED over ESCAPED over OK), and NaN indicators unless OK.  Device
+ * memory of about (1 + 2n)(2)(2N + 30) doubles per initial condition is
+ * held during the call.  Any NULL output is skipped. */
+typedef struct {
+  uint32_t dirs;     /* bit c: neighbours along coordinate c; 0 -> all 2N */
+  double sigma;      /* neighbour distance, finite and > 0 */
+  int32_t two_sided; /* non-zero: L over [-T, T]; 0: over [0, T] */
+} chx_ldn_options;
+typedef struct {
+  double *ld;       /* [n] L(x) */
+  double *D;        /* [n] */
+  double *R;        /* [n] */
+  double *S;        /* [n] */
+  int32_t *status;  /* [n] */
+} chx_ldn_result;
+chx_status chx_ld_indicators(const chx_system *sys, const double *x0, const uint8_t *mask,
+                             int64_t n, const chx_options *opt, const chx_ldn_options *lo,
+                             chx_ldn_result *res);
+
 /* Resumable ensemble: checkpoint/resume and chunked launches.  create
  * validates and uploads (no steps); advance integrates up to step s_end,
  * which must be a checkpoint step (a multiple of K, or the last step);
@@ -379,8 +422,8 @@ const char *chx_last_error(void);
 const char *chx_version(void);
 /* sizeof(chx_system), sizeof(chx_options), sizeof(chx_result),
  * sizeof(chx_batch_item), sizeof(chx_batch_stats), sizeof(chx_gate_train_cfg),
- * sizeof(chx_gate_stats) for which = 0..6 (0 otherwise): lets a binding
- * check its struct layouts. */
+ * sizeof(chx_gate_stats), sizeof(chx_ldn_options), sizeof(chx_ldn_result) for
+ * which = 0..8 (0 otherwise): lets a binding check its struct layouts. */
 size_t chx_struct_size(int32_t which);
 
 #ifdef __cplusplus

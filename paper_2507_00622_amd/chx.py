@@ -110,6 +110,8 @@ def lib():
         L.chx_options_default.argtypes = [O]
         L.chx_options_default.restype = None
         L.chx_integrate_ensemble.argtypes = [S, P, P, i64, O, R]
+        L.chx_ld_indicators.argtypes = [S, P, P, i64, O, C.POINTER(_LdnOptions),
+                                        C.POINTER(_LdnResult)]
         L.chx_sali.argtypes = [S, P, i64, d, d, u64, P, P]
         L.chx_gali.argtypes = [S, P, i64, d, d, i32, u64, P]
         L.chx_lyap_spectrum.argtypes = [S, P, i64, d, d, i32, i32, P]
@@ -393,6 +395,48 @@ def integrate_ensemble(sys, x0, mask=None, w0=None, outputs=None, **opts):
     keep = (x0a, ma, w0a)  # noqa: F841 -- alive until the call returns
     cs = sys._c()
     _check(lib().chx_integrate_ensemble(C.byref(cs), px0, pm, n, C.byref(o), C.byref(res)))
+    return out
+
+
+class _LdnOptions(C.Structure):
+    _fields_ = [("dirs", C.c_uint32), ("sigma", C.c_double), ("two_sided", C.c_int32)]
+
+
+LDN_FIELDS = ["ld", "D", "R", "S", "status"]
+
+
+class _LdnResult(C.Structure):
+    _fields_ = [(f, C.c_void_p) for f in LDN_FIELDS]
+
+
+def ld_indicators(sys, x0, sigma, dirs=None, two_sided=True, mask=None, outputs=None, **opts):
+    """chx_ld_indicators: the difference D, ratio R and second derivative S
+    of the (two-sided) LDs of each initial condition and its neighbours at
+    +/- sigma along the coordinates in dirs (a list of indices into the 2N
+    phase-space coordinates, or None for all); opts as for
+    integrate_ensemble (indicators defaults to the LD).  Returns a dict of
+    the requested outputs among LDN_FIELDS."""
+    arr = _Arrays(x0)
+    opts.setdefault("indicators", IND_LD)
+    o = make_options(**opts)
+    o.flags, o.stream = arr.flags, arr.stream
+    x0a, px0 = arr.inp(x0, np.float64)
+    n = int(x0a.shape[0])
+    ma, pm = arr.inp(mask, np.uint8)
+    lo = _LdnOptions()
+    lo.dirs = 0 if dirs is None else sum(1 << int(c) for c in dirs)
+    lo.sigma, lo.two_sided = float(sigma), int(bool(two_sided))
+    want = set(LDN_FIELDS if outputs is None else outputs)
+    res, out = _LdnResult(), {}
+    for f in LDN_FIELDS:
+        if f in want:
+            a, p = arr.out((n,), np.int32 if f == "status" else np.float64)
+            out[f] = a
+            setattr(res, f, p)
+    keep = (x0a, ma)  # noqa: F841 -- alive until the call returns
+    cs = sys._c()
+    _check(lib().chx_ld_indicators(C.byref(cs), px0, pm, n, C.byref(o), C.byref(lo),
+                                   C.byref(res)))
     return out
 
 

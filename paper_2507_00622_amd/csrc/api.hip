@@ -591,6 +591,8 @@ size_t chx_struct_size(int32_t which) {
   case 4: return sizeof(chx_batch_stats);
   case 5: return sizeof(chx_gate_train_cfg);
   case 6: return sizeof(chx_gate_stats);
+  case 7: return sizeof(chx_ldn_options);
+  case 8: return sizeof(chx_ldn_result);
   }
   return 0;
 }

@@ -38,7 +38,9 @@ def test_struct_layouts_match_header():
     assert L.chx_struct_size(4) == C.sizeof(chx._BatchStats)
     assert L.chx_struct_size(5) == C.sizeof(chx._GateTrainCfg) == 40
     assert L.chx_struct_size(6) == C.sizeof(chx._GateStats) == 56
-    assert L.chx_struct_size(7) == 0
+    assert L.chx_struct_size(7) == C.sizeof(chx._LdnOptions) == 24
+    assert L.chx_struct_size(8) == C.sizeof(chx._LdnResult) == 5 * 8
+    assert L.chx_struct_size(9) == 0
 
 
 def test_options_default():
@@ -130,6 +132,20 @@ def test_double_pendulum_validation():
     with pytest.raises(chx.ChxError, match="params"):
         chx.integrate_ensemble(chx.System(chx.SYS_DOUBLE_PENDULUM, 2, (1.0,)), dp0, dt=0.01,
                                T=1.0, indicators=chx.IND_SALI, integrator="dop853")
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(sigma=0.0), "sigma"),
+    (dict(sigma=float("nan")), "sigma"),
+    (dict(sigma=1e-3, dirs=[4]), "dirs"),
+    (dict(sigma=1e-3, indicators=chx.IND_SALI | chx.IND_LD), "LD alone"),
+    (dict(sigma=1e-3, dt=0.0), "dt"),
+])
+def test_ld_indicators_validation(kw, msg):
+    with pytest.raises(chx.ChxError) as e:
+        kw.setdefault("dt", 0.01)
+        chx.ld_indicators(P.henon_heiles(), hh_x0(), T=1.0, **kw)
+    assert e.value.status == chx.ERR_INVALID_ARG and msg in str(e.value)
 
 
 def test_label_needs_sali():

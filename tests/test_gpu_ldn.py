@@ -1,0 +1,139 @@
+"""GPU parity of chx_ld_indicators (chaos indicators from the two-sided LDs
+of neighbouring orbits) against the oracle's ld_indicators, through the C
+ABI.
+
+The LDs of the member orbits follow the lane kernels' LD tolerances (1e-9
+relative, same integrator on both sides).  D, R and S are differences of
+nearly equal LDs divided by an LD, so their relative error is the LDs'
+divided by the indicator's size: compared at 1e-9 / max(indicator, 1e-3)
+relative plus 1e-12 absolute.  Status codes exactly.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import seeded_inputs as S
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2507_00622_amd as P
+    from oracle import oracle as O
+    return torch, P, O
+
+
+def run_gpu(env, sys_, x0, sigma, dirs, mask=None, two_sided=True, **kw):
+    torch, P, _ = env
+    dev = torch.device("cuda:0")
+    t = lambda a: None if a is None else torch.as_tensor(a, device=dev)
+    out = P.ld_indicators(sys_, t(x0), sigma, dirs=dirs, two_sided=two_sided, mask=t(mask),
+                          **kw)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def compare(g, o, tag):
+    assert np.array_equal(g["status"], o["status"])
+    ok = o["status"] == 0
+    ld = np.max(np.abs(g["ld"][ok] / o["ld"][ok] - 1)) if ok.any() else 0.0
+    msg = f"  {tag}: {ok.sum()} ok, ld {ld:.2e}"
+    assert ld < 1e-9
+    for k in ("D", "R", "S"):
+        a, b = g[k][ok], o[k][ok]
+        tol = 1e-9 / np.maximum(np.abs(b), 1e-3) * np.abs(b) + 1e-12
+        err = np.abs(a - b)
+        msg += f" {k} {np.max(err / np.maximum(np.abs(b), 1e-300)):.1e}"
+        assert np.all(err <= tol), (k, np.max(err - tol))
+    for k in ("ld", "D", "R", "S"):
+        assert np.all(np.isnan(g[k][~ok])), k
+    say(msg)
+
+
+def hh_points(O, seed, n, E):
+    y, py = S.section_points(seed, n)
+    x0, m = O.hh_points(E, y, py)
+    return x0[m == 1]
+
+
+@pytest.mark.parametrize("E", [0.125, 1.0 / 6.0])
+def test_hh_two_sided_yoshida(env, E):
+    torch, P, O = env
+    x0 = hh_points(O, 61, 400, E)
+    say(f"case: LD indicators HH E={E:.4f} n={len(x0)}, dirs (y, p_y), sigma 1e-3, T=50, Yoshida-4")
+    kw = dict(dt=0.01, T=50.0)
+    g = run_gpu(env, P.henon_heiles(), x0, 1e-3, [1, 3], **kw)
+    o = O.ld_indicators(O.henon_heiles(), x0, O.Run(indicators=O.IND_LD, **kw), [1, 3], 1e-3,
+                        threads=8)
+    compare(g, o, "two-sided")
+    g1 = run_gpu(env, P.henon_heiles(), x0, 1e-3, [1, 3], two_sided=False, **kw)
+    o1 = O.ld_indicators(O.henon_heiles(), x0, O.Run(indicators=O.IND_LD, **kw), [1, 3], 1e-3,
+                         two_sided=False, threads=8)
+    compare(g1, o1, "forward only")
+
+
+def test_dp_all_directions_dop853(env):
+    torch, P, O = env
+    x0 = S.dp_states(62, 200, math.pi, 1.0)
+    say("case: LD indicators double pendulum n=200, all 4 directions, sigma 1e-4, T=10, DOP853")
+    kw = dict(dt=0.01, T=10.0, integrator="dop853")
+    g = run_gpu(env, P.double_pendulum(), x0, 1e-4, None, **kw)
+    o = O.ld_indicators(O.double_pendulum(), x0,
+                        O.Run(dt=0.01, T=10.0, indicators=O.IND_LD, integrator=O.INT_DOP853),
+                        [0, 1, 2, 3], 1e-4, threads=8)
+    compare(g, o, "dp")
+
+
+def test_quartic_adaptive(env):
+    torch, P, O = env
+    so = O.quartic(3, 0.1)
+    x0 = O.quartic_ic(so, S.quartic_draws(63, 150, 3))
+    say("case: LD indicators quartic N=3 n=150, dirs (q1, p2), adaptive 1e-10, T=20")
+    g = run_gpu(env, P.quartic(3, 0.1), x0, 1e-3, [0, 4], dt=0.1, T=20.0,
+                integrator="dop853_adaptive", rtol=1e-10, atol=1e-10)
+    o = O.ld_indicators(so, x0, O.Run(dt=0.1, T=20.0, indicators=O.IND_LD,
+                                      integrator=O.INT_DOP853_ADAPTIVE, rtol=1e-10, atol=1e-10),
+                        [0, 4], 1e-3, threads=8)
+    # each member orbit chooses its own steps; the LD sits outside the error
+    # control, so compare where the indicators are not dominated by it
+    assert np.array_equal(g["status"], o["status"])
+    rel = np.abs(g["ld"] / o["ld"] - 1)
+    say("  ld max rel", rel.max())
+    assert rel.max() < 1e-3
+
+
+def test_edges_and_layouts(env):
+    torch, P, O = env
+    say("case: LD indicators ragged n=333 with masked, non-finite and escaping states; "
+        "host pointers; block sizes; empty")
+    x0 = hh_points(O, 64, 460, 1.0 / 6.0)[:333].copy()
+    x0[5] = [np.nan, 0.0, 0.1, 0.0]
+    mask = (np.arange(333) % 7 != 3).astype(np.uint8)
+    kw = dict(dt=0.01, T=20.0, escape_r2=0.36)
+    g = run_gpu(env, P.henon_heiles(), x0, 2e-3, [1, 3], mask=mask, **kw)
+    o = O.ld_indicators(O.henon_heiles(), x0, O.Run(indicators=O.IND_LD, **kw), [1, 3], 2e-3,
+                        mask=mask, threads=8)
+    say("  statuses", np.bincount(g["status"]))
+    assert g["status"][5] == 3 and (g["status"] == 2).any() and (g["status"] == 1).any()
+    compare(g, o, "edges")
+    # host pointers: the same numbers
+    _, P_, _ = env
+    h = P_.ld_indicators(P_.henon_heiles(), x0, 2e-3, dirs=[1, 3], mask=mask, **kw)
+    for k in g:
+        assert np.array_equal(g[k], h[k], equal_nan=True), k
+    for block in (64, 128):
+        b = run_gpu(env, P.henon_heiles(), x0, 2e-3, [1, 3], mask=mask, block_size=block, **kw)
+        for k in g:
+            assert np.array_equal(g[k], b[k], equal_nan=True), (block, k)
+    e = run_gpu(env, P.henon_heiles(), np.zeros((0, 4)), 1e-3, [1], dt=0.01, T=1.0)
+    assert e["D"].shape == (0,)
