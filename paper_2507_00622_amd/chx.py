@@ -35,7 +35,7 @@ EXPORTS = [
     "chx_last_error", "chx_version", "chx_struct_size", "chx_integrate_batched",
     "chx_ensemble_subset", "chx_gate_create", "chx_gate_destroy", "chx_gate_train",
     "chx_gate_grad", "chx_gate_infer", "chx_gate_get", "chx_gate_set", "chx_gate_features",
-    "chx_gate_classify",
+    "chx_gate_classify", "chx_ld_indicators",
 ]
 GATE_NFEAT, GATE_NPARAM = 6, 74256
 
@@ -149,7 +149,7 @@ def lib():
                          "chx_version", "chx_struct_size", "chx_gate_destroy"):
                 getattr(L, f).restype = C.c_int
         for k, st in enumerate((_System, _Options, _Result, _BatchItem, _BatchStats,
-                                _GateTrainCfg, _GateStats)):
+                                _GateTrainCfg, _GateStats, _LdnOptions, _LdnResult)):
             if L.chx_struct_size(k) != C.sizeof(st):
                 raise ImportError(f"libchx struct {st.__name__} layout differs from the binding")
         _lib = L
