@@ -819,6 +819,172 @@ def bench_dp(args, P, chx, torch, dev):
                 cpu)
 
 
+def bench_fig2(args, P, chx, torch, dev):
+    """The Henon-Heiles timing figure: time per IC against the number of ICs
+    integrated together (2^8 .. 2^20 seeded accessible section points at
+    E = 0.125), two deviation vectors for SALI + energy, final time 1e4, the
+    adaptive DOP8(5) at rtol = atol = 1e-10 (first step 0.1, checkpoints
+    every 1).  Each point is one whole call.  The value is the largest
+    ensemble's ICs/s; the roofline is its integration kernel over attempted
+    steps, timed launch by launch."""
+    import numpy as np
+
+    import seeded_inputs as S
+    T = args.T or 1e4
+    dt, tol = 0.1, 1e-10
+    ind = chx.IND_SALI | chx.IND_ENERGY
+    sizes = (8, 10, 12, 14, 16, 18, 20)
+    y, py = S.section_points(1001, int((1 << sizes[-1]) * 1.35))
+    x, m = P.hh_section_points(0.125, torch.as_tensor(y, device=dev),
+                               torch.as_tensor(py, device=dev))
+    xa = x[m == 1][: 1 << sizes[-1]].contiguous()
+    stream = torch.cuda.current_stream()
+    leg = dict(dt=dt, integrator="dop853_adaptive", rtol=tol, atol=tol)
+    for _ in range(args.warmup):
+        P.integrate_ensemble(P.henon_heiles(), xa[:256].contiguous(), T=T, indicators=ind,
+                             seed=1001, outputs=("label",), **leg)
+    torch.cuda.synchronize()
+    rows, log = [], []
+    n_steps = int(round(T / dt))
+    spl = min(args.steps_per_launch or 20000, n_steps)
+    t_all = time.perf_counter()
+    for k in sizes:
+        xs = xa[: 1 << k].contiguous()
+        last = k == sizes[-1]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e = P.Ensemble(P.henon_heiles(), xs, steps_per_launch=spl, T=T, indicators=ind,
+                       seed=1001, outputs=("label", "energy_err", "steps"), **leg)
+        advance_timed(e, n_steps, spl, stream, torch, log if last else None)
+        out = e.results()
+        e.close()
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        st = out["steps"].cpu().numpy()
+        rows.append({"ics": 1 << k, "s": sec, "us_per_ic": sec * 1e6 / (1 << k),
+                     "ics_per_s": (1 << k) / sec,
+                     "max_energy_error": float(out["energy_err"].cpu().numpy().max()),
+                     "chaotic_fraction": float(np.mean(out["label"].cpu().numpy() == 1)),
+                     "accepted_steps_per_ic": float(st[:, 0].mean()),
+                     "rejected_steps_per_ic": float(st[:, 1].mean())})
+        progress(f"fig2: {1 << k} ICs, {sec:.3f} s, {rows[-1]['us_per_ic']:.3f} us per IC")
+        if last:
+            attempts = int(st.sum())
+    elapsed = time.perf_counter() - t_all
+    kernel_s = sum(a.elapsed_time(b) for a, b, _ in log) * 1e-3
+    n_big = 1 << sizes[-1]
+    fpa = flops_per_attempt_dop853(2, 2, 0, False)
+    ck = n_big * (n_steps // 10) * checkpoint_flops_hh(2, 2, 0, True, True)
+    achieved = (attempts * fpa + ck) / kernel_s
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        threads = max(1, min(16, len(os.sched_getaffinity(0))))
+        ns, cT = 256, min(T, 2000.0)
+        xs = xa[: 1 << sizes[-1]].cpu().numpy()
+        idx = np.linspace(0, len(xs) - 1, ns).astype(int)
+        w0 = np.concatenate([S.deviation_vectors(1001, 1, 2, 4, first_ic=int(i)) for i in idx])
+        t2 = time.perf_counter()
+        O.integrate(O.henon_heiles(), xs[idx], O.Run(dt=dt, T=cT, indicators=ind,
+                                                     integrator=O.INT_DOP853_ADAPTIVE,
+                                                     rtol=tol, atol=tol),
+                    w0=w0, threads=threads)
+        el = time.perf_counter() - t2
+        cpu = {"value": ns * (cT / T) / el, "unit": "ICs/s", "cores": threads, "kind": "oracle",
+               "sample": f"{ns} strided ICs of the largest ensemble to T={cT:g} ({el:.1f} s), "
+                         f"scaled to T={T:g}"}
+    return emit(args, "Henon-Heiles ICs/s (adaptive DOP8(5), SALI)", rows[-1]["ics_per_s"],
+                "ICs/s", elapsed, "f64", {
+                    "workload": f"henon-heiles E=0.125 seeded accessible section points, SALI "
+                                f"(2 vectors)+energy, T={T:g}, adaptive DOP8(5) rtol=atol={tol:g}, "
+                                f"first step {dt}, checkpoints every 1; 2^8..2^20 ICs per call "
+                                "(set-up and results included)",
+                    "sweep": rows, "kernel_s_largest": kernel_s},
+                {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
+                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
+                 "kernel": "chx::lane_rka_kernel<SysHH, 2, false>", "flops_per_attempt": fpa,
+                 "launch_ms": kernel_s * 1e3 / max(len(log), 1), "launches_timed": len(log)},
+                cpu)
+
+
+def bench_fig3(args, P, chx, torch, dev):
+    """The FPU timing figure: time of one call against the number of degrees
+    of freedom, N = 2, 3, .., 16, for 1000 ICs (energy U[0.1, 10] in the two
+    lowest normal modes), GALI_4 (four deviation vectors) + energy, final
+    time 1e3, Yoshida-4 at dt = 0.0025 (energy error below 1e-8, the
+    figure's level).  The value is ICs/s at N = 16; the oracle's time per N
+    on a sample stands beside the GPU's, as the figure compares GPU and CPU."""
+    import numpy as np
+
+    import seeded_inputs as S
+    T = args.T or 1e3
+    dt, n = 0.0025, 1000
+    ind = chx.IND_GALI | chx.IND_ENERGY
+    Ns = tuple(range(2, 17))
+    stream = torch.cuda.current_stream()
+    n_steps = int(round(T / dt))
+    spl = min(args.steps_per_launch or 100000, n_steps)
+    rows, log = [], []
+    x0s = {N: P.ic_fput_modes(P.fput(N), torch.as_tensor(S.fput_mode_draws(1003 + N, n),
+                                                           device=dev)) for N in Ns}
+    for _ in range(args.warmup):
+        P.integrate_ensemble(P.fput(2), x0s[2], dt=dt, T=min(T, 10.0), indicators=ind,
+                             gali_kmax=4, seed=1003, outputs=("gali",))
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for N in Ns:
+        last = N == Ns[-1]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e = P.Ensemble(P.fput(N), x0s[N], steps_per_launch=spl, dt=dt, T=T, indicators=ind,
+                       gali_kmax=4, seed=1003, outputs=("gali", "energy_err"))
+        advance_timed(e, n_steps, spl, stream, torch, log if last else None)
+        out = e.results()
+        e.close()
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        g4 = out["gali"].cpu().numpy()[:, 2]
+        rows.append({"N": N, "s": sec, "max_energy_error": float(out["energy_err"].cpu().numpy().max()),
+                     "median_log10_gali4": float(np.median(np.log10(np.maximum(g4, 1e-300))))})
+        progress(f"fig3: N={N}, {n} ICs, {sec:.3f} s")
+    elapsed = time.perf_counter() - t_all
+    kernel_s = sum(a.elapsed_time(b) for a, b, _ in log) * 1e-3
+    fps = flops_per_step_fput(16, 4, 0, False, True, False, 10)
+    achieved = fps * n * n_steps / kernel_s
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        threads = max(1, min(16, len(os.sched_getaffinity(0))))
+        ns, cT = 16, min(T, 100.0)
+        el_tot = 0.0
+        for r in rows:
+            N = r["N"]
+            xs = O.fput_ic(O.fput(N), S.fput_mode_draws(1003 + N, ns))
+            w0 = S.deviation_vectors(1003, ns, 4, 2 * N)
+            t1 = time.perf_counter()
+            O.integrate(O.fput(N), xs, O.Run(dt=dt, T=cT, indicators=O.IND_GALI | O.IND_ENERGY,
+                                              gali_kmax=4), w0=w0, threads=threads)
+            el = time.perf_counter() - t1
+            el_tot += el
+            # thread-seconds per IC, spread over all threads, for n ICs to T
+            per_ic = el * min(threads, ns) / ns
+            r["oracle_s_for_1000_ics"] = per_ic * n / threads * (T / cT)
+        last_el = rows[-1]["oracle_s_for_1000_ics"]
+        cpu = {"value": n / last_el, "unit": "ICs/s", "cores": threads, "kind": "oracle",
+               "sample": f"{ns} ICs per N to T={cT:g} on {threads} threads ({el_tot:.1f} s), "
+                         f"scaled to 1000 ICs and T={T:g}; the value is N=16"}
+    return emit(args, "FPU ICs/s at N=16 (GALI_4)", n / rows[-1]["s"], "ICs/s", elapsed, "f64", {
+                    "workload": f"FPU-beta chains (k=1, beta=1), N=2..16, {n} ICs each, "
+                                f"GALI_4 (4 vectors)+energy, Yoshida-4 dt={dt}, T={T:g}; time of "
+                                "each whole call",
+                    "per_N": rows, "kernel_s_N16": kernel_s},
+                {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
+                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
+                 "kernel": "chx::fput_crow_kernel<16, 4> (1000 orbits: a small fraction of the "
+                           "chip)", "flops_per_orbit_step": fps,
+                 "launch_ms": kernel_s * 1e3 / max(len(log), 1), "launches_timed": len(log)}, cpu)
+
+
 def auc(score, label):
     """Area under the ROC curve of score for label 1 against label 0 (ties
     counted half): the probability that a random chaotic orbit scores above
@@ -929,7 +1095,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", choices=("hh", "fput", "batched", "gate", "sweep", "dop853",
-                                           "dop853_adaptive", "dp", "ldn"),
+                                           "dop853_adaptive", "dp", "ldn", "fig2", "fig3"),
                     default="hh",
                     help="hh: the headline Henon-Heiles grids (default); fput: FPU-beta "
                          "chains with 3N deviation vectors; batched: the persistent mixed "
@@ -939,7 +1105,9 @@ def parse():
                          "dop853_adaptive: the adaptive DOP8(5) solver on the E=0.125 grid "
                          "against fixed-step Yoshida-4; dp: the double pendulum's time per "
                          "IC against the ensemble size, fixed and adaptive; ldn: chaos "
-                         "indicators from the LDs of neighbouring orbits against SALI labels")
+                         "indicators from the LDs of neighbouring orbits against SALI labels; "
+                         "fig2: Henon-Heiles time per IC against the ensemble size with the "
+                         "adaptive solver; fig3: FPU time against the degrees of freedom")
     ap.add_argument("--grid", type=int, default=1024, help="grid side per energy")
     ap.add_argument("--T", type=float, default=None,
                     help="final time (default: 1e4 for hh, gate and batched, 2e3 for fput, "
@@ -985,7 +1153,7 @@ def main():
         fn = {"fput": bench_fput, "batched": bench_batched, "gate": bench_gate,
               "sweep": bench_sweep, "dop853": bench_dop853,
               "dop853_adaptive": bench_dop853_adaptive, "dp": bench_dp,
-              "ldn": bench_ldn}[args.workload]
+              "ldn": bench_ldn, "fig2": bench_fig2, "fig3": bench_fig3}[args.workload]
         print(json.dumps(fn(args, P, chx, torch, dev)), flush=True)
         return
     if args.T is None:

@@ -62,7 +62,9 @@ enum {
                                q_0 = q_{N+1} = 0 and N+1 springs:
                                V = sum_j k d^2/2 + alpha d^3/3 + beta d^4/4,
                                d_j = q_j - q_{j-1}; params {k, alpha, beta};
-                               ndof 2..16 */
+                               ndof 2..16; more than four deviation vectors
+                               need ndof 2, 4, 8 or 16 (else
+                               CHX_ERR_UNSUPPORTED) */
   CHX_SYS_QUARTIC = 3,      /* V = sum q_i^4/4 + eps sum_{i<j} q_i^2 q_j^2;
                                params {eps}; ndof 1..3 */
   CHX_SYS_HARMONIC = 4,     /* V = sum omega_i^2 q_i^2 / 2; params {omega_i};

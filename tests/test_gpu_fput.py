@@ -157,3 +157,35 @@ def test_fput_harmonic_chain_exponents_vanish(env):
                 indicators=O.IND_LYAP | O.IND_GALI, n_lyap=2 * N, gali_kmax=N)
     assert np.max(np.abs(g["lyap"])) < 0.02
     assert np.min(g["gali"][:, N - 2]) > 1e-4
+
+
+@pytest.mark.parametrize("N", [3, 5, 6, 7, 9, 12, 15])
+def test_fput_any_dof_component_rows(env, N):
+    # chains whose N is not a power of two run on the component-row kernel
+    # (up to four vectors): GALI_4 with SALI, LD and energy, as in the
+    # degrees-of-freedom sweep
+    torch, P, O = env
+    say(f"case: FPU N={N} component rows, SALI + GALI_4 + LD + energy, n=41")
+    so, sg = O.fput(N), P.fput(N)
+    n = 41
+    x0 = O.fput_ic(so, S.fput_mode_draws(700 + N, n))
+    w0 = S.deviation_vectors(800 + N, n, 4, 2 * N)
+    kw = dict(dt=0.02, T=60.0, indicators=O.IND_SALI | O.IND_GALI | O.IND_LD | O.IND_ENERGY,
+              gali_kmax=4)
+    g = run_gpu(env, sg, x0, None, w0, **kw)
+    o = O.integrate(so, x0, O.Run(**kw), w0=w0, threads=8)
+    E = np.array([O.hamiltonian(so, x) for x in x0])
+    assert np.array_equal(g["status"], o["status"])
+    se = state_err(g["x_final"], o["x_final"])
+    ge = log_err(g["gali"], o["gali"], 1e-8)
+    say(f"  state {se.max():.3g} gali {ge:.3g}")
+    assert se.max() < 1e-9
+    assert ge < 1e-6
+    assert log_err(g["sali_min"], o["sali_min"], 1e-12) < 1e-6
+    assert np.max(np.abs(g["ld"] / o["ld"] - 1)) < 1e-9
+    assert np.max(np.abs(g["energy_err"] - o["energy_err"]) / np.maximum(1.0, E)) < 1e-12
+    # more than four vectors needs a power of two
+    from paper_2507_00622_amd import chx
+    with pytest.raises(chx.ChxError) as e:
+        run_gpu(env, sg, x0, None, None, dt=0.02, T=1.0, indicators=O.IND_LYAP, n_lyap=2 * N)
+    assert e.value.status == chx.ERR_UNSUPPORTED
