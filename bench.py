@@ -911,77 +911,110 @@ def bench_fig3(args, P, chx, torch, dev):
     """The FPU timing figure: time of one call against the number of degrees
     of freedom, N = 2, 3, .., 16, for 1000 ICs (energy U[0.1, 10] in the two
     lowest normal modes), GALI_4 (four deviation vectors) + energy, final
-    time 1e3, Yoshida-4 at dt = 0.0025 (energy error below 1e-8, the
-    figure's level).  The value is ICs/s at N = 16; the oracle's time per N
-    on a sample stands beside the GPU's, as the figure compares GPU and CPU."""
+    time 1e3, with the adaptive DOP8(5) (the figure's solver) at rtol =
+    atol = 1e-11 and with Yoshida-4 at dt = 0.0025, both holding the energy
+    error near 1e-8, the figure's level (the figure's absolute tolerance
+    1e-8 gives 3e-5 here).  The value is ICs/s of the adaptive
+    solver at N = 16; the oracle's time per N on a sample stands beside the
+    GPU's, as the figure compares GPU and CPU."""
     import numpy as np
 
     import seeded_inputs as S
     T = args.T or 1e3
-    dt, n = 0.0025, 1000
+    n = 1000
     ind = chx.IND_GALI | chx.IND_ENERGY
     Ns = tuple(range(2, 17))
+    legs = {"dop853_adaptive": dict(dt=0.1, integrator="dop853_adaptive", rtol=1e-11,
+                                    atol=1e-11),
+            "yoshida4": dict(dt=0.0025)}
     stream = torch.cuda.current_stream()
-    n_steps = int(round(T / dt))
-    spl = min(args.steps_per_launch or 100000, n_steps)
-    rows, log = [], []
     x0s = {N: P.ic_fput_modes(P.fput(N), torch.as_tensor(S.fput_mode_draws(1003 + N, n),
                                                            device=dev)) for N in Ns}
     for _ in range(args.warmup):
-        P.integrate_ensemble(P.fput(2), x0s[2], dt=dt, T=min(T, 10.0), indicators=ind,
-                             gali_kmax=4, seed=1003, outputs=("gali",))
+        for leg in legs.values():
+            P.integrate_ensemble(P.fput(2), x0s[2], T=min(T, 10.0), indicators=ind,
+                                 gali_kmax=4, seed=1003, outputs=("gali",), **leg)
     torch.cuda.synchronize()
+    rows = {k: [] for k in legs}
+    log = []
     t_all = time.perf_counter()
-    for N in Ns:
-        last = N == Ns[-1]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        e = P.Ensemble(P.fput(N), x0s[N], steps_per_launch=spl, dt=dt, T=T, indicators=ind,
-                       gali_kmax=4, seed=1003, outputs=("gali", "energy_err"))
-        advance_timed(e, n_steps, spl, stream, torch, log if last else None)
-        out = e.results()
-        e.close()
-        torch.cuda.synchronize()
-        sec = time.perf_counter() - t0
-        g4 = out["gali"].cpu().numpy()[:, 2]
-        rows.append({"N": N, "s": sec, "max_energy_error": float(out["energy_err"].cpu().numpy().max()),
-                     "median_log10_gali4": float(np.median(np.log10(np.maximum(g4, 1e-300))))})
-        progress(f"fig3: N={N}, {n} ICs, {sec:.3f} s")
+    for name, leg in legs.items():
+        n_steps = int(round(T / leg["dt"]))
+        spl = min(args.steps_per_launch or 100000, n_steps)
+        for N in Ns:
+            last = N == Ns[-1] and name == "dop853_adaptive"
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            outs = ("gali", "energy_err", "steps") if name != "yoshida4" else ("gali", "energy_err")
+            e = P.Ensemble(P.fput(N), x0s[N], steps_per_launch=spl, T=T, indicators=ind,
+                           gali_kmax=4, seed=1003, outputs=outs, **leg)
+            advance_timed(e, n_steps, spl, stream, torch, log if last else None)
+            out = e.results()
+            e.close()
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            g4 = out["gali"].cpu().numpy()[:, 2]
+            row = {"N": N, "s": sec,
+                   "max_energy_error": float(out["energy_err"].cpu().numpy().max()),
+                   "median_log10_gali4": float(np.median(np.log10(np.maximum(g4, 1e-300))))}
+            if "steps" in out:
+                st = out["steps"].cpu().numpy()
+                row["accepted_steps_per_ic"] = float(st[:, 0].mean())
+                row["rejected_steps_per_ic"] = float(st[:, 1].mean())
+                if last:
+                    attempts = int(st.sum())
+            rows[name].append(row)
+            progress(f"fig3 {name}: N={N}, {n} ICs, {sec:.3f} s")
     elapsed = time.perf_counter() - t_all
     kernel_s = sum(a.elapsed_time(b) for a, b, _ in log) * 1e-3
-    fps = flops_per_step_fput(16, 4, 0, False, True, False, 10)
-    achieved = fps * n * n_steps / kernel_s
+    # roofline of the adaptive N = 16 kernel over attempted steps: the state
+    # and four vectors' DOP853 stages (per stage: 12 spring evaluations and
+    # stiffnesses as in flops_per_step_fput, 8N per vector stage for the
+    # tridiagonal product, the stage sums) and the error terms
+    D = 32
+    sums = 2 * D * sum(DOP853_ROW_NNZ) + D * (len(DOP853_ROW_NNZ) - 1)
+    final = 2 * D * DOP853_B_NNZ + D
+    force = 6 * 17 + 16 + 4 * 17
+    state = sums + 12 * (force + D) + final
+    vec = sums + 12 * (3 * 2 * 16 + D) + final
+    err = D * 5 * (2 * DOP853_B_NNZ + 2 * 3 + 2 + 2 * 2)
+    fpa = state + 4 * vec + err + 8
+    achieved = attempts * fpa / kernel_s
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import oracle as O
         threads = max(1, min(16, len(os.sched_getaffinity(0))))
         ns, cT = 16, min(T, 100.0)
         el_tot = 0.0
-        for r in rows:
+        for r in rows["dop853_adaptive"]:
             N = r["N"]
             xs = O.fput_ic(O.fput(N), S.fput_mode_draws(1003 + N, ns))
             w0 = S.deviation_vectors(1003, ns, 4, 2 * N)
             t1 = time.perf_counter()
-            O.integrate(O.fput(N), xs, O.Run(dt=dt, T=cT, indicators=O.IND_GALI | O.IND_ENERGY,
-                                              gali_kmax=4), w0=w0, threads=threads)
+            O.integrate(O.fput(N), xs, O.Run(dt=0.1, T=cT, indicators=O.IND_GALI | O.IND_ENERGY,
+                                              gali_kmax=4, integrator=O.INT_DOP853_ADAPTIVE,
+                                              rtol=1e-11, atol=1e-11), w0=w0, threads=threads)
             el = time.perf_counter() - t1
             el_tot += el
             # thread-seconds per IC, spread over all threads, for n ICs to T
             per_ic = el * min(threads, ns) / ns
             r["oracle_s_for_1000_ics"] = per_ic * n / threads * (T / cT)
-        last_el = rows[-1]["oracle_s_for_1000_ics"]
+        last_el = rows["dop853_adaptive"][-1]["oracle_s_for_1000_ics"]
         cpu = {"value": n / last_el, "unit": "ICs/s", "cores": threads, "kind": "oracle",
-               "sample": f"{ns} ICs per N to T={cT:g} on {threads} threads ({el_tot:.1f} s), "
-                         f"scaled to 1000 ICs and T={T:g}; the value is N=16"}
-    return emit(args, "FPU ICs/s at N=16 (GALI_4)", n / rows[-1]["s"], "ICs/s", elapsed, "f64", {
+               "sample": f"{ns} ICs per N to T={cT:g} with the adaptive solver on {threads} "
+                         f"threads ({el_tot:.1f} s), scaled to 1000 ICs and T={T:g}; the value "
+                         "is N=16"}
+    big = rows["dop853_adaptive"][-1]
+    return emit(args, "FPU ICs/s at N=16 (GALI_4, adaptive DOP8(5))", n / big["s"], "ICs/s",
+                elapsed, "f64", {
                     "workload": f"FPU-beta chains (k=1, beta=1), N=2..16, {n} ICs each, "
-                                f"GALI_4 (4 vectors)+energy, Yoshida-4 dt={dt}, T={T:g}; time of "
-                                "each whole call",
-                    "per_N": rows, "kernel_s_N16": kernel_s},
+                                f"GALI_4 (4 vectors)+energy, T={T:g}; adaptive DOP8(5) "
+                                "rtol=atol=1e-11 and Yoshida-4 dt=0.0025; time of each whole call",
+                    "per_N": rows, "kernel_s_N16_adaptive": kernel_s},
                 {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
                  "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
-                 "kernel": "chx::fput_crow_kernel<16, 4> (1000 orbits: a small fraction of the "
-                           "chip)", "flops_per_orbit_step": fps,
+                 "kernel": "chx::fput_crow_rka_kernel<16, 4> (1000 orbits: a small fraction of "
+                           "the chip)", "flops_per_attempt": fpa,
                  "launch_ms": kernel_s * 1e3 / max(len(log), 1), "launches_timed": len(log)}, cpu)
 
 

@@ -110,7 +110,8 @@ enum {
                            Dormand and Prince that the paper's solvers build on
                            (Functionalities section), fixed step, applied to the
                            state, the variational equations and the LD integrand
-                           as one system; lane-per-orbit systems only (not FPU) */
+                           as one system; every system, FPU chains with at most
+                           four deviation vectors (else CHX_ERR_UNSUPPORTED) */
   CHX_INT_DOP853_ADAPTIVE = 2 /* the adaptive DOP 8(5) solver of the same
                            section: the same system, each orbit with its own step
                            size chosen from DOP853's embedded error estimate
@@ -122,7 +123,7 @@ enum {
                            stay at multiples of K dt and at T, which the steps hit
                            exactly.  More than 100000 attempts between two
                            checkpoints stop the orbit (CHX_ORBIT_STEP_FAILED).
-                           Lane-per-orbit systems only. */
+                           Systems as for CHX_INT_DOP853. */
 };
 
 /* Per-orbit status. */
@@ -144,7 +145,9 @@ typedef struct {
                              (renormalisation, SALI, QR, checks); 0 -> 10 */
   int32_t n_lyap;         /* Lyapunov vectors 1..2N; 0 -> 2N */
   int32_t gali_kmax;      /* 2..2N; 0 -> 2 */
-  double ld_p;            /* LD exponent in (0, 1]; 0 -> 0.5 */
+  double ld_p;            /* LD exponent in (0, 1]; 0 -> 0.5.  FPU chains and
+                             the batched form: 0.5 only (else
+                             CHX_ERR_UNSUPPORTED) */
   double sali_threshold;  /* chaotic iff min SALI < threshold; 0 -> 1e-8 */
   int32_t early_exit;     /* non-zero: stop an orbit at its first checkpoint
                              with SALI < threshold (needs CHX_IND_SALI) */

@@ -14,6 +14,11 @@
 using namespace chx;
 
 namespace chx {
+// DOP853 (fixed or adaptive) for FPU chains on the component rows
+// (fput_crow_rk.hip, fput_crow_rka.hip).
+hipError_t launch_fput_crow_rk(int ndof, int M, bool adaptive, const StepArgs &a,
+                               hipStream_t s);
+
 namespace host {
 
 thread_local std::string g_err;
@@ -122,8 +127,8 @@ chx_status make_plan(const chx_system *sys, const chx_options *opt, Plan *p) {
   if (o.integrator != CHX_INT_YOSHIDA4 && o.integrator != CHX_INT_DOP853 &&
       o.integrator != CHX_INT_DOP853_ADAPTIVE)
     return fail(CHX_ERR_INVALID_ARG, "unknown integrator %d", o.integrator);
-  if (o.integrator != CHX_INT_YOSHIDA4 && sys->kind == CHX_SYS_FPUT)
-    return fail(CHX_ERR_UNSUPPORTED, "DOP853 is available for the lane-per-orbit systems (Henon-Heiles, quartic, harmonic, double pendulum), not FPUT");
+  if (sys->kind == CHX_SYS_FPUT && (o.indicators & CHX_IND_LD) && o.ld_p != 0.5)
+    return fail(CHX_ERR_UNSUPPORTED, "the FPU kernels compute the LD with p = 1/2 only");
   if (o.integrator == CHX_INT_YOSHIDA4 && sys->kind == CHX_SYS_DOUBLE_PENDULUM)
     return fail(CHX_ERR_UNSUPPORTED, "the double pendulum is not separable: integrate it with DOP853 (fixed or adaptive)");
   if (o.integrator == CHX_INT_DOP853_ADAPTIVE) {
@@ -144,6 +149,8 @@ chx_status make_plan(const chx_system *sys, const chx_options *opt, Plan *p) {
   p->kmax = kmax;
   p->n_total = (int64_t)nr;
   const int sk = sys->kind;
+  if (o.integrator != CHX_INT_YOSHIDA4 && sk == CHX_SYS_FPUT && p->M > 4)
+    return fail(CHX_ERR_UNSUPPORTED, "DOP853 for FPU chains runs on the component rows: at most four deviation vectors (got %d)", p->M);
   const bool ok = (sk == CHX_SYS_FPUT)
                       ? fput_row_supported(N, p->M, p->n_l, (o.indicators & CHX_IND_SALI) != 0)
                       : lane_supported(sk, N, p->M);
@@ -309,7 +316,11 @@ chx_status advance(chx_ensemble *e, int64_t s_end) {
     a.s_end = nxt;
     if (a.n > 0) {
       hipError_t he = (e->kind == CHX_SYS_FPUT)
-                          ? launch_fput_row(pl.N, pl.M, a, e->stream)
+                          ? (pl.o.integrator != CHX_INT_YOSHIDA4
+                                 ? launch_fput_crow_rk(pl.N, pl.M,
+                                                       pl.o.integrator == CHX_INT_DOP853_ADAPTIVE,
+                                                       a, e->stream)
+                                 : launch_fput_row(pl.N, pl.M, a, e->stream))
                       : (pl.o.integrator != CHX_INT_YOSHIDA4)
                           ? launch_lane_rk(e->kind, pl.N, pl.M,
                                            pl.o.integrator == CHX_INT_DOP853_ADAPTIVE, a,

@@ -168,6 +168,8 @@ extern "C" chx_status chx_integrate_batched(const chx_batch_item *items, int32_t
     o.T = items[i].T;
     st = make_plan(&items[i].sys, &o, &plans[i]);
     if (st) return st;
+    if ((plans[i].o.indicators & CHX_IND_LD) && plans[i].o.ld_p != 0.5)
+      return fail(CHX_ERR_UNSUPPORTED, "the batched form computes the LD with p = 1/2 only");
     if (!pool_kind_of(items[i].sys.kind, items[i].sys.ndof, plans[i].M, &kinds[i]))
       return fail(CHX_ERR_UNSUPPORTED, "item %d: system kind %d ndof %d is not supported in the batched form", i, items[i].sys.kind, items[i].sys.ndof);
     if (plans[i].n_total % plans[i].K != 0)

@@ -92,12 +92,16 @@ struct CRowOrbit {
     }
   }
 
-  __device__ __forceinline__ void springs(const StepArgs &a) {
+  // Net spring force F = V'(d_l) - V'(d_{l+1}) on the mass of this lane at
+  // positions y (one per lane, ghosts zero), and the stiffnesses
+  // kl = V''(d_l), kr = V''(d_{l+1}) of its two springs; zero on ghosts.
+  __device__ __forceinline__ static void spring_terms(const StepArgs &a, double y, bool mass,
+                                                      double &F, double &kl, double &kr) {
     using namespace fputrow;
     const double kk = a.prm[0], al = a.prm[1], be = a.prm[2];
-    const double ql = dpp<0x111>(q);  // row_shr:1
-    const double qr = dpp<0x101>(q);  // row_shl:1
-    const double dl = q - ql, dr = qr - q;
+    const double ql = dpp<0x111>(y);  // row_shr:1
+    const double qr = dpp<0x101>(y);  // row_shl:1
+    const double dl = y - ql, dr = qr - y;
     const double fl = dl * __builtin_fma(dl, __builtin_fma(be, dl, al), kk);
     const double fr = dr * __builtin_fma(dr, __builtin_fma(be, dr, al), kk);
     F = mass ? fl - fr : 0.0;
@@ -105,6 +109,7 @@ struct CRowOrbit {
     kl = mass ? __builtin_fma(dl, __builtin_fma(threebe, dl, twoal), kk) : 0.0;
     kr = mass ? __builtin_fma(dr, __builtin_fma(threebe, dr, twoal), kk) : 0.0;
   }
+  __device__ __forceinline__ void springs(const StepArgs &a) { spring_terms(a, q, mass, F, kl, kr); }
   __device__ __forceinline__ void kick_state(double h) { p = __builtin_fma(-h, F, p); }
   __device__ __forceinline__ void drift(double c) {
     q = __builtin_fma(c, p, q);

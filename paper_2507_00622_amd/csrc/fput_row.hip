@@ -13,7 +13,7 @@ hipError_t launch_crow(int M, const StepArgs &a, hipStream_t s) {
   // 16 rows (orbits) per 256-thread block
   const unsigned grid = (unsigned)((a.n + 15) / 16);
   switch (M) {
-  case 0:
+  case 0: hipLaunchKernelGGL((fput_crow_kernel<N, 0>), dim3(grid), dim3(256), 0, s, a); break;
   case 1: hipLaunchKernelGGL((fput_crow_kernel<N, 1>), dim3(grid), dim3(256), 0, s, a); break;
   case 2: hipLaunchKernelGGL((fput_crow_kernel<N, 2>), dim3(grid), dim3(256), 0, s, a); break;
   case 3: hipLaunchKernelGGL((fput_crow_kernel<N, 3>), dim3(grid), dim3(256), 0, s, a); break;

@@ -98,16 +98,30 @@ def test_bad_options(kw, msg):
     assert e.value.status == chx.ERR_INVALID_ARG and msg in str(e.value)
 
 
-def test_dop853_is_for_lane_systems_only():
+def test_dop853_fpu_vector_limit():
+    # FPU chains run DOP853 on the component rows: at most four vectors
     for integ in ("dop853", "dop853_adaptive"):
         with pytest.raises(chx.ChxError) as e:
             chx.integrate_ensemble(P.fput(4), np.zeros((2, 8)), dt=0.01, T=1.0,
-                                   indicators=chx.IND_SALI, integrator=integ)
-        assert e.value.status == chx.ERR_UNSUPPORTED and "DOP853" in str(e.value)
+                                   indicators=chx.IND_SALI | chx.IND_LYAP, n_lyap=3,
+                                   integrator=integ)
+        assert e.value.status == chx.ERR_UNSUPPORTED and "four" in str(e.value)
     with pytest.raises(chx.ChxError) as e:
         chx.integrate_batched([dict(sys=P.henon_heiles(), x0=hh_x0(4), dt=0.01, T=1.0)],
                               indicators=chx.IND_SALI, integrator="dop853")
     assert e.value.status == chx.ERR_UNSUPPORTED and "Yoshida-4" in str(e.value)
+
+
+def test_ld_exponent_limits():
+    # the FPU kernels and the batched form integrate the LD with p = 1/2 only
+    with pytest.raises(chx.ChxError) as e:
+        chx.integrate_ensemble(P.fput(4), np.zeros((2, 8)), dt=0.01, T=1.0,
+                               indicators=chx.IND_LD, ld_p=0.3)
+    assert e.value.status == chx.ERR_UNSUPPORTED and "p = 1/2" in str(e.value)
+    with pytest.raises(chx.ChxError) as e:
+        chx.integrate_batched([dict(sys=P.henon_heiles(), x0=hh_x0(4), dt=0.01, T=1.0)],
+                              indicators=chx.IND_SALI | chx.IND_LD, ld_p=0.7)
+    assert e.value.status == chx.ERR_UNSUPPORTED and "p = 1/2" in str(e.value)
 
 
 def test_double_pendulum_validation():

@@ -189,3 +189,23 @@ def test_fput_any_dof_component_rows(env, N):
     with pytest.raises(chx.ChxError) as e:
         run_gpu(env, sg, x0, None, None, dt=0.02, T=1.0, indicators=O.IND_LYAP, n_lyap=2 * N)
     assert e.value.status == chx.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("N", [4, 7, 16])
+def test_fput_without_vectors(env, N):
+    # LD and energy alone (no deviation vectors): the state block of an
+    # orbit without vectors is followed directly by its accumulators, which
+    # a kernel must not treat as vector storage
+    torch, P, O = env
+    say(f"case: FPU N={N} without vectors, LD + energy")
+    so, sg = O.fput(N), P.fput(N)
+    n = 37
+    x0 = O.fput_ic(so, S.fput_mode_draws(900 + N, n))
+    kw = dict(dt=0.02, T=40.0, indicators=O.IND_LD | O.IND_ENERGY)
+    g = run_gpu(env, sg, x0, **kw)
+    o = O.integrate(so, x0, O.Run(**kw), threads=8)
+    E = np.array([O.hamiltonian(so, x) for x in x0])
+    assert np.array_equal(g["status"], o["status"])
+    assert np.max(state_err(g["x_final"], o["x_final"])) < 1e-9
+    assert np.max(np.abs(g["ld"] / o["ld"] - 1)) < 1e-9
+    assert np.max(np.abs(g["energy_err"] - o["energy_err"]) / np.maximum(1.0, E)) < 1e-12
