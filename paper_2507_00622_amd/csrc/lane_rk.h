@@ -347,10 +347,16 @@ __global__ void __launch_bounds__(256) lane_rk_kernel(const StepArgs a) {
 // iff err <= 1; q = err^(1/8) by three square roots; accepted:
 // h /= max(1/6, min(1/0.333, q / 0.9)), not growing right after a
 // rejection; rejected: h /= min(1/0.333, q / 0.9)).  A step that would end
-// within 1.01 h of the checkpoint ends on it exactly.  The lanes of a
-// wavefront run their step loops independently (exec-masked) and meet at
-// each checkpoint.  Dynamic LDS per thread: the 12 QW stage records, then
-// the M D components of the attempted vectors.
+// within 1.01 h of the checkpoint ends on it exactly.  Each lane runs
+// through its own checkpoints: one loop per lane in which every iteration
+// is an attempted step, preceded by the lane's checkpoint once it has
+// reached one, so the lanes of a wavefront meet only at the end of the
+// launch (waiting at every checkpoint for the lane with the most steps in
+// that interval would cost about a fifth of the time on the section grids).
+// Every lane ends: every iteration attempts a step, which either moves the
+// lane on or counts towards the limit of attempts.
+// Dynamic LDS per thread: the 12 LDS_STAGE stage records, then the M D
+// components of the attempted vectors.
 template <class S, int M, bool GP>
 __global__ void __launch_bounds__(256) lane_rka_kernel(const StepArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -368,64 +374,69 @@ __global__ void __launch_bounds__(256) lane_rka_kernel(const StepArgs a) {
   double *qs = lane_rk_lds + threadIdx.x;
   double *wn = lane_rk_lds + (size_t)12 * RKOrbit<S, M, GP>::LDS_STAGE * stride + threadIdx.x;
   const bool do_ld = (a.ind & CHX_IND_LD) != 0;
-  int64_t s = a.s_begin;
   const int64_t K = a.K;
+  int64_t s = a.s_begin;
+  int64_t next = (s / K + 1) * K;
+  if (next > a.n_total) next = a.n_total;
+  double t = (double)s * a.dt;
+  double tb = (double)next * a.dt;
+  int attempts = 0;
   while (s < a.s_end) {
-    int64_t next = (s / K + 1) * K;
-    if (next > a.n_total) next = a.n_total;
-    double t = (double)s * a.dt;
-    const double tb = (double)next * a.dt;
-    int attempts = 0, fail = CHX_ORBIT_OK;
-    while (t < tb) {
-      double hh = h;
-      bool last = false;
-      if (t + 1.01 * hh >= tb) {
-        hh = tb - t;
-        last = true;
-      }
-      double xn[D], ldn;
-      const double err = o.rk_attempt(a, hh, do_ld, qs, wn, stride, xn, ldn);
-      bool finite = __builtin_isfinite(err) && __builtin_isfinite(ldn);
-#pragma unroll
-      for (int c = 0; c < D; ++c) finite = finite && __builtin_isfinite(xn[c]);
-      if (!finite) {
-        fail = CHX_ORBIT_NONFINITE;
-        break;
-      }
-      if (++attempts > dop853::MAX_ATTEMPTS) {
-        fail = CHX_ORBIT_STEP_FAILED;
-        break;
-      }
-      const double q = sqrt(sqrt(sqrt(err)));
-      double fac = q / dop853::SAFE;
-      if (fac > dop853::FACC1) fac = dop853::FACC1;
-      if (err <= 1.0) {
-        if (fac < dop853::FACC2) fac = dop853::FACC2;
-        double hnew = hh / fac;
-        if (rej && hnew > hh) hnew = hh;
-        rej = false;
-        h = hnew;
-        nacc += 1.0;
-#pragma unroll
-        for (int c = 0; c < D; ++c) o.x[c] = xn[c];
-#pragma unroll
-        for (int v = 0; v < M; ++v)
-#pragma unroll
-          for (int c = 0; c < D; ++c) o.w[v][c] = wn[(v * D + c) * stride];
-        o.ld = ldn;
-        t = last ? tb : t + hh;
-      } else {
-        h = hh / fac;
-        rej = true;
-        nrej += 1.0;
-      }
+    if (t >= tb) {
+      // this lane's checkpoint, ahead of its next attempt in the same
+      // iteration (as an iteration of its own it would cost the wavefront a
+      // whole attempt while the other lanes step)
+      s = next;
+      if (!o.checkpoint(a, tb)) break;
+      if (s >= a.s_end) break;
+      next = (s / K + 1) * K;
+      if (next > a.n_total) next = a.n_total;
+      t = tb;
+      tb = (double)next * a.dt;
+      attempts = 0;
     }
-    if (fail != CHX_ORBIT_OK) {
-      o.st = fail;
+    double hh = h;
+    bool last = false;
+    if (t + 1.01 * hh >= tb) {
+      hh = tb - t;
+      last = true;
+    }
+    double xn[D], ldn;
+    const double err = o.rk_attempt(a, hh, do_ld, qs, wn, stride, xn, ldn);
+    bool finite = __builtin_isfinite(err) && __builtin_isfinite(ldn);
+#pragma unroll
+    for (int c = 0; c < D; ++c) finite = finite && __builtin_isfinite(xn[c]);
+    if (!finite) {
+      o.st = CHX_ORBIT_NONFINITE;
       break;
     }
-    s = next;
-    if (!o.checkpoint(a, tb)) break;
+    if (++attempts > dop853::MAX_ATTEMPTS) {
+      o.st = CHX_ORBIT_STEP_FAILED;
+      break;
+    }
+    const double q = sqrt(sqrt(sqrt(err)));
+    double fac = q / dop853::SAFE;
+    if (fac > dop853::FACC1) fac = dop853::FACC1;
+    if (err <= 1.0) {
+      if (fac < dop853::FACC2) fac = dop853::FACC2;
+      double hnew = hh / fac;
+      if (rej && hnew > hh) hnew = hh;
+      rej = false;
+      h = hnew;
+      nacc += 1.0;
+#pragma unroll
+      for (int c = 0; c < D; ++c) o.x[c] = xn[c];
+#pragma unroll
+      for (int v = 0; v < M; ++v)
+#pragma unroll
+        for (int c = 0; c < D; ++c) o.w[v][c] = wn[(v * D + c) * stride];
+      o.ld = ldn;
+      t = last ? tb : t + hh;
+    } else {
+      h = hh / fac;
+      rej = true;
+      nrej += 1.0;
+    }
   }
   int64_t ob = i;
   asm volatile("" : "+v"(ob));
