@@ -112,6 +112,20 @@ def test_quartic_adaptive(env):
     assert rel.max() < 1e-3
 
 
+@pytest.mark.parametrize("integ", ["yoshida4", "dop853"])
+def test_fpu_component_rows(env, integ):
+    torch, P, O = env
+    so = O.fput(5)
+    x0 = O.fput_ic(so, S.fput_mode_draws(65, 120))
+    say(f"case: LD indicators FPU N=5 n=120, dirs (q1, p3), sigma 1e-3, T=30, {integ}")
+    g = run_gpu(env, P.fput(5), x0, 1e-3, [0, 7], dt=0.02, T=30.0, integrator=integ)
+    o = O.ld_indicators(so, x0, O.Run(dt=0.02, T=30.0, indicators=O.IND_LD,
+                                      integrator=O.INT_DOP853 if integ == "dop853"
+                                      else O.INT_YOSHIDA4),
+                        [0, 7], 1e-3, threads=8)
+    compare(g, o, "fpu")
+
+
 def test_edges_and_layouts(env):
     torch, P, O = env
     say("case: LD indicators ragged n=333 with masked, non-finite and escaping states; "
