@@ -69,7 +69,7 @@ enum {
                                params {eps}; ndof 1..3 */
   CHX_SYS_HARMONIC = 4,     /* V = sum omega_i^2 q_i^2 / 2; params {omega_i};
                                ndof 1..3 */
-  CHX_SYS_DOUBLE_PENDULUM = 5 /* Examples section, dimensionless double pendulum:
+  CHX_SYS_DOUBLE_PENDULUM = 5, /* Examples section, dimensionless double pendulum:
                                x = (theta_1, theta_2, p_1, p_2),
                                H = p^T B^{-1}(c) p / 2 - alpha (1+sigma) cos theta_1
                                    - cos theta_2, c = cos(theta_1 - theta_2),
@@ -80,6 +80,27 @@ enum {
                                or CHX_INT_DOP853_ADAPTIVE (else
                                CHX_ERR_UNSUPPORTED); the LD integrand is
                                sum_c |dx_c/dt|^p over the four components */
+  CHX_SYS_CUSTOM = 6        /* a separable system given by the caller (the paper's
+                               package integrates any Hamiltonian the user writes):
+                               H = |p|^2/2 + V(q), ndof 1..3, up to 16 params
+                               (nparams of them, passed as prm).  source holds HIP
+                               device code defining
+                                 __device__ double chx_potential(const double *q,
+                                                                 const double *prm);
+                                 __device__ void chx_force(const double *q, double *F,
+                                                           const double *prm);
+                                     F = grad V (N values)
+                                 __device__ void chx_hess(const double *q, double *H,
+                                                          const double *prm);
+                                     H = Hess V, upper triangle packed row by
+                                     row: H[i N - i (i-1)/2 + (j - i)], i <= j.
+                               It is compiled for gfx950 with hipRTC together
+                               with the library's lane kernels at the first call
+                               that needs each kernel variant (about two seconds;
+                               cached per process by source, ndof and variant);
+                               source that does not compile gives
+                               CHX_ERR_INVALID_ARG with the compiler's log.  All
+                               integrators; not in the batched form or the gate. */
 };
 
 typedef struct {
@@ -87,6 +108,8 @@ typedef struct {
   int32_t ndof;         /* N; phase-space dimension 2N */
   const double *params; /* host memory, nparams values (see above) */
   int32_t nparams;
+  const char *source;   /* CHX_SYS_CUSTOM: NUL-terminated device source (host
+                           memory, read during the call); ignored otherwise */
 } chx_system;
 
 /* Indicator bits (Functionalities section). */

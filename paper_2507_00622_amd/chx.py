@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(HERE, "libchx.so")
 
 # --- constants mirrored from include/chx.h -----------------------------------
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_INTERNAL = range(6)
-SYS_HENON_HEILES, SYS_FPUT, SYS_QUARTIC, SYS_HARMONIC, SYS_DOUBLE_PENDULUM = 1, 2, 3, 4, 5
+SYS_HENON_HEILES, SYS_FPUT, SYS_QUARTIC, SYS_HARMONIC, SYS_DOUBLE_PENDULUM, SYS_CUSTOM = (
+    1, 2, 3, 4, 5, 6)
 IND_SALI, IND_GALI, IND_LYAP, IND_LD, IND_ENERGY = 1, 2, 4, 8, 16
 PTR_DEVICE = 1
 INT_YOSHIDA4, INT_DOP853, INT_DOP853_ADAPTIVE = 0, 1, 2
@@ -48,7 +49,8 @@ class ChxError(RuntimeError):
 
 class _System(C.Structure):
     _fields_ = [("kind", C.c_int32), ("ndof", C.c_int32),
-                ("params", C.POINTER(C.c_double)), ("nparams", C.c_int32)]
+                ("params", C.POINTER(C.c_double)), ("nparams", C.c_int32),
+                ("source", C.c_char_p)]
 
 
 class _Options(C.Structure):
@@ -168,11 +170,14 @@ class System:
     kind: int
     ndof: int
     params: tuple = ()
+    source: str = None  # SYS_CUSTOM only
 
     def _c(self):
         arr = (C.c_double * max(1, len(self.params)))(*self.params)
-        s = _System(self.kind, self.ndof, C.cast(arr, C.POINTER(C.c_double)), len(self.params))
-        s._keep = arr
+        src = None if self.source is None else self.source.encode()
+        s = _System(self.kind, self.ndof, C.cast(arr, C.POINTER(C.c_double)), len(self.params),
+                    src)
+        s._keep = (arr, src)
         return s
 
 
@@ -190,6 +195,13 @@ def quartic(N=3, eps=0.1):
 
 def harmonic(omegas):
     return System(SYS_HARMONIC, len(omegas), tuple(float(w) for w in omegas))
+
+
+def custom(ndof, source, params=()):
+    """A separable system H = |p|^2/2 + V(q) given as HIP device code
+    defining chx_potential, chx_force (grad V) and chx_hess (Hess V, upper
+    triangle packed row by row); ndof 1..3, up to 16 params (see chx.h)."""
+    return System(SYS_CUSTOM, int(ndof), tuple(float(v) for v in params), str(source))
 
 
 def double_pendulum(alpha=1.0, sigma=1.0):

@@ -52,6 +52,7 @@ int required_params(int kind, int ndof) {
   case CHX_SYS_QUARTIC: return 1;
   case CHX_SYS_HARMONIC: return ndof;
   case CHX_SYS_DOUBLE_PENDULUM: return 2;
+  case CHX_SYS_CUSTOM: return 0;
   }
   return -1;
 }
@@ -73,6 +74,15 @@ chx_status check_system(const chx_system *sys) {
   case CHX_SYS_DOUBLE_PENDULUM:
     if (N != 2) return fail(CHX_ERR_INVALID_ARG, "the double pendulum needs ndof == 2 (got %d)", N);
     break;
+  case CHX_SYS_CUSTOM:
+    if (N < 1 || N > 3) return fail(CHX_ERR_INVALID_ARG, "a custom system needs ndof 1..3 (got %d)", N);
+    if (!sys->source || !sys->source[0]) return fail(CHX_ERR_INVALID_ARG, "a custom system needs its source");
+    if (sys->nparams < 0 || sys->nparams > 16)
+      return fail(CHX_ERR_INVALID_ARG, "a custom system takes 0..16 params (got %d)", sys->nparams);
+    if (sys->nparams > 0 && !sys->params) return fail(CHX_ERR_INVALID_ARG, "system params is NULL");
+    for (int i = 0; i < sys->nparams; ++i)
+      if (!isfinite(sys->params[i])) return fail(CHX_ERR_INVALID_ARG, "system param %d is not finite", i);
+    return CHX_OK;
   default: return fail(CHX_ERR_INVALID_ARG, "unknown system kind %d", k);
   }
   const int np = required_params(k, N);
@@ -193,10 +203,21 @@ chx_status create(const chx_system *sys, const double *x0, const uint8_t *mask, 
   const hipStream_t s = device ? (hipStream_t)pl.o.stream : nullptr;
   if (!device && pl.o.stream) return fail(CHX_ERR_INVALID_ARG, "stream given without CHX_PTR_DEVICE");
 
+  void *custom = nullptr;
+  if (sys->kind == CHX_SYS_CUSTOM) {
+    // compile before any device work, so that source errors come first
+    st = custom_prepare(sys->source, sys->ndof, pl, &custom);
+    if (st) return st;
+  }
   chx_ensemble *e = new chx_ensemble();
   e->kind = sys->kind;
   memset(e->prm, 0, sizeof e->prm);
-  for (int i = 0; i < required_params(sys->kind, sys->ndof); ++i) e->prm[i] = sys->params[i];
+  const int np = sys->kind == CHX_SYS_CUSTOM ? sys->nparams : required_params(sys->kind, sys->ndof);
+  for (int i = 0; i < np; ++i) e->prm[i] = sys->params[i];
+  if (sys->kind == CHX_SYS_CUSTOM) {
+    e->custom_src = sys->source;
+    e->custom = custom;
+  }
   e->pl = pl;
   e->pl.o.w0 = nullptr;  // copied below, never retained
   e->n_all = n;
@@ -280,6 +301,7 @@ chx_status create(const chx_system *sys, const double *x0, const uint8_t *mask, 
     ia.ld_p = pl.o.ld_p;
     memcpy(ia.prm, e->prm, sizeof ia.prm);
     if ((he = launch_init(a, ia, s))) return bail(he, "initialise ensemble");
+    if (e->custom && (he = custom_init(e->custom, a, s))) return bail(he, "initialise custom system");
   }
   // default launch granularity: about 5e10 orbit-steps per launch
   int64_t spl = pl.o.steps_per_launch;
@@ -315,7 +337,9 @@ chx_status advance(chx_ensemble *e, int64_t s_end) {
     a.s_begin = e->s_done;
     a.s_end = nxt;
     if (a.n > 0) {
-      hipError_t he = (e->kind == CHX_SYS_FPUT)
+      hipError_t he = (e->kind == CHX_SYS_CUSTOM)
+                          ? custom_launch(e->custom, pl, a, e->block, e->stream)
+                      : (e->kind == CHX_SYS_FPUT)
                           ? (pl.o.integrator != CHX_INT_YOSHIDA4
                                  ? launch_fput_crow_rk(pl.N, pl.M,
                                                        pl.o.integrator == CHX_INT_DOP853_ADAPTIVE,
@@ -451,6 +475,8 @@ chx_status subset(chx_ensemble *e, const uint8_t *keep, chx_ensemble **out, int6
   }
   e2->kind = e->kind;
   memcpy(e2->prm, e->prm, sizeof e2->prm);
+  e2->custom_src = e->custom_src;
+  e2->custom = e->custom;
   e2->pl = pl;
   e2->n_all = n2;
   e2->n_active = n2;

@@ -37,6 +37,8 @@ struct chx_ensemble {
   double *state = nullptr;   // x, w, gm, sc
   int *istate = nullptr;     // ge, st
   chx::StepArgs args{};
+  std::string custom_src;  // CHX_SYS_CUSTOM: the caller's source
+  void *custom = nullptr;  // its compiled program (process cache)
   int block = 256;
   int64_t steps_per_launch = 0;
 };
@@ -49,5 +51,10 @@ chx_status create(const chx_system *sys, const double *x0, const uint8_t *mask, 
 chx_status advance(chx_ensemble *e, int64_t s_end);
 chx_status results(chx_ensemble *e, chx_result *res);
 chx_status subset(chx_ensemble *e, const uint8_t *keep, chx_ensemble **out, int64_t **orbit_out);
+// custom.hip: user systems compiled at run time
+chx_status custom_prepare(const std::string &src, int ndof, const Plan &pl, void **handle);
+hipError_t custom_init(void *handle, const chx::StepArgs &a, hipStream_t s);
+hipError_t custom_launch(void *handle, const Plan &pl, const chx::StepArgs &a, int block,
+                         hipStream_t s);
 }  // namespace host
 }  // namespace chx

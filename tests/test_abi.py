@@ -31,10 +31,10 @@ def test_exports_every_declared_function():
 
 def test_struct_layouts_match_header():
     L = chx.lib()
-    assert L.chx_struct_size(0) == C.sizeof(chx._System) == 24
+    assert L.chx_struct_size(0) == C.sizeof(chx._System) == 32
     assert L.chx_struct_size(1) == C.sizeof(chx._Options) == 120
     assert L.chx_struct_size(2) == C.sizeof(chx._Result) == 13 * 8
-    assert L.chx_struct_size(3) == C.sizeof(chx._BatchItem) == 64
+    assert L.chx_struct_size(3) == C.sizeof(chx._BatchItem) == 72
     assert L.chx_struct_size(4) == C.sizeof(chx._BatchStats)
     assert L.chx_struct_size(5) == C.sizeof(chx._GateTrainCfg) == 40
     assert L.chx_struct_size(6) == C.sizeof(chx._GateStats) == 56
@@ -160,6 +160,43 @@ def test_ld_indicators_validation(kw, msg):
         kw.setdefault("dt", 0.01)
         chx.ld_indicators(P.henon_heiles(), hh_x0(), T=1.0, **kw)
     assert e.value.status == chx.ERR_INVALID_ARG and msg in str(e.value)
+
+
+CUSTOM_HH = r"""
+__device__ double chx_potential(const double *q, const double *prm) {
+  return 0.5 * (q[0] * q[0] + q[1] * q[1]) + q[0] * q[0] * q[1] - q[1] * q[1] * q[1] / 3.0;
+}
+__device__ void chx_force(const double *q, double *F, const double *prm) {
+  F[0] = q[0] + 2.0 * q[0] * q[1];
+  F[1] = q[1] + q[0] * q[0] - q[1] * q[1];
+}
+__device__ void chx_hess(const double *q, double *H, const double *prm) {
+  H[0] = 1.0 + 2.0 * q[1];
+  H[1] = 2.0 * q[0];
+  H[2] = 1.0 - 2.0 * q[1];
+}
+"""
+
+
+def test_custom_system_validation():
+    # checked, and the source compiled, before any device work
+    with pytest.raises(chx.ChxError, match="needs its source"):
+        chx.sali(chx.System(chx.SYS_CUSTOM, 2), hh_x0(), 0.01, 1.0, 1)
+    with pytest.raises(chx.ChxError, match="ndof 1..3"):
+        chx.sali(P.custom(4, CUSTOM_HH), np.zeros((2, 8)), 0.01, 1.0, 1)
+    with pytest.raises(chx.ChxError, match="0..16 params"):
+        chx.sali(P.custom(2, CUSTOM_HH, params=[0.0] * 17), hh_x0(), 0.01, 1.0, 1)
+    bad = CUSTOM_HH.replace("H[2] = 1.0 - 2.0 * q[1];", "H[2] = 1.0 - 2.0 * q[1]")
+    with pytest.raises(chx.ChxError) as e:
+        chx.sali(P.custom(2, bad), hh_x0(), 0.01, 1.0, 1)
+    assert e.value.status == chx.ERR_INVALID_ARG and "does not compile" in str(e.value)
+    missing = CUSTOM_HH.replace("chx_hess", "chx_hessian")
+    with pytest.raises(chx.ChxError, match="does not compile"):
+        chx.sali(P.custom(2, missing), hh_x0(), 0.01, 1.0, 1)
+    with pytest.raises(chx.ChxError) as e:
+        chx.integrate_batched([dict(sys=P.custom(2, CUSTOM_HH), x0=hh_x0(4), dt=0.01, T=1.0)],
+                              indicators=chx.IND_SALI)
+    assert e.value.status == chx.ERR_UNSUPPORTED
 
 
 def test_label_needs_sali():
