@@ -1018,6 +1018,85 @@ def bench_fig3(args, P, chx, torch, dev):
                  "launch_ms": kernel_s * 1e3 / max(len(log), 1), "launches_timed": len(log)}, cpu)
 
 
+CUSTOM_HH_SOURCE = r"""
+__device__ double chx_potential(const double *q, const double *prm) {
+  return 0.5 * (q[0] * q[0] + q[1] * q[1]) + q[0] * q[0] * q[1] - q[1] * q[1] * q[1] / 3.0;
+}
+__device__ void chx_force(const double *q, double *F, const double *prm) {
+  F[0] = q[0] + 2.0 * q[0] * q[1];
+  F[1] = q[1] + q[0] * q[0] - q[1] * q[1];
+}
+__device__ void chx_hess(const double *q, double *H, const double *prm) {
+  H[0] = 1.0 + 2.0 * q[1];
+  H[1] = 2.0 * q[0];
+  H[2] = 1.0 - 2.0 * q[1];
+}
+"""
+
+
+def bench_custom(args, P, chx, torch, dev):
+    """The headline workload (Henon-Heiles 1024^2 grids at both energies,
+    six vectors, SALI + GALI_2 + Lyapunov + LD + energy, dt = 0.01) with the
+    system given as user source (CHX_SYS_CUSTOM, compiled at run time), T =
+    1000 by default, beside the built-in system on the same grids: the run-
+    time compiled kernels against the library's own."""
+    import numpy as np
+
+    T = args.T or 1e3
+    dt, K = 0.01, 10
+    ind = chx.IND_SALI | chx.IND_GALI | chx.IND_LYAP | chx.IND_LD | chx.IND_ENERGY
+    xs, ms = [], []
+    for E in (0.125, 1.0 / 6.0):
+        x, m = P.grid_hh_section(E, args.grid, args.grid, device=dev)
+        xs.append(x)
+        ms.append(m)
+    x0, mask = torch.cat(xs), torch.cat(ms)
+    n_steps = int(round(T / dt))
+    spl = min(args.steps_per_launch or 25000, n_steps)
+    stream = torch.cuda.current_stream()
+    opts = dict(dt=dt, T=T, indicators=ind, gali_kmax=2, n_lyap=4, renorm_every=K, seed=1002,
+                escape_r2=4.0)
+    res = {}
+    t_compile = time.perf_counter()
+    P.integrate_ensemble(P.custom(2, CUSTOM_HH_SOURCE), x0[:64].contiguous(), dt=dt, T=0.1,
+                         indicators=ind, gali_kmax=2, n_lyap=4, seed=1002, outputs=("status",))
+    torch.cuda.synchronize()
+    compile_s = time.perf_counter() - t_compile
+    for name, sysg in (("custom", P.custom(2, CUSTOM_HH_SOURCE)), ("built-in", P.henon_heiles())):
+        log = []
+        e = P.Ensemble(sysg, x0, mask=mask, steps_per_launch=spl, outputs=("label",), **opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        advance_timed(e, n_steps, spl, stream, torch, log)
+        lab = e.results()["label"].cpu().numpy()
+        n_act = e.info()[2]
+        e.close()
+        torch.cuda.synchronize()
+        full = [a.elapsed_time(b) for a, b, k in log if k == spl]
+        res[name] = dict(s=time.perf_counter() - t0, launch_ms=float(np.mean(full)), labels=lab,
+                         n=n_act)
+        progress(f"custom: {name} system, {n_act} orbits, T={T:g}: {res[name]['s']:.2f} s")
+    fps = flops_per_step(2, 2, 4, True, True, True, K)
+    c = res["custom"]
+    achieved = fps * c["n"] * spl / (c["launch_ms"] * 1e-3)
+    value = c["n"] * n_steps / c["s"]
+    agree = float(np.mean(res["custom"]["labels"] == res["built-in"]["labels"]))
+    return emit(args, "FP64 trajectory-steps/s (with tangents), user-source system", value,
+                "orbit-steps/s", c["s"], "f64", {
+                    "workload": f"henon-heiles 1024x1024 section grids at E=0.125 and E=1/6 "
+                                f"given as user source (run-time compiled), dt={dt}, T={T:g}, "
+                                "SALI+GALI_2+4 Lyapunov+LD+energy; the built-in system beside it",
+                    "compile_s_first_call": compile_s,
+                    "launch_ms_custom": c["launch_ms"],
+                    "launch_ms_builtin": res["built-in"]["launch_ms"],
+                    "label_agreement_with_builtin": agree},
+                {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
+                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
+                 "kernel": "chx::lane_kernel<SysCustom, 6, false, 2> (run-time compiled)",
+                 "flops_per_orbit_step": fps, "launch_ms": c["launch_ms"],
+                 "launches_timed": None}, None)
+
+
 def auc(score, label):
     """Area under the ROC curve of score for label 1 against label 0 (ties
     counted half): the probability that a random chaotic orbit scores above
@@ -1128,7 +1207,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", choices=("hh", "fput", "batched", "gate", "sweep", "dop853",
-                                           "dop853_adaptive", "dp", "ldn", "fig2", "fig3"),
+                                           "dop853_adaptive", "dp", "ldn", "fig2", "fig3",
+                                           "custom"),
                     default="hh",
                     help="hh: the headline Henon-Heiles grids (default); fput: FPU-beta "
                          "chains with 3N deviation vectors; batched: the persistent mixed "
@@ -1140,7 +1220,8 @@ def parse():
                          "IC against the ensemble size, fixed and adaptive; ldn: chaos "
                          "indicators from the LDs of neighbouring orbits against SALI labels; "
                          "fig2: Henon-Heiles time per IC against the ensemble size with the "
-                         "adaptive solver; fig3: FPU time against the degrees of freedom")
+                         "adaptive solver; fig3: FPU time against the degrees of freedom; "
+                         "custom: the headline grids with the system given as user source")
     ap.add_argument("--grid", type=int, default=1024, help="grid side per energy")
     ap.add_argument("--T", type=float, default=None,
                     help="final time (default: 1e4 for hh, gate and batched, 2e3 for fput, "
@@ -1186,7 +1267,8 @@ def main():
         fn = {"fput": bench_fput, "batched": bench_batched, "gate": bench_gate,
               "sweep": bench_sweep, "dop853": bench_dop853,
               "dop853_adaptive": bench_dop853_adaptive, "dp": bench_dp,
-              "ldn": bench_ldn, "fig2": bench_fig2, "fig3": bench_fig3}[args.workload]
+              "ldn": bench_ldn, "fig2": bench_fig2, "fig3": bench_fig3,
+              "custom": bench_custom}[args.workload]
         print(json.dumps(fn(args, P, chx, torch, dev)), flush=True)
         return
     if args.T is None:
