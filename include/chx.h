@@ -80,7 +80,7 @@ enum {
                                or CHX_INT_DOP853_ADAPTIVE (else
                                CHX_ERR_UNSUPPORTED); the LD integrand is
                                sum_c |dx_c/dt|^p over the four components */
-  CHX_SYS_CUSTOM = 6        /* a separable system given by the caller (the paper's
+  CHX_SYS_CUSTOM = 6,       /* a separable system given by the caller (the paper's
                                package integrates any Hamiltonian the user writes):
                                H = |p|^2/2 + V(q), ndof 1..3, up to 16 params
                                (nparams of them, passed as prm).  source holds HIP
@@ -101,6 +101,23 @@ enum {
                                source that does not compile gives
                                CHX_ERR_INVALID_ARG with the compiler's log.  All
                                integrators; not in the batched form or the gate. */
+  CHX_SYS_CUSTOM_GENERAL = 7 /* any Hamiltonian given by the caller, ndof 1..3,
+                               up to 16 params.  source defines
+                                 template <class T> __device__ void chx_field(
+                                     const T *x, T *f, const double *prm);
+                                     f = Hamilton's equations J grad H at
+                                     x = (q, p), 2N values, written over a
+                                     generic number type T (double and the
+                                     library's dual numbers, which provide
+                                     + - * /, with double operands too, and
+                                     sin cos exp log sqrt pow(T, double));
+                                 __device__ double chx_hamiltonian(
+                                     const double *x, const double *prm);
+                               The variational equations take the field's
+                               directional derivatives through the dual
+                               numbers.  DOP853 and adaptive DOP8(5) only (else
+                               CHX_ERR_UNSUPPORTED); compiled and cached as
+                               CHX_SYS_CUSTOM. */
 };
 
 typedef struct {

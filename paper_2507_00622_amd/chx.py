@@ -17,8 +17,8 @@ LIB_PATH = os.path.join(HERE, "libchx.so")
 
 # --- constants mirrored from include/chx.h -----------------------------------
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_INTERNAL = range(6)
-SYS_HENON_HEILES, SYS_FPUT, SYS_QUARTIC, SYS_HARMONIC, SYS_DOUBLE_PENDULUM, SYS_CUSTOM = (
-    1, 2, 3, 4, 5, 6)
+(SYS_HENON_HEILES, SYS_FPUT, SYS_QUARTIC, SYS_HARMONIC, SYS_DOUBLE_PENDULUM, SYS_CUSTOM,
+ SYS_CUSTOM_GENERAL) = (1, 2, 3, 4, 5, 6, 7)
 IND_SALI, IND_GALI, IND_LYAP, IND_LD, IND_ENERGY = 1, 2, 4, 8, 16
 PTR_DEVICE = 1
 INT_YOSHIDA4, INT_DOP853, INT_DOP853_ADAPTIVE = 0, 1, 2
@@ -202,6 +202,15 @@ def custom(ndof, source, params=()):
     defining chx_potential, chx_force (grad V) and chx_hess (Hess V, upper
     triangle packed row by row); ndof 1..3, up to 16 params (see chx.h)."""
     return System(SYS_CUSTOM, int(ndof), tuple(float(v) for v in params), str(source))
+
+
+def custom_general(ndof, source, params=()):
+    """Any Hamiltonian: HIP device code defining
+    template <class T> __device__ void chx_field(const T *x, T *f, const double *prm)
+    (Hamilton's equations over a generic number type) and
+    __device__ double chx_hamiltonian(const double *x, const double *prm);
+    ndof 1..3, up to 16 params; "dop853" or "dop853_adaptive" only."""
+    return System(SYS_CUSTOM_GENERAL, int(ndof), tuple(float(v) for v in params), str(source))
 
 
 def double_pendulum(alpha=1.0, sigma=1.0):

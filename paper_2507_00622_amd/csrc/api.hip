@@ -52,7 +52,8 @@ int required_params(int kind, int ndof) {
   case CHX_SYS_QUARTIC: return 1;
   case CHX_SYS_HARMONIC: return ndof;
   case CHX_SYS_DOUBLE_PENDULUM: return 2;
-  case CHX_SYS_CUSTOM: return 0;
+  case CHX_SYS_CUSTOM:
+  case CHX_SYS_CUSTOM_GENERAL: return 0;
   }
   return -1;
 }
@@ -75,6 +76,7 @@ chx_status check_system(const chx_system *sys) {
     if (N != 2) return fail(CHX_ERR_INVALID_ARG, "the double pendulum needs ndof == 2 (got %d)", N);
     break;
   case CHX_SYS_CUSTOM:
+  case CHX_SYS_CUSTOM_GENERAL:
     if (N < 1 || N > 3) return fail(CHX_ERR_INVALID_ARG, "a custom system needs ndof 1..3 (got %d)", N);
     if (!sys->source || !sys->source[0]) return fail(CHX_ERR_INVALID_ARG, "a custom system needs its source");
     if (sys->nparams < 0 || sys->nparams > 16)
@@ -141,6 +143,8 @@ chx_status make_plan(const chx_system *sys, const chx_options *opt, Plan *p) {
     return fail(CHX_ERR_UNSUPPORTED, "the FPU kernels compute the LD with p = 1/2 only");
   if (o.integrator == CHX_INT_YOSHIDA4 && sys->kind == CHX_SYS_DOUBLE_PENDULUM)
     return fail(CHX_ERR_UNSUPPORTED, "the double pendulum is not separable: integrate it with DOP853 (fixed or adaptive)");
+  if (o.integrator == CHX_INT_YOSHIDA4 && sys->kind == CHX_SYS_CUSTOM_GENERAL)
+    return fail(CHX_ERR_UNSUPPORTED, "a general custom system is not separable: integrate it with DOP853 (fixed or adaptive)");
   if (o.integrator == CHX_INT_DOP853_ADAPTIVE) {
     if (o.rtol == 0.0 && o.atol == 0.0) o.rtol = o.atol = 1e-10;
     if (!(o.rtol >= 0.0) || !(o.atol >= 0.0) || !isfinite(o.rtol) || !isfinite(o.atol))
@@ -204,17 +208,18 @@ chx_status create(const chx_system *sys, const double *x0, const uint8_t *mask, 
   if (!device && pl.o.stream) return fail(CHX_ERR_INVALID_ARG, "stream given without CHX_PTR_DEVICE");
 
   void *custom = nullptr;
-  if (sys->kind == CHX_SYS_CUSTOM) {
+  const bool is_custom = sys->kind == CHX_SYS_CUSTOM || sys->kind == CHX_SYS_CUSTOM_GENERAL;
+  if (is_custom) {
     // compile before any device work, so that source errors come first
-    st = custom_prepare(sys->source, sys->ndof, pl, &custom);
+    st = custom_prepare(sys->source, sys->ndof, sys->kind == CHX_SYS_CUSTOM_GENERAL, pl, &custom);
     if (st) return st;
   }
   chx_ensemble *e = new chx_ensemble();
   e->kind = sys->kind;
   memset(e->prm, 0, sizeof e->prm);
-  const int np = sys->kind == CHX_SYS_CUSTOM ? sys->nparams : required_params(sys->kind, sys->ndof);
+  const int np = is_custom ? sys->nparams : required_params(sys->kind, sys->ndof);
   for (int i = 0; i < np; ++i) e->prm[i] = sys->params[i];
-  if (sys->kind == CHX_SYS_CUSTOM) {
+  if (is_custom) {
     e->custom_src = sys->source;
     e->custom = custom;
   }
@@ -337,8 +342,9 @@ chx_status advance(chx_ensemble *e, int64_t s_end) {
     a.s_begin = e->s_done;
     a.s_end = nxt;
     if (a.n > 0) {
-      hipError_t he = (e->kind == CHX_SYS_CUSTOM)
-                          ? custom_launch(e->custom, pl, a, e->block, e->stream)
+      hipError_t he = e->custom
+                          ? custom_launch(e->custom, e->kind == CHX_SYS_CUSTOM_GENERAL, pl, a,
+                                          e->block, e->stream)
                       : (e->kind == CHX_SYS_FPUT)
                           ? (pl.o.integrator != CHX_INT_YOSHIDA4
                                  ? launch_fput_crow_rk(pl.N, pl.M,

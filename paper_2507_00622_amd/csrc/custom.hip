@@ -1,11 +1,12 @@
-// custom.hip -- user-supplied separable systems (CHX_SYS_CUSTOM): the
-// user's potential, gradient and Hessian (HIP device code) are compiled at
-// run time with hipRTC together with the library's own lane-per-orbit
-// kernel templates (lane_kernel.h, lane_rk.h), so a custom system runs the
-// same Yoshida-4, DOP853 and adaptive DOP8(5) kernels, checkpoints and
-// indicators as the built-in ones.  The paper's package integrates any
-// Hamiltonian system given by the user; this is that entry for H =
-// |p|^2/2 + V(q) with N <= 3.
+// custom.hip -- user-supplied systems: separable (CHX_SYS_CUSTOM: the
+// user's potential, gradient and Hessian) or general (CHX_SYS_CUSTOM_GENERAL:
+// the user's field J grad H over a generic number type, and H), HIP device
+// code compiled at run time with hipRTC together with the library's own
+// lane-per-orbit kernel templates (lane_kernel.h, lane_rk.h), so a custom
+// system runs the same Yoshida-4 (separable only), DOP853 and adaptive
+// DOP8(5) kernels, checkpoints and indicators as the built-in ones.  The
+// paper's package integrates any Hamiltonian system given by its user; this
+// is that entry, for N <= 3.
 //
 // The kernel headers are read from the csrc/ directory beside libchx.so
 // (and include/chx.h from ../include), so the run-time compilation uses the
@@ -50,9 +51,10 @@ const char *kStdintStub =
     "#define INT64_MAX 9223372036854775807L\n";
 const char *kStddefStub = "#pragma once\n";
 
-// The wrapper that turns the user's functions into a system of the lane
+// The wrappers that turn the user's functions into a system of the lane
 // kernels, and the kernel that sets H(0) and the LD integrand at t = 0
-// (the built-in set-up kernel knows only the built-in systems).
+// (the built-in set-up kernel knows only the built-in systems).  Separable
+// form: V, grad V, Hess V.
 const char *kWrapper = R"(
 namespace chx {
 struct SysCustom {
@@ -89,6 +91,73 @@ extern "C" __global__ void chx_custom_init(const chx::StepArgs a) {
     g += (a.ld_p == 0.5) ? sqrt(fabs(F[r])) : pow(fabs(F[r]), a.ld_p);
   }
   a.sc[chx::SC_H0 * P + i] = 0.5 * kin + chx::SysCustom::potential(x, a.prm);
+  a.sc[chx::SC_GPREV * P + i] = (a.ind & CHX_IND_LD) ? g : 0.0;
+}
+)";
+
+// General form (any Hamiltonian): the field f = J grad H written once over
+// T = double and T = MDual<M> (value and M derivative parts), and H itself;
+// the Runge-Kutta kernels take the field, the records and the tangents
+// from it exactly as for the built-in double pendulum.
+const char *kWrapperGeneral = R"(
+namespace chx {
+struct SysCustom {
+  static constexpr int N = CHX_CUSTOM_NDOF;
+  static constexpr int NREC = 2 * N;  // stage record: the stage state
+  __device__ static inline void rhs_rec(const double *x, double *f, double *rec,
+                                        const double *prm) {
+#pragma unroll
+    for (int c = 0; c < 2 * N; ++c) rec[c] = x[c];
+    ::chx_field<double>(x, f, prm);
+  }
+  __device__ static inline void jvp(const double *rec, const double *dx, double *df,
+                                    const double *prm) {
+    MDual<1> X[2 * N], F[2 * N];
+#pragma unroll
+    for (int c = 0; c < 2 * N; ++c) {
+      X[c].v = rec[c];
+      X[c].d[0] = dx[c];
+    }
+    ::chx_field<MDual<1>>(X, F, prm);
+#pragma unroll
+    for (int c = 0; c < 2 * N; ++c) df[c] = F[c].d[0];
+  }
+  template <int M>
+  __device__ static inline void rhs_multi(const double *x, const double (&dx)[M][2 * N],
+                                          double *f, double (&df)[M][2 * N], const double *prm) {
+    MDual<M> X[2 * N], F[2 * N];
+#pragma unroll
+    for (int c = 0; c < 2 * N; ++c) {
+      X[c].v = x[c];
+#pragma unroll
+      for (int v = 0; v < M; ++v) X[c].d[v] = dx[v][c];
+    }
+    ::chx_field<MDual<M>>(X, F, prm);
+#pragma unroll
+    for (int c = 0; c < 2 * N; ++c) {
+      f[c] = F[c].v;
+#pragma unroll
+      for (int v = 0; v < M; ++v) df[v][c] = F[c].d[v];
+    }
+  }
+  __device__ static inline double hamiltonian(const double *x, const double *prm) {
+    return ::chx_hamiltonian(x, prm);
+  }
+};
+}  // namespace chx
+
+extern "C" __global__ void chx_custom_init(const chx::StepArgs a) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n || a.st[i] != CHX_ORBIT_OK) return;
+  constexpr int N = chx::SysCustom::N;
+  const long P = a.pitch;
+  double x[2 * N], f[2 * N];
+  for (int c = 0; c < 2 * N; ++c) x[c] = a.x[c * P + i];
+  ::chx_field<double>(x, f, a.prm);
+  double g = 0.0;
+  for (int c = 0; c < 2 * N; ++c)
+    g += (a.ld_p == 0.5) ? sqrt(fabs(f[c])) : pow(fabs(f[c]), a.ld_p);
+  a.sc[chx::SC_H0 * P + i] = chx::SysCustom::hamiltonian(x, a.prm);
   a.sc[chx::SC_GPREV * P + i] = (a.ind & CHX_IND_LD) ? g : 0.0;
 }
 )";
@@ -134,7 +203,8 @@ std::string kernel_expr(int integrator, int M, bool gp, int m_s) {
   return b;
 }
 
-chx_status compile(const std::string &src, int ndof, const std::string &expr, Program *pg) {
+chx_status compile(const std::string &src, int ndof, bool general, const std::string &expr,
+                   Program *pg) {
   const std::string dir = lib_dir();
   if (dir.empty()) return fail(CHX_ERR_INTERNAL, "custom system: cannot locate libchx.so");
   const char *hdr[] = {"chx_internal.h", "device_math.h", "systems.h", "lane_kernel.h",
@@ -167,7 +237,8 @@ chx_status compile(const std::string &src, int ndof, const std::string &expr, Pr
   }
   const std::string full = "#include \"lane_rk.h\"\n#define CHX_CUSTOM_NDOF " +
                            std::to_string(ndof) + "\n#line 1 \"custom system\"\n" + src +
-                           "\n#line 1 \"custom wrapper\"\n" + kWrapper;
+                           "\n#line 1 \"custom wrapper\"\n" +
+                           (general ? kWrapperGeneral : kWrapper);
   hiprtcProgram p;
   if (hiprtcCreateProgram(&p, full.c_str(), "custom.hip", (int)hn.size(), hb.data(), hn.data()) !=
       HIPRTC_SUCCESS)
@@ -204,15 +275,17 @@ chx_status compile(const std::string &src, int ndof, const std::string &expr, Pr
 
 // Compile (or find) the program of the ensemble's custom system for its
 // plan; no device work, so compile errors surface before any allocation.
-chx_status custom_prepare(const std::string &src, int ndof, const Plan &pl, void **handle) {
+chx_status custom_prepare(const std::string &src, int ndof, bool general, const Plan &pl,
+                          void **handle) {
   const bool gp = (pl.o.indicators & CHX_IND_LD) && pl.o.ld_p != 0.5;
   const std::string expr = kernel_expr(pl.o.integrator, pl.M, gp, pl.m_s);
-  const std::string key = std::to_string(ndof) + "\n" + expr + "\n" + src;
+  const std::string key =
+      std::to_string(ndof) + (general ? " general\n" : " separable\n") + expr + "\n" + src;
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_progs.find(key);
   if (it == g_progs.end()) {
     auto pg = std::make_unique<Program>();
-    const chx_status st = compile(src, ndof, expr, pg.get());
+    const chx_status st = compile(src, ndof, general, expr, pg.get());
     if (st) return st;
     it = g_progs.emplace(key, std::move(pg)).first;
   }
@@ -247,11 +320,10 @@ hipError_t custom_init(void *handle, const StepArgs &a, hipStream_t s) {
 }
 
 // One integration launch with the plan's kernel: lane per orbit, block
-// threads per block; the Runge-Kutta kernels take their stage records (N
-// doubles per stage and thread) and, adaptive, the attempted vectors in
-// dynamic LDS, at most 64 KB per block.
-hipError_t custom_launch(void *handle, const Plan &pl, const StepArgs &a, int block,
-                         hipStream_t s) {
+// threads per block; the Runge-Kutta kernels take their stage records and,
+// adaptive, the attempted vectors in dynamic LDS, at most 64 KB per block.
+hipError_t custom_launch(void *handle, bool general, const Plan &pl, const StepArgs &a,
+                         int block, hipStream_t s) {
   Program *pg = (Program *)handle;
   if (a.n == 0) return hipSuccess;
   hipError_t e;
@@ -262,7 +334,10 @@ hipError_t custom_launch(void *handle, const Plan &pl, const StepArgs &a, int bl
   size_t lds = 0;
   if (pl.o.integrator != CHX_INT_YOSHIDA4 && pl.M > 0) {
     const bool adaptive = pl.o.integrator == CHX_INT_DOP853_ADAPTIVE;
-    const size_t per = sizeof(double) * (12 * pl.N + (adaptive ? pl.M * 2 * pl.N : 0));
+    // per stage: the positions (separable); the stage state (general),
+    // none when one or two vectors go through the stages with the state
+    const int stage = general ? ((pl.M <= 2) ? 0 : 2 * pl.N) : pl.N;
+    const size_t per = sizeof(double) * (12 * stage + (adaptive ? pl.M * 2 * pl.N : 0));
     while (block > 64 && per * (size_t)block > 65536) block /= 2;
     lds = per * (size_t)block;
   }

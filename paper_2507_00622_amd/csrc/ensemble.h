@@ -52,9 +52,10 @@ chx_status advance(chx_ensemble *e, int64_t s_end);
 chx_status results(chx_ensemble *e, chx_result *res);
 chx_status subset(chx_ensemble *e, const uint8_t *keep, chx_ensemble **out, int64_t **orbit_out);
 // custom.hip: user systems compiled at run time
-chx_status custom_prepare(const std::string &src, int ndof, const Plan &pl, void **handle);
+chx_status custom_prepare(const std::string &src, int ndof, bool general, const Plan &pl,
+                          void **handle);
 hipError_t custom_init(void *handle, const chx::StepArgs &a, hipStream_t s);
-hipError_t custom_launch(void *handle, const Plan &pl, const chx::StepArgs &a, int block,
-                         hipStream_t s);
+hipError_t custom_launch(void *handle, bool general, const Plan &pl, const chx::StepArgs &a,
+                         int block, hipStream_t s);
 }  // namespace host
 }  // namespace chx

@@ -33,14 +33,16 @@ bool lane_supported(int sys, int ndof, int M) {
   case SYS_QUARTIC:
   case SYS_HARMONIC: return ndof >= 1 && ndof <= 3;
   case SYS_DP: return ndof == 2;  // DOP853 kernels only
-  case CHX_SYS_CUSTOM: return ndof >= 1 && ndof <= 3;  // compiled at run time
+  case CHX_SYS_CUSTOM:
+  case CHX_SYS_CUSTOM_GENERAL: return ndof >= 1 && ndof <= 3;  // compiled at run time
   }
   return false;
 }
 
 hipError_t launch_lane(int sys, int ndof, int M, const StepArgs &a, int block,
                        hipStream_t s) {
-  if (!lane_supported(sys, ndof, M) || sys == SYS_DP || sys == CHX_SYS_CUSTOM)
+  if (!lane_supported(sys, ndof, M) || sys == SYS_DP || sys == CHX_SYS_CUSTOM ||
+      sys == CHX_SYS_CUSTOM_GENERAL)
     return hipErrorInvalidValue;
   if (a.n == 0) return hipSuccess;
   switch (sys) {

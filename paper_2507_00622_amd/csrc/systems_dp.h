@@ -84,6 +84,88 @@ __device__ __forceinline__ MDual<M> inv(const MDual<M> &a) {
 }
 __device__ __forceinline__ double inv(double a) { return 1.0 / a; }
 
+// The rest of the arithmetic a general field written over T may use (the
+// run-time compiled user systems write theirs this way): mixed operands,
+// negation, quotients and the elementary functions, each with its
+// derivative parts by the chain rule.
+template <int M>
+__device__ __forceinline__ MDual<M> operator-(const MDual<M> &a) {
+  return 0.0 - a;
+}
+template <int M>
+__device__ __forceinline__ MDual<M> operator*(const MDual<M> &a, double k) {
+  return k * a;
+}
+template <int M>
+__device__ __forceinline__ MDual<M> operator+(const MDual<M> &a, double k) {
+  MDual<M> r = a;
+  r.v = a.v + k;
+  return r;
+}
+template <int M>
+__device__ __forceinline__ MDual<M> operator+(double k, const MDual<M> &a) {
+  return a + k;
+}
+template <int M>
+__device__ __forceinline__ MDual<M> operator-(const MDual<M> &a, double k) {
+  return a + (-k);
+}
+template <int M>
+__device__ __forceinline__ MDual<M> operator/(const MDual<M> &a, const MDual<M> &b) {
+  return a * inv(b);
+}
+template <int M>
+__device__ __forceinline__ MDual<M> operator/(const MDual<M> &a, double k) {
+  return (1.0 / k) * a;
+}
+template <int M>
+__device__ __forceinline__ MDual<M> operator/(double k, const MDual<M> &b) {
+  return k * inv(b);
+}
+// (the library's double functions stay visible beside these overloads)
+using ::cos;
+using ::exp;
+using ::log;
+using ::pow;
+using ::sin;
+using ::sqrt;
+// f(a) with value fv and derivative dv at a.v
+template <int M>
+__device__ __forceinline__ MDual<M> chain(const MDual<M> &a, double fv, double dv) {
+  MDual<M> r;
+  r.v = fv;
+#pragma unroll
+  for (int i = 0; i < M; ++i) r.d[i] = dv * a.d[i];
+  return r;
+}
+template <int M>
+__device__ __forceinline__ MDual<M> sin(const MDual<M> &a) {
+  return chain(a, ::sin(a.v), ::cos(a.v));
+}
+template <int M>
+__device__ __forceinline__ MDual<M> cos(const MDual<M> &a) {
+  return chain(a, ::cos(a.v), -::sin(a.v));
+}
+template <int M>
+__device__ __forceinline__ MDual<M> exp(const MDual<M> &a) {
+  const double e = ::exp(a.v);
+  return chain(a, e, e);
+}
+template <int M>
+__device__ __forceinline__ MDual<M> log(const MDual<M> &a) {
+  return chain(a, ::log(a.v), 1.0 / a.v);
+}
+template <int M>
+__device__ __forceinline__ MDual<M> sqrt(const MDual<M> &a) {
+  const double r = ::sqrt(a.v);
+  return chain(a, r, 0.5 / r);
+}
+template <int M>
+__device__ __forceinline__ MDual<M> pow(const MDual<M> &a, double k) {
+  const double r = ::pow(a.v, k);
+  return chain(a, r, k * ::pow(a.v, k - 1.0));
+}
+
 // sin and cos of an angle x with |x| < 2^32 (NaN beyond): Cody-Waite
 // reduction x = k pi/2 + r + dr, k = rint(2x/pi), with pi/2 split into five
 // heads of at most 20 significant bits (each k * head exact for |k| < 2^32)

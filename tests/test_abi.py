@@ -197,6 +197,10 @@ def test_custom_system_validation():
         chx.integrate_batched([dict(sys=P.custom(2, CUSTOM_HH), x0=hh_x0(4), dt=0.01, T=1.0)],
                               indicators=chx.IND_SALI)
     assert e.value.status == chx.ERR_UNSUPPORTED
+    # a general system is not separable: no Yoshida-4
+    with pytest.raises(chx.ChxError) as e:
+        chx.sali(P.custom_general(2, "/* field */"), hh_x0(), 0.01, 1.0, 1)
+    assert e.value.status == chx.ERR_UNSUPPORTED and "not separable" in str(e.value)
 
 
 def test_label_needs_sali():

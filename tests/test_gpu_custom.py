@@ -204,3 +204,51 @@ def test_custom_harmonic_and_ld_indicators_and_subset(env):
     e.close()
     for k in r:
         assert np.array_equal(r[k], g[k][::3], equal_nan=True), k
+
+
+# the double pendulum written by a user as a general field over T
+DP_GENERAL = r"""
+template <class T>
+__device__ void chx_field(const T *x, T *f, const double *prm) {
+  const double al = prm[0], sg = prm[1];
+  const T c = cos(x[0] - x[1]), s = sin(x[0] - x[1]);
+  const T D = (1.0 + sg) - c * c;
+  const T p1 = x[2], p2 = x[3];
+  f[0] = (p1 / (al * al) - c * p2 / al) / D;
+  f[1] = ((1.0 + sg) * p2 - c * p1 / al) / D;
+  const T Q = p1 * p1 / (al * al) - 2.0 * c * p1 * p2 / al + (1.0 + sg) * p2 * p2;
+  const T dTdc = (c * Q - p1 * p2 * D / al) / (D * D);
+  f[2] = s * dTdc - al * (1.0 + sg) * sin(x[0]);
+  f[3] = -(s * dTdc) - sin(x[1]);
+}
+__device__ double chx_hamiltonian(const double *x, const double *prm) {
+  const double al = prm[0], sg = prm[1];
+  const double c = cos(x[0] - x[1]);
+  const double D = 1.0 + sg - c * c;
+  const double Q = x[2] * x[2] / (al * al) - 2.0 * c * x[2] * x[3] / al + (1.0 + sg) * x[3] * x[3];
+  return Q / (2.0 * D) - al * (1.0 + sg) * cos(x[0]) - cos(x[1]);
+}
+"""
+
+
+@pytest.mark.parametrize("integ,nvec", [("dop853", 2), ("dop853", 8), ("dop853_adaptive", 2)])
+def test_custom_general_double_pendulum(env, integ, nvec):
+    torch, P, O = env
+    say(f"case: user-written double pendulum (general field), {integ}, {nvec} vectors, T=10")
+    x0 = S.dp_states(74, 200, np.pi, 1.0)
+    extra = dict(rtol=1e-10, atol=1e-10) if integ == "dop853_adaptive" else {}
+    ind = ALL if nvec == 8 else (O.IND_SALI | O.IND_LD | O.IND_ENERGY)
+    kw = dict(dt=0.1 if integ == "dop853_adaptive" else 0.01, T=10.0, indicators=ind, **extra)
+    if nvec == 8:
+        kw.update(gali_kmax=4, n_lyap=4)
+    w0 = S.deviation_vectors(75, len(x0), 4 if nvec == 8 else 2, 4)
+    g = run_gpu(env, P.custom_general(2, DP_GENERAL, params=[0.7, 2.5]), x0, None, w0,
+                integrator=integ, **kw)
+    o = O.integrate(O.double_pendulum(0.7, 2.5), x0, oracle_run(O, integ, **kw), w0=w0,
+                    threads=8)
+    assert np.array_equal(g["status"], o["status"])
+    sel = np.ones(len(x0), bool)
+    if integ == "dop853_adaptive":
+        sel = (g["steps"][:, 0] == o["steps_accepted"]) & (g["steps"][:, 1] == o["steps_rejected"])
+        assert sel.sum() >= 0.99 * len(x0)
+    compare(g, o, sel, 1e-3 if integ == "dop853_adaptive" else 1e-9, f"dp general {nvec}")
