@@ -14,7 +14,8 @@
 // hip/hip_runtime.h, stddef.h and stdint.h are given as small stand-ins
 // holding what the headers' host-side declarations name (never compiled
 // into device code).  Compiled programs are cached per process, keyed by
-// the source text, ndof and the kernel instantiation.
+// the source text, ndof and the kernel instantiation, and loaded on each
+// device where they run.
 #include <dlfcn.h>
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
@@ -162,11 +163,14 @@ extern "C" __global__ void chx_custom_init(const chx::StepArgs a) {
 }
 )";
 
-struct Program {
+struct Loaded {
   hipModule_t mod = nullptr;
-  std::vector<char> code;
-  std::string lowered;  // the integration kernel's symbol
   hipFunction_t kernel = nullptr, init = nullptr;
+};
+struct Program {
+  std::vector<char> code;
+  std::string lowered;        // the integration kernel's symbol
+  std::map<int, Loaded> dev;  // the code object loaded on each device used
 };
 
 std::mutex g_mu;
@@ -294,12 +298,19 @@ chx_status custom_prepare(const std::string &src, int ndof, bool general, const 
 }
 
 namespace {
-hipError_t load(Program *pg) {
-  if (pg->mod) return hipSuccess;
-  hipError_t e = hipModuleLoadData(&pg->mod, pg->code.data());
+// the program's functions on the current device (loaded there at first use)
+hipError_t load(Program *pg, Loaded **out) {
+  int d = 0;
+  hipError_t e = hipGetDevice(&d);
   if (e != hipSuccess) return e;
-  if ((e = hipModuleGetFunction(&pg->kernel, pg->mod, pg->lowered.c_str())) != hipSuccess) return e;
-  return hipModuleGetFunction(&pg->init, pg->mod, "chx_custom_init");
+  Loaded &l = pg->dev[d];
+  if (!l.mod) {
+    if ((e = hipModuleLoadData(&l.mod, pg->code.data())) != hipSuccess) return e;
+    if ((e = hipModuleGetFunction(&l.kernel, l.mod, pg->lowered.c_str())) != hipSuccess) return e;
+    if ((e = hipModuleGetFunction(&l.init, l.mod, "chx_custom_init")) != hipSuccess) return e;
+  }
+  *out = &l;
+  return hipSuccess;
 }
 }  // namespace
 
@@ -309,14 +320,15 @@ hipError_t custom_init(void *handle, const StepArgs &a, hipStream_t s) {
   Program *pg = (Program *)handle;
   if (a.n == 0) return hipSuccess;
   hipError_t e;
+  Loaded *l = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    if ((e = load(pg)) != hipSuccess) return e;
+    if ((e = load(pg, &l)) != hipSuccess) return e;
   }
   StepArgs arg = a;
   void *params[] = {&arg};
   const unsigned grid = (unsigned)((a.n + 255) / 256);
-  return hipModuleLaunchKernel(pg->init, grid, 1, 1, 256, 1, 1, 0, s, params, nullptr);
+  return hipModuleLaunchKernel(l->init, grid, 1, 1, 256, 1, 1, 0, s, params, nullptr);
 }
 
 // One integration launch with the plan's kernel: lane per orbit, block
@@ -327,9 +339,10 @@ hipError_t custom_launch(void *handle, bool general, const Plan &pl, const StepA
   Program *pg = (Program *)handle;
   if (a.n == 0) return hipSuccess;
   hipError_t e;
+  Loaded *l = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    if ((e = load(pg)) != hipSuccess) return e;
+    if ((e = load(pg, &l)) != hipSuccess) return e;
   }
   size_t lds = 0;
   if (pl.o.integrator != CHX_INT_YOSHIDA4 && pl.M > 0) {
@@ -344,7 +357,7 @@ hipError_t custom_launch(void *handle, bool general, const Plan &pl, const StepA
   StepArgs arg = a;
   void *params[] = {&arg};
   const unsigned grid = (unsigned)((a.n + block - 1) / block);
-  return hipModuleLaunchKernel(pg->kernel, grid, 1, 1, (unsigned)block, 1, 1, (unsigned)lds, s,
+  return hipModuleLaunchKernel(l->kernel, grid, 1, 1, (unsigned)block, 1, 1, (unsigned)lds, s,
                                params, nullptr);
 }
 
