@@ -247,7 +247,10 @@ chx_status compile(const std::string &src, int ndof, bool general, const std::st
   if (hiprtcCreateProgram(&p, full.c_str(), "custom.hip", (int)hn.size(), hb.data(), hn.data()) !=
       HIPRTC_SUCCESS)
     return fail(CHX_ERR_INTERNAL, "custom system: hiprtcCreateProgram failed");
-  hiprtcAddNameExpression(p, expr.c_str());
+  if (hiprtcAddNameExpression(p, expr.c_str()) != HIPRTC_SUCCESS) {
+    hiprtcDestroyProgram(&p);
+    return fail(CHX_ERR_INTERNAL, "custom system: cannot name kernel %s", expr.c_str());
+  }
   const char *opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off",
                         "-Wno-cuda-compat", "-Xclang", "-target-feature", "-Xclang",
                         "-packed-fp32-ops"};
@@ -268,10 +271,14 @@ chx_status compile(const std::string &src, int ndof, bool general, const std::st
   }
   pg->lowered = low;
   size_t cs = 0;
-  hiprtcGetCodeSize(p, &cs);
-  pg->code.resize(cs);
-  hiprtcGetCode(p, pg->code.data());
+  hiprtcResult rc = hiprtcGetCodeSize(p, &cs);
+  if (rc == HIPRTC_SUCCESS && cs > 0) {
+    pg->code.resize(cs);
+    rc = hiprtcGetCode(p, pg->code.data());
+  }
   hiprtcDestroyProgram(&p);
+  if (rc != HIPRTC_SUCCESS || cs == 0)
+    return fail(CHX_ERR_INTERNAL, "custom system: no code object from hipRTC");
   return CHX_OK;
 }
 
