@@ -82,7 +82,7 @@ enum {
                                sum_c |dx_c/dt|^p over the four components */
   CHX_SYS_CUSTOM = 6,       /* a separable system given by the caller (the paper's
                                package integrates any Hamiltonian the user writes):
-                               H = |p|^2/2 + V(q), ndof 1..3, up to 16 params
+                               H = |p|^2/2 + V(q), ndof 1..8, up to 16 params
                                (nparams of them, passed as prm).  source holds HIP
                                device code defining
                                  __device__ double chx_potential(const double *q,
@@ -100,8 +100,15 @@ enum {
                                cached per process by source, ndof and variant);
                                source that does not compile gives
                                CHX_ERR_INVALID_ARG with the compiler's log.  All
-                               integrators; not in the batched form or the gate. */
-  CHX_SYS_CUSTOM_GENERAL = 7 /* any Hamiltonian given by the caller, ndof 1..3,
+                               integrators; not in the batched form or the gate.
+                               One lane holds an orbit with its vectors, so large
+                               ndof x vectors run slower (register spills).  The
+                               DOP853 kernels keep per-stage values in LDS, at most
+                               1024 B per orbit: 8 (12 N + [adaptive] 2 N M) bytes
+                               here, 8 (12 [M > 2] 2 N + [adaptive] 2 N M) for
+                               CHX_SYS_CUSTOM_GENERAL; more gives
+                               CHX_ERR_UNSUPPORTED. */
+  CHX_SYS_CUSTOM_GENERAL = 7 /* any Hamiltonian given by the caller, ndof 1..8,
                                up to 16 params.  source defines
                                  template <class T> __device__ void chx_field(
                                      const T *x, T *f, const double *prm);

@@ -200,7 +200,7 @@ def harmonic(omegas):
 def custom(ndof, source, params=()):
     """A separable system H = |p|^2/2 + V(q) given as HIP device code
     defining chx_potential, chx_force (grad V) and chx_hess (Hess V, upper
-    triangle packed row by row); ndof 1..3, up to 16 params (see chx.h)."""
+    triangle packed row by row); ndof 1..8, up to 16 params (see chx.h)."""
     return System(SYS_CUSTOM, int(ndof), tuple(float(v) for v in params), str(source))
 
 
@@ -209,7 +209,7 @@ def custom_general(ndof, source, params=()):
     template <class T> __device__ void chx_field(const T *x, T *f, const double *prm)
     (Hamilton's equations over a generic number type) and
     __device__ double chx_hamiltonian(const double *x, const double *prm);
-    ndof 1..3, up to 16 params; "dop853" or "dop853_adaptive" only."""
+    ndof 1..8, up to 16 params; "dop853" or "dop853_adaptive" only."""
     return System(SYS_CUSTOM_GENERAL, int(ndof), tuple(float(v) for v in params), str(source))
 
 

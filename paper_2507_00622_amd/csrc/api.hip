@@ -77,7 +77,8 @@ chx_status check_system(const chx_system *sys) {
     break;
   case CHX_SYS_CUSTOM:
   case CHX_SYS_CUSTOM_GENERAL:
-    if (N < 1 || N > 3) return fail(CHX_ERR_INVALID_ARG, "a custom system needs ndof 1..3 (got %d)", N);
+    if (N < 1 || N > CHX_CUSTOM_MAX_NDOF)
+      return fail(CHX_ERR_INVALID_ARG, "a custom system needs ndof 1..%d (got %d)", CHX_CUSTOM_MAX_NDOF, N);
     if (!sys->source || !sys->source[0]) return fail(CHX_ERR_INVALID_ARG, "a custom system needs its source");
     if (sys->nparams < 0 || sys->nparams > 16)
       return fail(CHX_ERR_INVALID_ARG, "a custom system takes 0..16 params (got %d)", sys->nparams);
@@ -170,6 +171,12 @@ chx_status make_plan(const chx_system *sys, const chx_options *opt, Plan *p) {
                       : lane_supported(sk, N, p->M);
   if (!ok)
     return fail(CHX_ERR_UNSUPPORTED, "system kind %d with ndof %d and %d deviation vectors is not supported", sk, N, p->M);
+  if ((sk == CHX_SYS_CUSTOM || sk == CHX_SYS_CUSTOM_GENERAL) && o.integrator != CHX_INT_YOSHIDA4) {
+    const size_t lds = custom_rk_lds_per_lane(sk == CHX_SYS_CUSTOM_GENERAL,
+                                              o.integrator == CHX_INT_DOP853_ADAPTIVE, N, p->M);
+    if (lds * 64 > 65536)
+      return fail(CHX_ERR_UNSUPPORTED, "a custom system with ndof %d and %d deviation vectors needs %zu B of LDS per orbit for the DOP853 stages; at most 1024 B fit", N, p->M, lds);
+  }
   return CHX_OK;
 }
 

@@ -67,6 +67,8 @@ struct StepArgs {
 // Launchers of the integration kernels (one per source file).
 hipError_t launch_lane(int sys, int ndof, int M, const StepArgs &a, int block,
                        hipStream_t s);
+// largest ndof of a system compiled at run time from the caller's source
+#define CHX_CUSTOM_MAX_NDOF 8
 bool lane_supported(int sys, int ndof, int M);
 hipError_t launch_lane_rk(int sys, int ndof, int M, bool adaptive, const StepArgs &a,
                           int block, hipStream_t s);

@@ -304,6 +304,16 @@ chx_status custom_prepare(const std::string &src, int ndof, bool general, const 
   return CHX_OK;
 }
 
+// LDS bytes per lane of the DOP853 kernels for a custom system: per stage
+// the positions (separable) or the stage state (general; none when one or
+// two vectors go through the stages with the state), and for the adaptive
+// solver the vectors' step-start values.
+size_t custom_rk_lds_per_lane(bool general, bool adaptive, int N, int M) {
+  if (M == 0) return 0;
+  const int stage = general ? ((M <= 2) ? 0 : 2 * N) : N;
+  return sizeof(double) * (size_t)(12 * stage + (adaptive ? M * 2 * N : 0));
+}
+
 namespace {
 // the program's functions on the current device (loaded there at first use)
 hipError_t load(Program *pg, Loaded **out) {
@@ -353,13 +363,11 @@ hipError_t custom_launch(void *handle, bool general, const Plan &pl, const StepA
   }
   size_t lds = 0;
   if (pl.o.integrator != CHX_INT_YOSHIDA4 && pl.M > 0) {
-    const bool adaptive = pl.o.integrator == CHX_INT_DOP853_ADAPTIVE;
-    // per stage: the positions (separable); the stage state (general),
-    // none when one or two vectors go through the stages with the state
-    const int stage = general ? ((pl.M <= 2) ? 0 : 2 * pl.N) : pl.N;
-    const size_t per = sizeof(double) * (12 * stage + (adaptive ? pl.M * 2 * pl.N : 0));
+    const size_t per = custom_rk_lds_per_lane(general, pl.o.integrator == CHX_INT_DOP853_ADAPTIVE,
+                                              pl.N, pl.M);
     while (block > 64 && per * (size_t)block > 65536) block /= 2;
     lds = per * (size_t)block;
+    if (lds > 65536) return hipErrorInvalidValue;  // rejected by the plan already
   }
   StepArgs arg = a;
   void *params[] = {&arg};

@@ -52,6 +52,7 @@ chx_status advance(chx_ensemble *e, int64_t s_end);
 chx_status results(chx_ensemble *e, chx_result *res);
 chx_status subset(chx_ensemble *e, const uint8_t *keep, chx_ensemble **out, int64_t **orbit_out);
 // custom.hip: user systems compiled at run time
+size_t custom_rk_lds_per_lane(bool general, bool adaptive, int N, int M);
 chx_status custom_prepare(const std::string &src, int ndof, bool general, const Plan &pl,
                           void **handle);
 hipError_t custom_init(void *handle, const chx::StepArgs &a, hipStream_t s);

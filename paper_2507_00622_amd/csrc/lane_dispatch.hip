@@ -34,7 +34,7 @@ bool lane_supported(int sys, int ndof, int M) {
   case SYS_HARMONIC: return ndof >= 1 && ndof <= 3;
   case SYS_DP: return ndof == 2;  // DOP853 kernels only
   case CHX_SYS_CUSTOM:
-  case CHX_SYS_CUSTOM_GENERAL: return ndof >= 1 && ndof <= 3;  // compiled at run time
+  case CHX_SYS_CUSTOM_GENERAL: return ndof >= 1 && ndof <= CHX_CUSTOM_MAX_NDOF;  // compiled at run time
   }
   return false;
 }

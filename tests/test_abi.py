@@ -182,8 +182,8 @@ def test_custom_system_validation():
     # checked, and the source compiled, before any device work
     with pytest.raises(chx.ChxError, match="needs its source"):
         chx.sali(chx.System(chx.SYS_CUSTOM, 2), hh_x0(), 0.01, 1.0, 1)
-    with pytest.raises(chx.ChxError, match="ndof 1..3"):
-        chx.sali(P.custom(4, CUSTOM_HH), np.zeros((2, 8)), 0.01, 1.0, 1)
+    with pytest.raises(chx.ChxError, match="ndof 1..8"):
+        chx.sali(P.custom(9, CUSTOM_HH), np.zeros((2, 18)), 0.01, 1.0, 1)
     with pytest.raises(chx.ChxError, match="0..16 params"):
         chx.sali(P.custom(2, CUSTOM_HH, params=[0.0] * 17), hh_x0(), 0.01, 1.0, 1)
     bad = CUSTOM_HH.replace("H[2] = 1.0 - 2.0 * q[1];", "H[2] = 1.0 - 2.0 * q[1]")

@@ -252,3 +252,102 @@ def test_custom_general_double_pendulum(env, integ, nvec):
         sel = (g["steps"][:, 0] == o["steps_accepted"]) & (g["steps"][:, 1] == o["steps_rejected"])
         assert sel.sum() >= 0.99 * len(x0)
     compare(g, o, sel, 1e-3 if integ == "dop853_adaptive" else 1e-9, f"dp general {nvec}")
+
+
+# V = sum q_i^4/4 + eps sum_{i<j} q_i^2 q_j^2 for any ndof (eps = prm[0])
+QUARTIC_N = r"""
+#define NQ CHX_CUSTOM_NDOF
+__device__ double chx_potential(const double *q, const double *prm) {
+  double v = 0.0;
+  for (int i = 0; i < NQ; ++i) {
+    v += 0.25 * q[i] * q[i] * q[i] * q[i];
+    for (int j = i + 1; j < NQ; ++j) v += prm[0] * q[i] * q[i] * q[j] * q[j];
+  }
+  return v;
+}
+__device__ void chx_force(const double *q, double *F, const double *prm) {
+  for (int i = 0; i < NQ; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < NQ; ++j) if (j != i) s += q[j] * q[j];
+    F[i] = q[i] * q[i] * q[i] + 2.0 * prm[0] * q[i] * s;
+  }
+}
+__device__ void chx_hess(const double *q, double *H, const double *prm) {
+  int k = 0;
+  for (int i = 0; i < NQ; ++i)
+    for (int j = i; j < NQ; ++j) {
+      if (i == j) {
+        double s = 0.0;
+        for (int l = 0; l < NQ; ++l) if (l != i) s += q[l] * q[l];
+        H[k++] = 3.0 * q[i] * q[i] + 2.0 * prm[0] * s;
+      } else {
+        H[k++] = 4.0 * prm[0] * q[i] * q[j];
+      }
+    }
+}
+"""
+
+
+@pytest.mark.parametrize("integ", ["yoshida4", "dop853", "dop853_adaptive"])
+def test_custom_quartic_five_dof(env, integ):
+    torch, P, O = env
+    say(f"case: custom quartic N=5 (eps=0.1), {integ}, T=20")
+    so = O.quartic(5, 0.1)
+    x0 = O.quartic_ic(so, S.quartic_draws(76, 120, 5))
+    w0 = S.deviation_vectors(77, len(x0), 2, 10)
+    extra = dict(rtol=1e-10, atol=1e-10) if integ == "dop853_adaptive" else {}
+    if integ == "yoshida4":
+        ind, more = ALL, dict(gali_kmax=2, n_lyap=4)
+    else:
+        ind, more = O.IND_SALI | O.IND_LD | O.IND_ENERGY, {}
+    kw = dict(dt=0.05 if integ == "dop853_adaptive" else 0.01, T=20.0, indicators=ind,
+              **more, **extra)
+    g = run_gpu(env, P.custom(5, QUARTIC_N, params=[0.1]), x0, None, w0, integrator=integ, **kw)
+    o = O.integrate(so, x0, oracle_run(O, integ, **kw), w0=w0, threads=8)
+    assert np.array_equal(g["status"], o["status"])
+    sel = o["status"] == 0
+    if integ == "dop853_adaptive":
+        same = sel & (g["steps"][:, 0] == o["steps_accepted"]) & (
+            g["steps"][:, 1] == o["steps_rejected"])
+        assert same.sum() >= 0.99 * sel.sum()
+        sel = same
+    compare(g, o, sel, 1e-3 if integ == "dop853_adaptive" else 1e-9, f"quartic5 {integ}")
+
+
+# four uncoupled oscillators written as a general field over T
+HARMONIC4_GENERAL = r"""
+template <class T>
+__device__ void chx_field(const T *x, T *f, const double *prm) {
+  for (int i = 0; i < 4; ++i) {
+    f[i] = x[4 + i];
+    f[4 + i] = -(prm[i] * prm[i]) * x[i];
+  }
+}
+__device__ double chx_hamiltonian(const double *x, const double *prm) {
+  double h = 0.0;
+  for (int i = 0; i < 4; ++i) h += 0.5 * (x[4 + i] * x[4 + i] + prm[i] * prm[i] * x[i] * x[i]);
+  return h;
+}
+"""
+
+
+def test_custom_general_four_dof_and_lds_limit(env):
+    torch, P, O = env
+    om = [0.7, 1.0, 1.3, 2.1]
+    say("case: general harmonic N=4, dop853, SALI + LD + energy, T=10")
+    so = O.harmonic(om)
+    rng = np.random.default_rng(78)
+    x0 = rng.uniform(-1.0, 1.0, size=(96, 8))
+    w0 = S.deviation_vectors(79, len(x0), 2, 8)
+    kw = dict(dt=0.01, T=10.0, indicators=O.IND_SALI | O.IND_LD | O.IND_ENERGY)
+    sg = P.custom_general(4, HARMONIC4_GENERAL, params=om)
+    g = run_gpu(env, sg, x0, None, w0, integrator="dop853", **kw)
+    o = O.integrate(so, x0, oracle_run(O, "dop853", **kw), w0=w0, threads=8)
+    assert np.array_equal(g["status"], o["status"])
+    compare(g, o, np.ones(len(x0), bool), 1e-9, "harmonic4 general")
+    # eight vectors with stage states of 2N = 8 values need 8 (12*8 + 8*8) = 1280 B of
+    # LDS per orbit on the adaptive solver: refused before any device work
+    say("case: general harmonic N=4, adaptive, 8 vectors: refused (LDS per orbit)")
+    with pytest.raises(P.ChxError, match="LDS"):
+        run_gpu(env, sg, x0, None, None, integrator="dop853_adaptive", dt=0.1, T=1.0,
+                indicators=O.IND_LYAP | O.IND_SALI, n_lyap=6, rtol=1e-9, atol=1e-9)
