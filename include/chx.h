@@ -273,8 +273,11 @@ chx_status chx_ld(const chx_system *sys, const double *x0, int64_t n, double dt,
  *   L(x) = M+(x) + M-(x): the M-function of chx_ld over [0, T] plus the
  *     same over [-T, 0] (two_sided; M+ alone otherwise).  M- is computed as
  *     M+ of the momentum-reversed state (q, -p): every built-in Hamiltonian
- *     is even in the momenta, so the backward orbit is the reflection of
- *     that forward orbit and |dx/dt| has the same components;
+ *     and every separable user system is even in the momenta, so the
+ *     backward orbit is the reflection of that forward orbit and |dx/dt|
+ *     has the same components; a general user system
+ *     (CHX_SYS_CUSTOM_GENERAL) may not be, and two_sided is refused for it
+ *     with CHX_ERR_UNSUPPORTED;
  *   neighbours y_i^(+/-) = x +/- sigma e_c for each coordinate c of the 2N
  *     phase-space coordinates whose bit is set in dirs (n of them);
  *   D = (1/2n) sum_i (|L(x) - L(y_i^+)| + |L(x) - L(y_i^-)|) / L(x)

@@ -21,8 +21,17 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=
          "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
 
 
-def _compile(src):
+def _headers_mtime():
+    hs = glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(ROOT, "include", "*.h"))
+    return max(os.path.getmtime(h) for h in hs)
+
+
+def _compile(src, incremental=False):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if incremental and os.path.exists(obj):
+        newest = max(os.path.getmtime(src), _headers_mtime())
+        if os.path.getmtime(obj) >= newest:
+            return obj
     cmd = ["hipcc", *FLAGS, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
@@ -31,13 +40,15 @@ def _compile(src):
     return obj
 
 
-def build(jobs=None):
-    """Compile every csrc/*.hip and link libchx.so; returns the library path."""
+def build(jobs=None, incremental=False):
+    """Compile every csrc/*.hip and link libchx.so; returns the library path.
+    With incremental, an object newer than its source and every header is
+    kept (a developer's shortcut; the default rebuilds everything)."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     jobs = jobs or min(len(srcs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda f: _compile(f, incremental), srcs))
     tmp = LIB + ".tmp"
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lhiprtc"]
     subprocess.run(cmd, check=True)
@@ -46,4 +57,5 @@ def build(jobs=None):
 
 
 if __name__ == "__main__":
-    print(build())
+    import sys
+    print(build(incremental="--incremental" in sys.argv))

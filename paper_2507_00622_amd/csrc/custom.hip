@@ -6,7 +6,9 @@
 // system runs the same Yoshida-4 (separable only), DOP853 and adaptive
 // DOP8(5) kernels, checkpoints and indicators as the built-in ones.  The
 // paper's package integrates any Hamiltonian system given by its user; this
-// is that entry, for N <= 3.
+// is that entry, for N <= CHX_CUSTOM_MAX_NDOF (8).  The DOP853 kernels keep
+// their per-stage records in LDS: plans needing more than 1 KB per orbit are
+// refused before any device work.
 //
 // The kernel headers are read from the csrc/ directory beside libchx.so
 // (and include/chx.h from ../include), so the run-time compilation uses the

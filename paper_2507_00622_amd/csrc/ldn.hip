@@ -165,6 +165,11 @@ extern "C" chx_status chx_ld_indicators(const chx_system *sys, const double *x0,
     return fail(CHX_ERR_INVALID_ARG, "dirs has bits beyond the 2N = %d coordinates", D);
   if (!(lo->sigma > 0.0) || !isfinite(lo->sigma))
     return fail(CHX_ERR_INVALID_ARG, "sigma must be finite and > 0");
+  // M- is taken as M+ of the momentum-reversed state, which is the backward
+  // integral only when H is even in the momenta: true of every built-in
+  // system and of separable user systems (p^2/2 + V), not of a general one.
+  if (lo->two_sided && sys->kind == CHX_SYS_CUSTOM_GENERAL)
+    return fail(CHX_ERR_UNSUPPORTED, "two-sided LD indicators need H even in the momenta: not available for a general custom system (set two_sided = 0)");
   chx_options o2 = *opt;
   o2.indicators = CHX_IND_LD;
   Plan pl;

@@ -201,6 +201,12 @@ def test_custom_system_validation():
     with pytest.raises(chx.ChxError) as e:
         chx.sali(P.custom_general(2, "/* field */"), hh_x0(), 0.01, 1.0, 1)
     assert e.value.status == chx.ERR_UNSUPPORTED and "not separable" in str(e.value)
+    # two-sided LD indicators take M- from the momentum-reversed orbit, which
+    # needs H even in p: refused for a general system, before any device work
+    with pytest.raises(chx.ChxError) as e:
+        chx.ld_indicators(P.custom_general(2, "/* field */"), hh_x0(), 1e-3, dt=0.01, T=1.0,
+                          integrator="dop853", two_sided=True)
+    assert e.value.status == chx.ERR_UNSUPPORTED and "even in the momenta" in str(e.value)
 
 
 def test_label_needs_sali():
