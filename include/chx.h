@@ -236,6 +236,13 @@ typedef struct {
   double *ln_growth;  /* [n][m_s] sum of ln |w_v| over renormalisations */
   int64_t *steps;     /* [n][2] accepted and rejected steps of the adaptive
                          solver (zeros for the fixed-step integrators) */
+  double *step_err;   /* [n][2] the adaptive solver's error estimate of its
+                         accepted steps (Functionalities section: the error of
+                         each integration step): the largest and the last.
+                         The estimate is the scaled DOP853 one the step-size
+                         control compares with 1, so both are <= 1; 0 before
+                         the first accepted step and for the fixed-step
+                         integrators; NaN for masked orbits */
 } chx_result;
 
 /* Whole-ensemble integration (Functionalities section: the solvers with

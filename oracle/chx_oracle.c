@@ -627,6 +627,8 @@ enum {
   ST_REJ,        /* adaptive: the last attempt was rejected (0 / 1)      */
   ST_NACC,       /* adaptive: accepted steps                             */
   ST_NREJ,       /* adaptive: rejected steps                             */
+  ST_ERR_MAX,    /* adaptive: largest error estimate of an accepted step */
+  ST_ERR_LAST,   /* adaptive: error estimate of the last accepted step   */
   ST_NSCAL
 };
 
@@ -920,6 +922,8 @@ int ora_advance_adaptive(int kind, int N, const double *pr, double *state, int64
           v.sc[ST_REJ] = 0.0;
           v.sc[ST_H] = hnew;
           v.sc[ST_NACC] += 1.0;
+          if (err > v.sc[ST_ERR_MAX]) v.sc[ST_ERR_MAX] = err;
+          v.sc[ST_ERR_LAST] = err;
           for (int64_t c = 0; c < ny; ++c) y[c] = ynew[c];
           t = last ? tb : t + h;
         } else {
@@ -959,6 +963,15 @@ void ora_step_counts(int N, const double *state, int64_t n, int m_s, int n_l,
   for (int64_t o = 0; o < n; ++o) {
     accepted[o] = (int64_t)state[o * L + ST_NACC];
     rejected[o] = (int64_t)state[o * L + ST_NREJ];
+  }
+}
+
+void ora_step_errors(int N, const double *state, int64_t n, int m_s, int n_l,
+                     double *err_max, double *err_last) {
+  int64_t L = ora_state_len(N, m_s, n_l);
+  for (int64_t o = 0; o < n; ++o) {
+    err_max[o] = state[o * L + ST_ERR_MAX];
+    err_last[o] = state[o * L + ST_ERR_LAST];
   }
 }
 

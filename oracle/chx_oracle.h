@@ -140,6 +140,11 @@ int ora_advance_adaptive(int kind, int ndof, const double *params, double *state
 /* Accepted and rejected step counts of the adaptive driver. */
 void ora_step_counts(int ndof, const double *state, int64_t n, int m_s, int n_l,
                      int64_t *accepted, int64_t *rejected);
+/* The adaptive driver's error estimate (the scaled DOP853 estimate its
+ * controller compares with 1) of the accepted steps: the largest and the
+ * last, per orbit (0 before the first accepted step). */
+void ora_step_errors(int ndof, const double *state, int64_t n, int m_s, int n_l,
+                     double *err_max, double *err_last);
 /* Outputs (any may be NULL): x_final[n][2N], t_end[n], status[n], label[n],
  * sali_final[n], sali_min[n], t_chaos[n], gali[n][kmax-1], lyap[n][n_l],
  * ld[n], energy_err[n], ln_growth[n][m_s]. */

@@ -72,6 +72,7 @@ def lib():
         L.ora_advance_adaptive.restype = i
         L.ora_advance_adaptive.argtypes = L.ora_advance.argtypes + [d, d]
         L.ora_step_counts.argtypes = [i, P, i64, i, i, P, P]
+        L.ora_step_errors.argtypes = [i, P, i64, i, i, P, P]
         L.ora_dop853_step.argtypes = [i, i, P, d, P, P, i, i, d, P]
         L.ora_finalize.restype = i
         L.ora_finalize.argtypes = [i, P, i64, i, i, u32, i, d] + [P] * 12
@@ -324,6 +325,15 @@ class State:
                               self.run.n_lyap, _p(acc), _p(rej))
         return acc, rej
 
+    def step_errors(self):
+        """Largest and last error estimate of the accepted steps per orbit
+        (adaptive driver), as [n][2]."""
+        emax = np.zeros(self.n)
+        elast = np.zeros(self.n)
+        lib().ora_step_errors(self.sys.ndof, _p(self.buf), self.n, self.run.m_s,
+                              self.run.n_lyap, _p(emax), _p(elast))
+        return np.stack([emax, elast], axis=1)
+
     def finalize(self):
         run, sys, n, N2 = self.run, self.sys, self.n, 2 * self.sys.ndof
         o = dict(
@@ -360,6 +370,7 @@ def integrate(sys, x0, run, w0=None, mask=None, threads=1):
     out = st.finalize()
     if run.integrator == INT_DOP853_ADAPTIVE:
         out["steps_accepted"], out["steps_rejected"] = st.step_counts()
+        out["step_err"] = st.step_errors()
     return out
 
 

@@ -64,7 +64,7 @@ class _Options(C.Structure):
 
 
 RESULT_FIELDS = ["x_final", "t_end", "status", "label", "sali_final", "sali_min", "t_chaos",
-                 "gali", "lyap", "ld", "energy_err", "ln_growth", "steps"]
+                 "gali", "lyap", "ld", "energy_err", "ln_growth", "steps", "step_err"]
 
 
 class _Result(C.Structure):
@@ -302,7 +302,7 @@ def _alloc_results(arr, sys, o, n, want):
             "t_chaos": ((n,), np.float64), "gali": ((n, max(kmax - 1, 0)), np.float64),
             "lyap": ((n, n_l), np.float64), "ld": ((n,), np.float64),
             "energy_err": ((n,), np.float64), "ln_growth": ((n, m_s), np.float64),
-            "steps": ((n, 2), np.int64)}
+            "steps": ((n, 2), np.int64), "step_err": ((n, 2), np.float64)}
     ind = o.indicators
     avail = {"x_final", "t_end", "status"}
     if ind & IND_SALI:
@@ -318,7 +318,7 @@ def _alloc_results(arr, sys, o, n, want):
     if m_s:
         avail.add("ln_growth")
     if o.integrator == INT_DOP853_ADAPTIVE:
-        avail.add("steps")
+        avail |= {"steps", "step_err"}
     want = avail if want is None else (set(want) & avail)
     res = _Result()
     out = {}

@@ -415,7 +415,8 @@ chx_status results(chx_ensemble *e, chx_result *res) {
             {r.ld, (void **)&d.ld, sizeof(double) * n},
             {r.energy_err, (void **)&d.energy_err, sizeof(double) * n},
             {r.ln_growth, (void **)&d.ln_growth, sizeof(double) * n * pl.m_s},
-            {r.steps, (void **)&d.steps, sizeof(int64_t) * n * 2}};
+            {r.steps, (void **)&d.steps, sizeof(int64_t) * n * 2},
+            {r.step_err, (void **)&d.step_err, sizeof(double) * n * 2}};
     for (auto &o : outs) {
       *o.dev = nullptr;
       if (o.host && o.bytes) {

@@ -33,6 +33,8 @@ enum Sc {
   SC_REJ,        // adaptive: 1 if the last attempt was rejected
   SC_NACC,       // adaptive: accepted steps
   SC_NREJ,       // adaptive: rejected steps
+  SC_ERR_MAX,    // adaptive: largest error estimate of an accepted step
+  SC_ERR_LAST,   // adaptive: error estimate of the last accepted step
   NSC
 };
 

@@ -173,6 +173,7 @@ __global__ void __launch_bounds__(256) fput_crow_rka_kernel(const StepArgs a) {
   if (!(h > 0.0)) h = a.dt;  // the first step
   bool rej = a.sc[SC_REJ * P + o] != 0.0;
   double nacc = a.sc[SC_NACC * P + o], nrej = a.sc[SC_NREJ * P + o];
+  double emax = a.sc[SC_ERR_MAX * P + o], elast = a.sc[SC_ERR_LAST * P + o];
   const bool do_ld = (a.ind & CHX_IND_LD) != 0;
   int64_t s = a.s_begin;
   const int64_t K = a.K;
@@ -211,6 +212,8 @@ __global__ void __launch_bounds__(256) fput_crow_rka_kernel(const StepArgs a) {
         rej = false;
         h = hnew;
         nacc += 1.0;
+        emax = fmax(emax, err);
+        elast = err;
         r.q = qn;
         r.p = pn;
 #pragma unroll
@@ -239,6 +242,8 @@ __global__ void __launch_bounds__(256) fput_crow_rka_kernel(const StepArgs a) {
     a.sc[SC_REJ * P + o] = rej ? 1.0 : 0.0;
     a.sc[SC_NACC * P + o] = nacc;
     a.sc[SC_NREJ * P + o] = nrej;
+    a.sc[SC_ERR_MAX * P + o] = emax;
+    a.sc[SC_ERR_LAST * P + o] = elast;
   }
 }
 

@@ -370,6 +370,7 @@ __global__ void __launch_bounds__(256) lane_rka_kernel(const StepArgs a) {
   if (!(h > 0.0)) h = a.dt;  // the first step
   bool rej = a.sc[SC_REJ * P + i] != 0.0;
   double nacc = a.sc[SC_NACC * P + i], nrej = a.sc[SC_NREJ * P + i];
+  double emax = a.sc[SC_ERR_MAX * P + i], elast = a.sc[SC_ERR_LAST * P + i];
   const int stride = blockDim.x;
   double *qs = lane_rk_lds + threadIdx.x;
   double *wn = lane_rk_lds + (size_t)12 * RKOrbit<S, M, GP>::LDS_STAGE * stride + threadIdx.x;
@@ -424,6 +425,8 @@ __global__ void __launch_bounds__(256) lane_rka_kernel(const StepArgs a) {
       rej = false;
       h = hnew;
       nacc += 1.0;
+      emax = fmax(emax, err);
+      elast = err;
 #pragma unroll
       for (int c = 0; c < D; ++c) o.x[c] = xn[c];
 #pragma unroll
@@ -445,6 +448,8 @@ __global__ void __launch_bounds__(256) lane_rka_kernel(const StepArgs a) {
   a.sc[SC_REJ * P + ob] = rej ? 1.0 : 0.0;
   a.sc[SC_NACC * P + ob] = nacc;
   a.sc[SC_NREJ * P + ob] = nrej;
+  a.sc[SC_ERR_MAX * P + ob] = emax;
+  a.sc[SC_ERR_LAST * P + ob] = elast;
 }
 
 // Launch the fixed-step (ADAPT = false) or adaptive (true) kernel with M

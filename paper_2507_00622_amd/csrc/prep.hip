@@ -146,6 +146,8 @@ __global__ void init_kernel(StepArgs a, InitArgs ia) {
   a.sc[SC_REJ * P + i] = 0.0;
   a.sc[SC_NACC * P + i] = 0.0;
   a.sc[SC_NREJ * P + i] = 0.0;
+  a.sc[SC_ERR_MAX * P + i] = 0.0;
+  a.sc[SC_ERR_LAST * P + i] = 0.0;
   a.st[i] = finite ? CHX_ORBIT_OK : CHX_ORBIT_NONFINITE;
 }
 
@@ -179,6 +181,10 @@ __global__ void finalize_kernel(StepArgs a, OutArgs o, int N, double *gscratch) 
   if (r.steps) {
     r.steps[2 * j] = (int64_t)a.sc[SC_NACC * P + i];
     r.steps[2 * j + 1] = (int64_t)a.sc[SC_NREJ * P + i];
+  }
+  if (r.step_err) {
+    r.step_err[2 * j] = a.sc[SC_ERR_MAX * P + i];
+    r.step_err[2 * j + 1] = a.sc[SC_ERR_LAST * P + i];
   }
   const double LN2 = 0.69314718055994530942;
   if (r.ln_growth)
@@ -243,6 +249,7 @@ __global__ void masked_fill_kernel(const double *x0, const uint8_t *mask, int64_
   if (r.ld) r.ld[j] = NAN;
   if (r.energy_err) r.energy_err[j] = NAN;
   if (r.steps) r.steps[2 * j] = r.steps[2 * j + 1] = 0;
+  if (r.step_err) r.step_err[2 * j] = r.step_err[2 * j + 1] = NAN;
   if (r.ln_growth)
     for (int v = 0; v < m_s; ++v) r.ln_growth[j * m_s + v] = NAN;
   if (r.lyap)

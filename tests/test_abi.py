@@ -33,7 +33,7 @@ def test_struct_layouts_match_header():
     L = chx.lib()
     assert L.chx_struct_size(0) == C.sizeof(chx._System) == 32
     assert L.chx_struct_size(1) == C.sizeof(chx._Options) == 120
-    assert L.chx_struct_size(2) == C.sizeof(chx._Result) == 13 * 8
+    assert L.chx_struct_size(2) == C.sizeof(chx._Result) == 14 * 8
     assert L.chx_struct_size(3) == C.sizeof(chx._BatchItem) == 72
     assert L.chx_struct_size(4) == C.sizeof(chx._BatchStats)
     assert L.chx_struct_size(5) == C.sizeof(chx._GateTrainCfg) == 40

@@ -135,6 +135,13 @@ def test_fput_dop853_adaptive(env, N):
         "rejected", g["steps"][:, 1].sum())
     assert same.sum() >= 0.99 * n
     compare(g, o, same, E, 1e-3, "adaptive")
+    # the largest accepted step error (the last one of a step shortened to
+    # end on a checkpoint sits near the rounding floor and is not compared)
+    se_rel = np.max(np.abs(g["step_err"][same, 0] / o["step_err"][same, 0] - 1))
+    say("  largest step_err rel err", se_rel)
+    assert se_rel < 3e-4
+    e = g["step_err"]
+    assert np.all(e[:, 1] <= e[:, 0]) and np.all(e[:, 0] <= 1.0) and np.all(e[:, 1] > 0)
 
 
 def test_fput_dop853_edges_resume_blocks(env):

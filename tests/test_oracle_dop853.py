@@ -343,3 +343,75 @@ def test_adaptive_gives_up_on_an_impossible_tolerance(O):
     o = O.integrate(s, np.array([[1.0, 0.0]]), adaptive_run(O, 1.0, 1e-40, dt=0.1, K=10))
     assert o["status"][0] == O.ST_STEPFAIL and o["label"][0] == 3
     assert np.isnan(o["energy_err"][0])
+
+
+# --- the adaptive driver's per-step error (Functionalities section: the
+# error of each integration step of the adaptive solvers) ---------------------
+
+def hh_ext_rhs(t, y):
+    """Henon-Heiles with one deviation vector appended (variational
+    equations): d(dq)/dt = dp, d(dp)/dt = -Hess V(q) dq."""
+    x, yy, px, py, dx, dy, dpx, dpy = y
+    hxx, hxy, hyy = 1 + 2 * yy, 2 * x, 1 - 2 * yy
+    return np.array([px, py, -x - 2 * x * yy, -yy - x * x + yy * yy,
+                     dpx, dpy, -(hxx * dx + hxy * dy), -(hxy * dx + hyy * dy)])
+
+
+def scipy_error_norm(fun, y0, h, tol):
+    """SciPy's DOP853 error norm of one attempted step of size h from y0
+    (its own stage evaluation and estimate, rtol = atol = tol), and the
+    relative rounding noise that two implementations may differ by: the
+    estimate is h sum_i e_i k_i / sk, a sum of stage derivatives of size
+    |k| that cancels to err sk / h, so summing in another order moves it by
+    about eps |h| max|k| / (err min sk) relative (times a small count)."""
+    from scipy.integrate._ivp import rk
+    s = rk.DOP853(fun, 0.0, np.array(y0, float), 1e3, rtol=tol, atol=tol, first_step=h)
+    y_new, _ = rk.rk_step(s.fun, 0.0, s.y, s.f, h, s.A, s.B, s.C, s.K)
+    scale = tol + np.maximum(np.abs(s.y), np.abs(y_new)) * tol
+    err = s._estimate_error_norm(s.K, h, scale)
+    noise = 16 * np.finfo(float).eps * abs(h) * np.max(np.abs(s.K)) / (err * np.min(scale))
+    return err, noise + 1e-12
+
+
+@pytest.mark.parametrize("x0,h,tol", [
+    ([0.0, 0.1, 0.45, 0.05], 0.2, 1e-10),
+    ([0.0, -0.3, 0.2, 0.1], 0.5, 1e-8),
+    ([0.0, -0.3, 0.2, 0.1], 0.3, 1e-9),
+])
+def test_step_error_equals_scipy_dop853_estimate(O, x0, h, tol):
+    # one checkpoint interval of one step: the driver's first attempt has
+    # size h, is accepted, and its estimate is both the largest and the last
+    s = O.henon_heiles()
+    o = O.integrate(s, np.array([x0]), adaptive_run(O, h, tol, dt=h, K=1))
+    ref, noise = scipy_error_norm(lambda t, y: np.array(hh_rhs(t, y)), x0, h, tol)
+    assert o["steps_accepted"][0] == 1 and o["steps_rejected"][0] == 0
+    assert o["step_err"][0, 0] == o["step_err"][0, 1]
+    assert abs(o["step_err"][0, 1] / ref - 1) < noise, (o["step_err"][0], ref, noise)
+    assert noise < 1e-3  # a dropped stage or a wrong weight moves it by O(1)
+    # the estimate is measured on the state and the deviation vectors: the
+    # Lyapunov set starts as e_1, so SciPy integrates the state with e_1
+    run = adaptive_run(O, h, tol, dt=h, K=1, ind=O.IND_LYAP, n_lyap=1)
+    st = O.State(s, run, np.array([x0]))
+    st.advance(1)
+    ref_v, noise_v = scipy_error_norm(hh_ext_rhs, list(x0) + [1.0, 0.0, 0.0, 0.0], h, tol)
+    assert abs(st.step_errors()[0, 1] / ref_v - 1) < noise_v, (st.step_errors()[0], ref_v)
+    assert abs(ref_v / ref - 1) > 10 * (noise + noise_v)  # the vector counts
+
+
+def test_step_error_bounds_and_resume(O):
+    # every accepted step has an estimate <= 1; the largest bounds the last;
+    # the estimates resume bitwise across launches like the rest of the state
+    s = O.henon_heiles()
+    x0 = np.array([[0.0, 0.1, 0.45, 0.05], [0.0, -0.3, 0.2, 0.1]])
+    run = adaptive_run(O, 30.0, 1e-9, dt=0.05, K=20)
+    full = O.integrate(s, x0, run)
+    e = full["step_err"]
+    assert np.all(e[:, 1] <= e[:, 0]) and np.all(e[:, 0] <= 1.0) and np.all(e[:, 1] > 0)
+    st = O.State(s, run, x0)
+    st.advance(200)
+    st.advance(600)
+    assert np.array_equal(st.step_errors(), e)
+    # a rejected first step is not an accepted step's estimate
+    o = O.integrate(O.harmonic([1.0]), np.array([[0.3, 0.8]]),
+                    adaptive_run(O, 4.0, 1e-10, dt=4.0, K=1))
+    assert o["steps_rejected"][0] >= 1 and o["step_err"][0, 0] <= 1.0
