@@ -21,18 +21,22 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=
          "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
 
 
-def _headers_mtime():
-    hs = glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(ROOT, "include", "*.h"))
-    return max(os.path.getmtime(h) for h in hs)
+def _up_to_date(obj, dep):
+    """True when obj is newer than every file its dependency list names."""
+    if not (os.path.exists(obj) and os.path.exists(dep)):
+        return False
+    text = open(dep).read().replace("\\\n", " ")
+    files = [f for f in text.split(":", 1)[1].split() if f]
+    t = os.path.getmtime(obj)
+    return all(os.path.exists(f) and os.path.getmtime(f) <= t for f in files)
 
 
 def _compile(src, incremental=False):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    if incremental and os.path.exists(obj):
-        newest = max(os.path.getmtime(src), _headers_mtime())
-        if os.path.getmtime(obj) >= newest:
-            return obj
-    cmd = ["hipcc", *FLAGS, "-c", src, "-o", obj]
+    dep = obj + ".d"
+    if incremental and _up_to_date(obj, dep):
+        return obj
+    cmd = ["hipcc", *FLAGS, "-MD", "-MF", dep, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:
