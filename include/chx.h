@@ -252,6 +252,28 @@ chx_status chx_integrate_ensemble(const chx_system *sys, const double *x0,
                                   const uint8_t *mask, int64_t n,
                                   const chx_options *opt, chx_result *res);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * call as chx_integrate_ensemble, with the same arguments, outputs and
+ * results, but it calls no hipMalloc, hipFree or other allocating routine.
+ * Its working buffers come from a library-owned device array of
+ * CHX_NOALLOC_MAX_BYTES that every GPU the library runs on holds until the
+ * process ends.  Restrictions: CHX_PTR_DEVICE is required (x0, mask,
+ * opt->w0 and every output are device pointers, read and written in place;
+ * opt->stream orders the work); built-in systems only (custom systems
+ * return CHX_ERR_UNSUPPORTED).  The workspace needed grows with n: about
+ * (2N(M + 1) + M + 15) doubles and (M + 1) ints per initial condition,
+ * with M = the deviation vectors (plus gali_kmax * 2N doubles when GALI is
+ * an output); a call that needs more than CHX_NOALLOC_MAX_BYTES returns
+ * CHX_ERR_INVALID_ARG before any device work, its message giving the
+ * figure.  Calls that overlap in time on one GPU share its array and race:
+ * serialise them.  The call synchronises the stream once (it reads the
+ * number of unmasked orbits). */
+#define CHX_NOALLOC_MAX_BYTES (64ull << 20)
+chx_status chx_integrate_ensemble_noalloc(const chx_system *sys, const double *x0,
+                                          const uint8_t *mask, int64_t n,
+                                          const chx_options *opt, chx_result *res);
+
 /* Host-pointer convenience calls (synchronous). */
 /* SALI (Functionalities section) with two seeded unit vectors, K = 10:
  * min SALI over checkpoints and the label (0 regular, 1 chaotic at 1e-8). */

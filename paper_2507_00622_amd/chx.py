@@ -36,7 +36,7 @@ EXPORTS = [
     "chx_last_error", "chx_version", "chx_struct_size", "chx_integrate_batched",
     "chx_ensemble_subset", "chx_gate_create", "chx_gate_destroy", "chx_gate_train",
     "chx_gate_grad", "chx_gate_infer", "chx_gate_get", "chx_gate_set", "chx_gate_features",
-    "chx_gate_classify", "chx_ld_indicators",
+    "chx_gate_classify", "chx_ld_indicators", "chx_integrate_ensemble_noalloc",
 ]
 GATE_NFEAT, GATE_NPARAM = 6, 74256
 
@@ -112,6 +112,7 @@ def lib():
         L.chx_options_default.argtypes = [O]
         L.chx_options_default.restype = None
         L.chx_integrate_ensemble.argtypes = [S, P, P, i64, O, R]
+        L.chx_integrate_ensemble_noalloc.argtypes = [S, P, P, i64, O, R]
         L.chx_ld_indicators.argtypes = [S, P, P, i64, O, C.POINTER(_LdnOptions),
                                         C.POINTER(_LdnResult)]
         L.chx_sali.argtypes = [S, P, i64, d, d, u64, P, P]
@@ -416,6 +417,28 @@ def integrate_ensemble(sys, x0, mask=None, w0=None, outputs=None, **opts):
     keep = (x0a, ma, w0a)  # noqa: F841 -- alive until the call returns
     cs = sys._c()
     _check(lib().chx_integrate_ensemble(C.byref(cs), px0, pm, n, C.byref(o), C.byref(res)))
+    return out
+
+
+def integrate_ensemble_noalloc(sys, x0, mask=None, w0=None, outputs=None, **opts):
+    """chx_integrate_ensemble_noalloc: chx_integrate_ensemble on device
+    tensors with the library's fixed workspace (no device allocation by the
+    library; the output tensors are allocated here, by the caller)."""
+    arr = _Arrays(x0)
+    if not arr.device:
+        raise TypeError("the allocation-free entry takes device (torch) tensors only")
+    o = make_options(**opts)
+    o.flags, o.stream = arr.flags, arr.stream
+    x0a, px0 = arr.inp(x0, np.float64)
+    n = int(x0a.shape[0])
+    ma, pm = arr.inp(mask, np.uint8)
+    w0a, pw = arr.inp(w0, np.float64)
+    o.w0 = pw
+    res, out = _alloc_results(arr, sys, o, n, outputs)
+    keep = (x0a, ma, w0a)  # noqa: F841 -- alive until the call returns
+    cs = sys._c()
+    _check(lib().chx_integrate_ensemble_noalloc(C.byref(cs), px0, pm, n, C.byref(o),
+                                                C.byref(res)))
     return out
 
 

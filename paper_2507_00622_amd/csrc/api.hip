@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "chx_internal.h"
@@ -189,6 +190,10 @@ hipError_t dalloc(T **p, size_t count, hipStream_t s) {
 
 void release(chx_ensemble *e) {
   if (!e) return;
+  if (e->in_arena) {  // every buffer belongs to the caller's workspace
+    delete e;
+    return;
+  }
   hipStream_t s = e->stream;
   if (e->x0) (void)hipFreeAsync(e->x0, s);
   if (e->mask) (void)hipFreeAsync(e->mask, s);
@@ -200,7 +205,7 @@ void release(chx_ensemble *e) {
 }
 
 chx_status create(const chx_system *sys, const double *x0, const uint8_t *mask, int64_t n,
-                  const chx_options *opt, chx_ensemble **out) {
+                  const chx_options *opt, chx_ensemble **out, Arena *arena) {
   if (!out) return fail(CHX_ERR_INVALID_ARG, "output handle pointer is NULL");
   *out = nullptr;
   chx_status st = check_system(sys);
@@ -213,6 +218,7 @@ chx_status create(const chx_system *sys, const double *x0, const uint8_t *mask, 
   const bool device = pl.o.flags & CHX_PTR_DEVICE;
   const hipStream_t s = device ? (hipStream_t)pl.o.stream : nullptr;
   if (!device && pl.o.stream) return fail(CHX_ERR_INVALID_ARG, "stream given without CHX_PTR_DEVICE");
+  if (arena && !device) return fail(CHX_ERR_INVALID_ARG, "a workspace needs device pointers");
 
   void *custom = nullptr;
   const bool is_custom = sys->kind == CHX_SYS_CUSTOM || sys->kind == CHX_SYS_CUSTOM_GENERAL;
@@ -236,33 +242,50 @@ chx_status create(const chx_system *sys, const double *x0, const uint8_t *mask, 
   e->stream = s;
   e->device = device;
   e->block = pl.o.block_size ? pl.o.block_size : 256;
+  e->in_arena = arena != nullptr;
   const int D = pl.D, M = pl.M;
   const hipMemcpyKind kin = device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   double *w0 = nullptr;
   int64_t *scratch = nullptr, *count = nullptr;
   hipError_t he = hipSuccess;
+  // buffers from the caller's workspace, else allocated on the stream
+  auto get = [&](auto **p, size_t cnt) -> hipError_t {
+    using T = std::remove_reference_t<decltype(**p)>;
+    if (!arena) return dalloc(p, cnt, s);
+    *p = arena->template take<T>(cnt);
+    return (cnt == 0 || *p) ? hipSuccess : hipErrorOutOfMemory;
+  };
   auto bail = [&](hipError_t err, const char *what) {
-    if (w0) (void)hipFreeAsync(w0, s);
-    if (scratch) (void)hipFreeAsync(scratch, s);
-    if (count) (void)hipFreeAsync(count, s);
+    if (!arena) {
+      if (w0) (void)hipFreeAsync(w0, s);
+      if (scratch) (void)hipFreeAsync(scratch, s);
+      if (count) (void)hipFreeAsync(count, s);
+    }
     release(e);
     return dev_fail(err, what);
   };
   if (n > 0) {
-    if ((he = dalloc(&e->x0, (size_t)n * D, s))) return bail(he, "allocate x0");
-    if ((he = hipMemcpyAsync(e->x0, x0, sizeof(double) * n * D, kin, s))) return bail(he, "copy x0");
-    if (mask) {
-      if ((he = dalloc(&e->mask, (size_t)n, s))) return bail(he, "allocate mask");
-      if ((he = hipMemcpyAsync(e->mask, mask, n, kin, s))) return bail(he, "copy mask");
+    if (arena) {
+      // device inputs are read in place for the duration of the call
+      e->x0 = const_cast<double *>(x0);
+      e->mask = const_cast<uint8_t *>(mask);
+      if (opt->w0 && pl.m_s > 0) w0 = const_cast<double *>(opt->w0);
+    } else {
+      if ((he = dalloc(&e->x0, (size_t)n * D, s))) return bail(he, "allocate x0");
+      if ((he = hipMemcpyAsync(e->x0, x0, sizeof(double) * n * D, kin, s))) return bail(he, "copy x0");
+      if (mask) {
+        if ((he = dalloc(&e->mask, (size_t)n, s))) return bail(he, "allocate mask");
+        if ((he = hipMemcpyAsync(e->mask, mask, n, kin, s))) return bail(he, "copy mask");
+      }
+      if (opt->w0 && pl.m_s > 0) {
+        if ((he = dalloc(&w0, (size_t)n * pl.m_s * D, s))) return bail(he, "allocate w0");
+        if ((he = hipMemcpyAsync(w0, opt->w0, sizeof(double) * n * pl.m_s * D, kin, s)))
+          return bail(he, "copy w0");
+      }
     }
-    if (opt->w0 && pl.m_s > 0) {
-      if ((he = dalloc(&w0, (size_t)n * pl.m_s * D, s))) return bail(he, "allocate w0");
-      if ((he = hipMemcpyAsync(w0, opt->w0, sizeof(double) * n * pl.m_s * D, kin, s)))
-        return bail(he, "copy w0");
-    }
-    if ((he = dalloc(&e->idx, (size_t)n, s))) return bail(he, "allocate index");
-    if ((he = dalloc(&scratch, (size_t)compact_scratch_len(n), s))) return bail(he, "allocate scratch");
-    if ((he = dalloc(&count, 1, s))) return bail(he, "allocate count");
+    if ((he = get(&e->idx, (size_t)n))) return bail(he, "allocate index");
+    if ((he = get(&scratch, (size_t)compact_scratch_len(n)))) return bail(he, "allocate scratch");
+    if ((he = get(&count, 1))) return bail(he, "allocate count");
     if ((he = launch_compact(e->mask, n, e->idx, count, scratch, s))) return bail(he, "compact mask");
     int64_t hc = 0;
     if ((he = hipMemcpyAsync(&hc, count, sizeof hc, hipMemcpyDeviceToHost, s))) return bail(he, "read count");
@@ -275,8 +298,8 @@ chx_status create(const chx_system *sys, const double *x0, const uint8_t *mask, 
   const int64_t P = e->pitch;
   const size_t nd = (size_t)P * (D + (size_t)M * D + M + NSC);
   const size_t ni = (size_t)P * (M + 1);
-  if ((he = dalloc(&e->state, nd, s))) return bail(he, "allocate state");
-  if ((he = dalloc(&e->istate, ni, s))) return bail(he, "allocate state");
+  if ((he = get(&e->state, nd))) return bail(he, "allocate state");
+  if ((he = get(&e->istate, ni))) return bail(he, "allocate state");
   StepArgs &a = e->args;
   a.x = e->state;
   a.w = a.x + (size_t)D * P;
@@ -321,9 +344,11 @@ chx_status create(const chx_system *sys, const double *x0, const uint8_t *mask, 
   spl = (spl / pl.K) * pl.K;
   if (spl < pl.K) spl = pl.K;
   e->steps_per_launch = spl;
-  if (w0) (void)hipFreeAsync(w0, s);
-  if (scratch) (void)hipFreeAsync(scratch, s);
-  if (count) (void)hipFreeAsync(count, s);
+  if (!arena) {
+    if (w0) (void)hipFreeAsync(w0, s);
+    if (scratch) (void)hipFreeAsync(scratch, s);
+    if (count) (void)hipFreeAsync(count, s);
+  }
   if (!device) {
     if ((he = hipStreamSynchronize(s))) {
       release(e);
@@ -371,7 +396,7 @@ chx_status advance(chx_ensemble *e, int64_t s_end) {
   return CHX_OK;
 }
 
-chx_status results(chx_ensemble *e, chx_result *res) {
+chx_status results(chx_ensemble *e, chx_result *res, double *gali_scratch) {
   if (!e) return fail(CHX_ERR_INVALID_ARG, "ensemble is NULL");
   if (!res) return fail(CHX_ERR_INVALID_ARG, "result is NULL");
   if (e->s_done == 0) return fail(CHX_ERR_INVALID_ARG, "no steps integrated yet");
@@ -432,7 +457,7 @@ chx_status results(chx_ensemble *e, chx_result *res) {
   }
   oa.r = d;
   hipError_t he = launch_masked_fill(e->x0, e->mask, n, pl.N, oa, pl.m_s, pl.n_l, s);
-  if (he == hipSuccess) he = launch_finalize(e->args, oa, pl.N, s);
+  if (he == hipSuccess) he = launch_finalize(e->args, oa, pl.N, gali_scratch, s);
   if (!e->device) {
     for (auto &o : outs)
       if (*o.dev && he == hipSuccess) he = hipMemcpyAsync(o.host, *o.dev, o.bytes, hipMemcpyDeviceToHost, s);

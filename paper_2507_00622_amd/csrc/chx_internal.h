@@ -97,7 +97,9 @@ struct OutArgs {
   int sali;             // SALI requested
   double thr;
 };
-hipError_t launch_finalize(const StepArgs &a, const OutArgs &oa, int ndof,
+// scratch: a.n * gali_kmax * 2N doubles for the GALI QR when GALI is an
+// output, or null to allocate them for the call.
+hipError_t launch_finalize(const StepArgs &a, const OutArgs &oa, int ndof, double *scratch,
                            hipStream_t s);
 hipError_t launch_masked_fill(const double *x0, const uint8_t *mask, int64_t n_all,
                               int ndof, const OutArgs &oa, int m_s, int n_l,

@@ -15,6 +15,23 @@ struct Plan {
   int64_t n_total;
 };
 
+// A device workspace handed in by the caller of create() / results(): their
+// buffers are carved from it (256-byte aligned) instead of allocated, and
+// nothing is freed (the allocation-free entry point, noalloc.hip).
+struct Arena {
+  char *base = nullptr;
+  size_t cap = 0, used = 0;
+  template <class T>
+  T *take(size_t count) {
+    const size_t bytes = ((sizeof(T) * count + 255) / 256) * 256;
+    if (count == 0) return nullptr;
+    if (used + bytes > cap) return nullptr;
+    T *p = reinterpret_cast<T *>(base + used);
+    used += bytes;
+    return p;
+  }
+};
+
 chx_status fail(chx_status st, const char *fmt, ...);
 chx_status dev_fail(hipError_t e, const char *what);
 chx_status check_system(const chx_system *sys);
@@ -41,15 +58,20 @@ struct chx_ensemble {
   void *custom = nullptr;  // its compiled program (process cache)
   int block = 256;
   int64_t steps_per_launch = 0;
+  bool in_arena = false;   // buffers carved from a caller's workspace: not freed
 };
 
 namespace chx {
 namespace host {
 void release(chx_ensemble *e);
+// With an arena (device pointers only) x0, mask and w0 are used in place
+// and every other buffer comes from the arena.
 chx_status create(const chx_system *sys, const double *x0, const uint8_t *mask, int64_t n,
-                  const chx_options *opt, chx_ensemble **out);
+                  const chx_options *opt, chx_ensemble **out, Arena *arena = nullptr);
 chx_status advance(chx_ensemble *e, int64_t s_end);
-chx_status results(chx_ensemble *e, chx_result *res);
+// gali_scratch: n_active * gali_kmax * 2N doubles for the GALI QR, or null
+// to allocate it
+chx_status results(chx_ensemble *e, chx_result *res, double *gali_scratch = nullptr);
 chx_status subset(chx_ensemble *e, const uint8_t *keep, chx_ensemble **out, int64_t **orbit_out);
 // custom.hip: user systems compiled at run time
 size_t custom_rk_lds_per_lane(bool general, bool adaptive, int N, int M);

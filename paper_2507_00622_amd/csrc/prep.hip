@@ -493,19 +493,24 @@ hipError_t launch_init(const StepArgs &a, const InitArgs &ia, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const StepArgs &a, const OutArgs &oa, int ndof, hipStream_t s) {
+hipError_t launch_finalize(const StepArgs &a, const OutArgs &oa, int ndof, double *given,
+                           hipStream_t s) {
   if (a.n == 0) return hipSuccess;
   double *scratch = nullptr;
   hipError_t e;
   if (oa.r.gali && oa.gali_kmax >= 2) {
-    e = hipMallocAsync((void **)&scratch,
-                       sizeof(double) * (size_t)a.n * oa.gali_kmax * 2 * ndof, s);
-    if (e != hipSuccess) return e;
+    if (given) {
+      scratch = given;
+    } else {
+      e = hipMallocAsync((void **)&scratch,
+                         sizeof(double) * (size_t)a.n * oa.gali_kmax * 2 * ndof, s);
+      if (e != hipSuccess) return e;
+    }
   }
   hipLaunchKernelGGL(finalize_kernel, dim3(blocks_for(a.n)), dim3(TPB), 0, s, a, oa, ndof,
                      scratch);
   e = hipGetLastError();
-  if (scratch) {
+  if (scratch && scratch != given) {
     hipError_t e2 = hipFreeAsync(scratch, s);
     if (e == hipSuccess) e = e2;
   }

@@ -209,6 +209,26 @@ def test_custom_system_validation():
     assert e.value.status == chx.ERR_UNSUPPORTED and "even in the momenta" in str(e.value)
 
 
+def test_noalloc_refusals_before_device_work():
+    # host pointers, custom systems and oversized calls are refused by the
+    # allocation-free entry before it touches the device
+    L = chx.lib()
+    o = chx.make_options(dt=0.01, T=0.1, indicators=chx.IND_SALI)
+    x0 = hh_x0(3)
+    r = chx._Result()
+    cs = P.henon_heiles()._c()
+    st = L.chx_integrate_ensemble_noalloc(C.byref(cs), x0.ctypes.data_as(C.c_void_p), None, 3,
+                                          C.byref(o), C.byref(r))
+    assert st == chx.ERR_INVALID_ARG and b"device pointers" in L.chx_last_error()
+    o.flags = chx.PTR_DEVICE
+    fake = C.c_void_p(0x1000)  # never dereferenced: the size check comes first
+    st = L.chx_integrate_ensemble_noalloc(C.byref(cs), fake, None, 10**7, C.byref(o), C.byref(r))
+    assert st == chx.ERR_INVALID_ARG and b"workspace" in L.chx_last_error()
+    cg = P.custom(2, CUSTOM_HH)._c()
+    st = L.chx_integrate_ensemble_noalloc(C.byref(cg), fake, None, 3, C.byref(o), C.byref(r))
+    assert st == chx.ERR_UNSUPPORTED and b"built-in" in L.chx_last_error()
+
+
 def test_label_needs_sali():
     with pytest.raises(chx.ChxError, match="label"):
         o = chx.make_options(dt=0.01, T=1.0, indicators=chx.IND_LD)
