@@ -27,23 +27,73 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64 = 78.6e12  # MI355X FP64 vector peak, FLOP/s (FMA = 2)
 
-# Sources of the benchmarked integration kernel: the HBM traffic recorded in
-# profiles/ applies only while their hash is the one recorded beside it.
-KERNEL_SOURCES = ["paper_2507_00622_amd/csrc/lane_kernel.h",
-                  "paper_2507_00622_amd/csrc/systems.h",
-                  "paper_2507_00622_amd/csrc/device_math.h",
-                  "paper_2507_00622_amd/csrc/chx_internal.h",
-                  "paper_2507_00622_amd/csrc/lane_hh.hip"]
+# The benchmarked integration kernel: the HBM traffic recorded in profiles/
+# applies only while the kernel's machine code (its gfx950 instructions and
+# kernel descriptor in the built library) hashes to the value recorded
+# beside it.
+KERNEL_SYMBOL = "_ZN3chx11lane_kernelINS_5SysHHELi6ELb0ELi2EEEvNS_8StepArgsE"
+LIBRARY = "paper_2507_00622_amd/libchx.so"
 TRAFFIC_FILE = "profiles/lane_kernel_hh6_traffic.md"
 
 
-def kernel_source_hash():
+def _code_objects(data, arch="gfx950"):
+    """The arch's device code objects in the (uncompressed) clang offload
+    bundles embedded in a host shared library."""
+    import struct
+    magic = b"__CLANG_OFFLOAD_BUNDLE__"
+    out, i = [], data.find(magic)
+    while i >= 0:
+        p = i + len(magic)
+        (num,) = struct.unpack_from("<Q", data, p)
+        p += 8
+        for _ in range(num):
+            off, size, idlen = struct.unpack_from("<QQQ", data, p)
+            p += 24
+            ident = data[p:p + idlen].decode(errors="replace")
+            p += idlen
+            if arch in ident and size:
+                out.append(data[i + off:i + off + size])
+        i = data.find(magic, i + 1)
+    return out
+
+
+def _elf_symbol_bytes(co, names):
+    """Bytes of the named symbols (value and size from the ELF64 symbol
+    table, located through their sections) of one code object."""
+    import struct
+    e_shoff, = struct.unpack_from("<Q", co, 0x28)
+    e_shentsize, e_shnum = struct.unpack_from("<HH", co, 0x3A)
+    secs = [struct.unpack_from("<IIQQQQIIQQ", co, e_shoff + k * e_shentsize)
+            for k in range(e_shnum)]
+    found = {}
+    for s in secs:
+        if s[1] != 2:  # SHT_SYMTAB
+            continue
+        strtab = secs[s[6]]
+        for k in range(s[5] // s[9]):
+            name_off, _, _, shndx, value, size = struct.unpack_from("<IBBHQQ", co, s[4] + k * s[9])
+            end = co.find(b"\0", strtab[4] + name_off)
+            name = co[strtab[4] + name_off:end].decode(errors="replace")
+            if name in names and 0 < shndx < len(secs):
+                sec = secs[shndx]
+                start = sec[4] + value - sec[3]
+                found[name] = co[start:start + size]
+    return found
+
+
+def kernel_code_hash(symbol=KERNEL_SYMBOL, lib=LIBRARY):
+    """sha256 over a kernel's machine code and its kernel descriptor in the
+    built library, or None if it is not there."""
     import hashlib
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
+    try:
+        data = open(os.path.join(ROOT, lib), "rb").read()
+    except OSError:
+        return None
+    for co in _code_objects(data):
+        b = _elf_symbol_bytes(co, {symbol, symbol + ".kd"})
+        if symbol in b and symbol + ".kd" in b:
+            return hashlib.sha256(b[symbol] + b[symbol + ".kd"]).hexdigest()
+    return None
 
 
 def recorded_traffic():
@@ -55,15 +105,47 @@ def recorded_traffic():
         return None
     vals = {}
     for line in txt.splitlines():
-        if ":" in line and line.strip().startswith(("kernel-source-sha256", "traffic-bytes-per-launch")):
+        if ":" in line and line.strip().startswith(("kernel-code-sha256", "traffic-bytes-per-launch")):
             k, v = line.strip().split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
-    if vals.get("kernel-source-sha256") != kernel_source_hash():
+    h = kernel_code_hash()
+    if h is None or vals.get("kernel-code-sha256") != h:
         return None
     try:
         return float(vals["traffic-bytes-per-launch"])
     except (KeyError, ValueError):
         return None
+
+
+def model_flops_hh(m_s, n_l, ld, sali, K):
+    """Algorithmic FP64 flops per orbit-step of Henon-Heiles under Yoshida-4
+    by the path's flop model (FMA = 2, add/sub/mul = 1; sqrt, division, log
+    = 0): the state 70 (3 force and Hessian evaluations of 10, 4 kicks of 4,
+    the Hessian scaled for the 4 kicks 12, 3 drifts of 4), 44 per tangent
+    vector (4 kicks of 8, 3 drifts of 4), the LD 6 per step, and per
+    checkpoint (divided by K) the renormalised SALI pair 44 and the modified
+    Gram-Schmidt of 4 Lyapunov vectors 134.  This is the count of the
+    method as stated; the kernel merges commuting kicks and does fewer
+    (flops_per_step)."""
+    if (m_s, n_l) not in ((2, 0), (2, 4)) or not sali:
+        raise ValueError("the flop model covers the SALI pair with 0 or 4 Lyapunov vectors")
+    per = 70 + 44 * (m_s + n_l) + (6 if ld else 0)
+    return per + (44 + (134 if n_l == 4 else 0)) / K
+
+
+def model_flops_fput(N, n_l, m_g, K):
+    """The same model for an FPU-beta chain of N masses: the state 42N + 19
+    (3 force evaluations of 8N + 5, 4 kicks of 2N, the stiffnesses scaled
+    for the kicks 4N + 4, 3 drifts of 2N), 22N per tangent vector (4 kicks
+    of 4N, 3 drifts of 2N), and per checkpoint (divided by K) the modified
+    Gram-Schmidt of the 2N Lyapunov vectors 16N^3 + 4N^2 and the
+    renormalisation of the N GALI vectors 6N^2."""
+    if n_l not in (0, 2 * N) or m_g not in (0, N, 2):
+        raise ValueError("the flop model covers 2N Lyapunov and N (or 2 SALI) vectors")
+    per = 42 * N + 19 + 22 * N * (n_l + m_g)
+    ck = (16 * N ** 3 + 4 * N ** 2 if n_l else 0) + (6 * N ** 2 if m_g == N else 0) + \
+        (12 * N + 8 if m_g == 2 else 0)
+    return per + ck / K
 
 
 def flops_per_step(N, m_s, n_l, ld, energy, sali, K, system="hh"):
@@ -1327,7 +1409,8 @@ def main():
 
     orbit_steps = n_active * n_steps * args.steps
     value = orbit_steps / elapsed
-    fps = flops_per_step(2, 2, 4, True, True, True, K)
+    fps = model_flops_hh(2, 4, True, True, K)
+    fps_exec = flops_per_step(2, 2, 4, True, True, True, K)
     # dominant kernel: the integration launches (full-length ones)
     full = [(a.elapsed_time(b), n) for a, b, n in kernel_ms if n == spl]
     ms_avg = float(np.mean([t for t, _ in full])) if full else float("nan")
@@ -1372,7 +1455,9 @@ def main():
             "frac": achieved / PEAK_FP64,
             "traffic": recorded_traffic(),
             "kernel": "chx::lane_kernel<SysHH, 6, false, 2>",
+            "kernel_code_sha256": kernel_code_hash(),
             "flops_per_orbit_step": fps,
+            "flops_per_orbit_step_executed": fps_exec,
             "launch_ms": ms_avg,
             "launches_timed": len(full),
         },
@@ -1381,30 +1466,59 @@ def main():
     print(json.dumps(line), flush=True)
 
 
+def host_cpu():
+    """The host's logical CPU count, the CPUs this process may run on, and
+    the CPU model string."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return os.cpu_count() or 1, len(os.sched_getaffinity(0)), model
+
+
+# A GPU box gives one GPU's share of its host: 16 CPUs, whatever the count
+# of logical CPUs shows; the oracle's thread pool is held to that share.
+HOST_SHARE = 16
+
+
 def cpu_baseline(args, energies, n_side, dt, K):
     """The oracle, as it stands, on this host's cores: a strided sample of the
-    workload's orbits (both energies) for T = cpu_T."""
+    workload's orbits (both energies) for T = cpu_T, once on the CPUs of one
+    GPU's share of the host and once on one thread (a sixteenth of the
+    sample)."""
     import numpy as np
 
     import seeded_inputs as S
     from oracle import oracle as O
-    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    nproc, avail, model = host_cpu()
+    threads = max(1, min(HOST_SHARE, avail))
     xs = []
     for E in energies:
         x0, m = O.hh_grid(E, n_side, n_side)
         xs.append(x0[m == 1])
     x = np.concatenate(xs)
-    idx = np.linspace(0, len(x) - 1, args.cpu_sample).astype(int)
-    xs = x[idx]
-    w0 = S.deviation_vectors(1002, len(xs), 2, 4)
     run = O.Run(dt=dt, T=args.cpu_T, indicators=31, gali_kmax=2, n_lyap=4, K=K, escape_r2=4.0)
-    t0 = time.perf_counter()
-    O.integrate(O.henon_heiles(), xs, run, w0=w0, threads=threads)
-    el = time.perf_counter() - t0
-    n = len(xs) * int(round(args.cpu_T / dt))
+    steps = int(round(args.cpu_T / dt))
+
+    def timed(count, nthreads):
+        idx = np.linspace(0, len(x) - 1, count).astype(int)
+        w0 = S.deviation_vectors(1002, count, 2, 4)
+        t0 = time.perf_counter()
+        O.integrate(O.henon_heiles(), x[idx], run, w0=w0, threads=nthreads)
+        return count * steps, time.perf_counter() - t0
+
+    n, el = timed(args.cpu_sample, threads)
+    n1, el1 = timed(max(1, args.cpu_sample // 16), 1)
     return {"value": n / el, "unit": "orbit-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(xs)} orbits strided over both grids, T={args.cpu_T:g} "
-                      f"({n:.3g} orbit-steps, {el:.1f} s)"}
+            "sample": f"{args.cpu_sample} orbits strided over both grids, T={args.cpu_T:g} "
+                      f"({n:.3g} orbit-steps, {el:.1f} s on {threads} threads); one thread: "
+                      f"{max(1, args.cpu_sample // 16)} orbits ({n1:.3g} orbit-steps, {el1:.1f} s)",
+            "single_thread_value": n1 / el1,
+            "host": {"logical_cpus": nproc, "cpus_available": avail, "model": model}}
 
 
 if __name__ == "__main__":

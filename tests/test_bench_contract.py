@@ -72,10 +72,18 @@ def test_fput_and_quartic_flop_models():
     assert b - a > 8 * 24 * 16
 
 
-def test_traffic_record_needs_matching_sources(tmp_path, monkeypatch):
+def test_traffic_record_needs_matching_kernel_code(tmp_path, monkeypatch):
     f = tmp_path / "t.md"
-    f.write_text("kernel-source-sha256: `deadbeef`\ntraffic-bytes-per-launch: `123`\n")
+    f.write_text("kernel-code-sha256: `deadbeef`\ntraffic-bytes-per-launch: `123`\n")
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
     assert bench.recorded_traffic() is None
-    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "deadbeef")
+    monkeypatch.setattr(bench, "kernel_code_hash", lambda: "deadbeef")
     assert bench.recorded_traffic() == 123.0
+
+
+def test_kernel_code_hash_finds_the_benchmarked_kernel():
+    # the built library holds the kernel's gfx950 code and descriptor; a
+    # symbol that is not there gives None
+    h = bench.kernel_code_hash()
+    assert h is not None and len(h) == 64
+    assert bench.kernel_code_hash(symbol="_Z_no_such_kernel") is None
