@@ -23,6 +23,28 @@
 // empty.  Because the per-orbit code is the same LaneOrbit / CRowOrbit as
 // the plain kernels, an orbit's results do not depend on which slot or
 // launch integrated it.
+//
+// Memory ordering.  Within one launch no orbit, step count or queue slot
+// passes between wavefronts: an orbit is popped at most once per launch
+// and what a launch pushes is popped only by a later one.  All hand-over
+// goes from one kernel to a later one and across the XCDs, each with its
+// own L2.  Plain accesses there would depend on the cache maintenance at
+// the kernel boundary, and a plain store to a location that other kernels
+// read or update with atomics (the counters) meets accesses that do not
+// go through the writer's L2.  The protocol depends on neither:
+//   - every access to data that changes hands (the orbit's state and step
+//     count, queue slots, the counters) is an agent-scope atomic access,
+//     which reads and writes the device-coherent copy, never a line one
+//     XCD's L2 still holds from an earlier launch;
+//   - push: the orbit's state and step count are stored, then the queue
+//     slot is written with release semantics, so whoever reads the slot
+//     finds the state it names already written;
+//   - pop: the queue slot is read with acquire semantics before the state
+//     it names is loaded;
+//   - the counters move only by agent-scope atomics: the wave-aggregated
+//     atomicAdd of pop and push, the loads of head and (acquire) tail0 when
+//     a wavefront enters a pool, and the flip kernel's acquire load and
+//     release store of tail0.
 #include "batched.h"
 #include "fput_crow.h"
 #include "lane_kernel.h"
@@ -31,8 +53,18 @@ namespace chx {
 
 namespace {
 
+__device__ __forceinline__ unsigned long long ctr_acquire(unsigned long long *c) {
+  return __hip_atomic_load(c, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long ctr_relaxed(unsigned long long *c) {
+  return __hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void ctr_release(unsigned long long *c, unsigned long long v) {
+  __hip_atomic_store(c, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ unsigned long long tail0_of(const Pool &pl) {
-  return __atomic_load_n(&pl.ctr[2], __ATOMIC_RELAXED);
+  return ctr_acquire(&pl.ctr[2]);
 }
 
 // Wave-aggregated pop: lanes with need get an orbit index, or -1 when the
@@ -48,7 +80,9 @@ __device__ int64_t pop(const Pool &pl, unsigned long long t0, bool need) {
   if (!need) return -1;
   const unsigned long long slot = base + __popcll(m & ((1ull << lane) - 1ull));
   if (slot >= t0) return -1;
-  return gld<true>(&pl.queue[slot % (unsigned long long)pl.qcap]);
+  // acquire: pairs with the pushing launch's release of this slot
+  return __hip_atomic_load(&pl.queue[slot % (unsigned long long)pl.qcap], __ATOMIC_ACQUIRE,
+                           __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Wave-aggregated push of unfinished orbits.
@@ -62,7 +96,10 @@ __device__ void push(const Pool &pl, bool want, int64_t idx) {
   base = __shfl(base, leader);
   if (want) {
     const unsigned long long slot = base + __popcll(m & ((1ull << lane) - 1ull));
-    gst<true>(&pl.queue[slot % (unsigned long long)pl.qcap], idx);
+    // release: the orbit's state and step count, stored before, are
+    // visible to whoever acquires this slot
+    __hip_atomic_store(&pl.queue[slot % (unsigned long long)pl.qcap], idx, __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -129,7 +166,9 @@ __device__ int64_t run_crow_pool(const Pool &pl, int64_t left) {
     while (true) {
       const bool need = !have;
       if (!__any(need)) return;
-      // one pop per row, by its first lane, then shared with the row
+      // one pop per row, by its first lane, then shared with the row; the
+      // acquire is one wavefront instruction, so it orders the state loads
+      // of every lane of the row after it
       int64_t got = pop(pl, t0, need && (lane & 15) == 0);
       got = __shfl(got, head_lane);
       if (!__any(need && got >= 0)) return;
@@ -168,24 +207,15 @@ __device__ int64_t run_crow_pool(const Pool &pl, int64_t left) {
 
 // Three wavefronts per SIMD: the union of the four pool paths would take 180
 // VGPRs (two wavefronts); held to 168 the compiler spills 6 dwords, all
-// outside the step loops.
-// Orbit states, step counts and queue slots written in one launch are read
-// in the next by wavefronts on other XCDs, whose L2 caches are not coherent
-// with each other, and neighbouring orbits of one cache line are held by
-// wavefronts on different XCDs at once.  All of them are therefore read and
-// written with agent-scope (coherent) accesses, gld/gst, and each thread
-// also starts and ends with an agent-scope fence.  With plain accesses and
-// no fences, 25 of 100 runs of a mixed ensemble at 50 steps per launch
-// differed from the plain results; with both, none of 430 did.
+// outside the step loops.  The ordering rules are in the header comment.
 __global__ void __launch_bounds__(256, 3) batched_kernel(const BatchArgs b) {
-  __threadfence();
   const int wave = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   int p = 0;
   while (p + 1 < b.npool && wave >= b.split[p + 1]) ++p;
   int64_t left = b.budget;
   for (int tried = 0; tried < b.npool && left > 0; ++tried, p = (p + 1) % b.npool) {
     const Pool &pl = b.pool[p];
-    const unsigned long long head = __atomic_load_n(&pl.ctr[0], __ATOMIC_RELAXED);
+    const unsigned long long head = ctr_relaxed(&pl.ctr[0]);
     if (head >= tail0_of(pl)) continue;
     switch (pl.kind) {
     case POOL_HH2: left = run_lane_pool<SysHH>(pl, left); break;
@@ -194,19 +224,21 @@ __global__ void __launch_bounds__(256, 3) batched_kernel(const BatchArgs b) {
     case POOL_FPUT8_2: left = run_crow_pool<8>(pl, left); break;
     }
   }
-  __threadfence();
 }
 
 // Between launches: claims past tail0 return to it, and what was pushed in
-// the last launch becomes poppable.
+// the last launch becomes poppable.  Agent-scope atomics throughout (the
+// counters were last moved by atomicAdd on any XCD): acquire on entry,
+// release of the new tail0 last.
 __global__ void flip_kernel(const BatchArgs b) {
   const int p = threadIdx.x;
   if (p >= b.npool) return;
   unsigned long long *c = b.pool[p].ctr;
-  const unsigned long long t0 = c[2];
-  if (c[0] > t0) c[0] = t0;
-  c[2] = c[1];
-  __threadfence();
+  const unsigned long long t0 = ctr_acquire(&c[2]);
+  const unsigned long long head = ctr_relaxed(&c[0]);
+  const unsigned long long tail = ctr_relaxed(&c[1]);
+  if (head > t0) __hip_atomic_store(&c[0], t0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  ctr_release(&c[2], tail);
 }
 
 // Queue of all orbits 0..n-1; head = tail0 = 0, tail = n.
