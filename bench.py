@@ -310,10 +310,13 @@ def emit(args, metric, value, unit, elapsed, dtype, config, roofline, cpu, highe
             "data": "synthetic", "config": config, "roofline": roofline, "cpu_baseline": cpu}
 
 
-def advance_timed(e, n_steps, spl, stream, torch, log):
+def advance_timed(e, n_steps, spl, stream, torch, log, label=None, sync_every=50):
     """Advance an ensemble to its last step in launches of spl steps, with
-    HIP events around each launch on the stream it runs on."""
-    s = 0
+    HIP events around each launch on the stream it runs on.  With a label,
+    every sync_every launches the stream is drained and the count printed
+    (a progress line from the work itself for long runs)."""
+    s, k = 0, 0
+    total = (n_steps + spl - 1) // spl
     while s < n_steps:
         nxt = min(s + spl, n_steps)
         if log is not None:
@@ -326,6 +329,10 @@ def advance_timed(e, n_steps, spl, stream, torch, log):
         else:
             e.advance(nxt)
         s = nxt
+        k += 1
+        if label and k % sync_every == 0 and k < total:
+            stream.synchronize()
+            progress(f"{label}: {k}/{total} launches done")
 
 
 def bench_fput(args, P, chx, torch, dev):
@@ -347,6 +354,7 @@ def bench_fput(args, P, chx, torch, dev):
         u = torch.as_tensor(S.fput_mode_draws(1003 + N, n), device=dev)
         x0s[N] = P.ic_fput_modes(P.fput(N), u)
     logs = {8: [], 16: []}
+    last = {}
 
     def one_pass(record):
         for N in (8, 16):
@@ -354,8 +362,9 @@ def bench_fput(args, P, chx, torch, dev):
             e = P.Ensemble(P.fput(N), x0s[N], steps_per_launch=spl, dt=dt, T=T, indicators=ind,
                            gali_kmax=N, n_lyap=2 * N, renorm_every=K, seed=1003,
                            outputs=("status", "lyap", "gali"))
-            advance_timed(e, n_steps, spl, stream, torch, logs[N] if record else None)
-            e.results()
+            advance_timed(e, n_steps, spl, stream, torch, logs[N] if record else None,
+                          label=f"fput N={N}")
+            last[N] = e.results()
             e.close()
 
     for _ in range(args.warmup):
@@ -368,17 +377,29 @@ def bench_fput(args, P, chx, torch, dev):
     elapsed = time.perf_counter() - t0
     value = 2 * n * n_steps * args.steps / elapsed
     per_n = {}
+    checks = {}
     for N in (8, 16):
-        fps = flops_per_step_fput(N, N, 2 * N, False, True, True, K)
+        fps = model_flops_fput(N, 2 * N, N, K)
         full = [a.elapsed_time(b) for a, b, k in logs[N] if k == spl]
         ms = float(np.mean(full))
-        per_n[N] = dict(fps=fps, ms=ms, achieved=fps * n * spl / (ms * 1e-3), launches=len(full))
+        per_n[N] = dict(fps=fps, fps_exec=flops_per_step_fput(N, N, 2 * N, False, True, True, K),
+                        ms=ms, achieved=fps * n * spl / (ms * 1e-3), launches=len(full))
+        # on every orbit: the exponents of a Hamiltonian flow sum to zero;
+        # GALI_k lies in [0, 1] and does not grow with k
+        st = last[N]["status"].cpu().numpy()
+        ly = last[N]["lyap"].cpu().numpy()[st == 0]
+        ga = last[N]["gali"].cpu().numpy()[st == 0]
+        checks[N] = {"orbits_ok": int((st == 0).sum()), "orbits_stopped": int((st != 0).sum()),
+                     "max_abs_lyap_sum": float(np.max(np.abs(ly.sum(axis=1)))),
+                     "gali_outside_0_1": int(np.sum((ga < 0) | (ga > 1 + 1e-12))),
+                     "gali_increasing_in_k": int(np.sum(ga[:, 1:] > ga[:, :-1] * (1 + 1e-9))),
+                     "gali_N_median": float(np.median(ga[:, -1]))}
     r = per_n[16]
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import oracle as O
         threads = max(1, min(16, len(os.sched_getaffinity(0))))
-        cT = args.cpu_T if args.cpu_T != 1e4 else 100.0
+        cT = args.cpu_T if args.cpu_T != 1e4 else 2000.0
         tot, el = 0, 0.0
         for N in (8, 16):
             m = 32
@@ -389,22 +410,31 @@ def bench_fput(args, P, chx, torch, dev):
             O.integrate(O.fput(N), xs, run, w0=w0, threads=threads)
             el += time.perf_counter() - t1
             tot += m * int(round(cT / dt))
+        nproc, avail, model = host_cpu()
         cpu = {"value": tot / el, "unit": "orbit-steps/s", "cores": threads, "kind": "oracle",
-               "sample": f"32 orbits per N (8 and 16), T={cT:g} ({tot:.3g} orbit-steps, "
-                         f"{el:.1f} s)"}
+               "sample": f"32 orbits per N (8 and 16), T={cT:g}, same vectors and "
+                         f"checkpoints ({tot:.3g} orbit-steps, "
+                         f"{el:.1f} s)",
+               "host": {"logical_cpus": nproc, "cpus_available": avail, "model": model}}
     return emit(args, "FP64 trajectory-steps/s (with tangents)", value, "orbit-steps/s", elapsed,
                 "f64", {
                     "workload": f"FPU-beta chains N=8 and N=16 (k=1, beta=1), 65536 orbits each, "
                                 f"3N deviation vectors (2N Lyapunov by MGS/10 + N GALI), "
                                 f"dt={dt}, T={T:g}",
                     "orbits": 2 * n, "steps_per_orbit": n_steps, "steps_per_launch": spl,
-                    "per_N": {str(N): {"flops_per_orbit_step": v["fps"], "launch_ms": v["ms"],
+                    "per_N": {str(N): {"kernel": ("chx::fput_row_kernel<16, 3, 1, 1>" if N == 16
+                                                  else "chx::fput_row_kernel<8, 2, 1, 1>"),
+                                       "flops_per_orbit_step": v["fps"],
+                                       "flops_per_orbit_step_executed": v["fps_exec"],
+                                       "launch_ms": v["ms"],
                                        "tflops": v["achieved"] / 1e12,
-                                       "frac": v["achieved"] / PEAK_FP64}
+                                       "frac": v["achieved"] / PEAK_FP64,
+                                       "checks": checks[N]}
                               for N, v in per_n.items()}},
                 {"bound": "alu", "achieved": r["achieved"] / 1e12, "peak": PEAK_FP64 / 1e12,
                  "unit": "TFLOP/s", "frac": r["achieved"] / PEAK_FP64, "traffic": None,
-                 "kernel": "chx::fput_row_kernel<16, 2, 2>", "flops_per_orbit_step": r["fps"],
+                 "kernel": "chx::fput_row_kernel<16, 3, 1, 1>", "flops_per_orbit_step": r["fps"],
+                 "flops_per_orbit_step_executed": r["fps_exec"],
                  "launch_ms": r["ms"], "launches_timed": r["launches"]}, cpu)
 
 

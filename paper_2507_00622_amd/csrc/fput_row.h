@@ -17,11 +17,13 @@
 // lane's V vectors) -- no LDS, no readlane, no scalar memory.
 //
 // At checkpoints the Lyapunov set is orthonormalised by modified
-// Gram-Schmidt: the pivot's owner lane stages it in LDS, each lane of the
-// orbit reads one or two of its components, and every lane projects it out
-// of its own later vectors, taking the components by row_newbcast.  Row sums (energy, LD, escape radius) use a
-// quad_perm / half-mirror / mirror butterfly, so all 16 lanes hold the
-// same bits.
+// Gram-Schmidt.  With one row per orbit every lane takes the pivot's
+// components straight from the owner lane's registers through the FMA's
+// row_newbcast operand (pivots unrolled, no LDS); with two rows per orbit
+// the owner stages the pivot in LDS, each lane reads one or two of its
+// components and spreads them by row_newbcast.  Row sums (energy, LD,
+// escape radius) use a quad_perm / half-mirror / mirror butterfly, so all
+// 16 lanes hold the same bits.
 #pragma once
 #include <type_traits>
 
@@ -99,13 +101,14 @@ __device__ __forceinline__ double row_sum(double s) {
 // slot s of lane l in row r of the orbit is vector position
 // pos = (s R + r) 16 + l -- the rows interleave, so the Lyapunov set (the
 // first positions) is spread over all rows of the orbit.
-template <int N, int V, int R>
+// B: Gram-Schmidt pivots per round (one-row layouts).
+template <int N, int V, int R, int B = 1>
 __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
   using namespace fputrow;
   constexpr int D = 2 * N;
   constexpr int OPW = 4 / R;  // orbits per wavefront
   constexpr int CPL = (D + 15) / 16;  // pivot components per lane
-  __shared__ __align__(16) double piv[OPW][16][CPL];
+  __shared__ __align__(16) double piv[R == 1 ? 1 : OPW][16][CPL];
   const int lane = threadIdx.x & 15, row = threadIdx.x >> 4;
   const int ow = row / R, ro = row % R;
   const int64_t o = (int64_t)blockIdx.x * OPW + ow;
@@ -318,6 +321,163 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
 #pragma unroll
     for (int s = 0; s < V; ++s) own2[s] = 1.0;
     const int nls = (n_l + 16 * R - 1) / (16 * R);  // slots holding Lyapunov vectors
+    if constexpr (R == 1) {
+      // One row per orbit: the pivots are read straight from their owners'
+      // registers.  The dot products and the updates take component c of
+      // pivot j from lane j % 16 through the FMA's row_newbcast operand, so
+      // the pivots are unrolled (the lane is an immediate) and nothing is
+      // staged in LDS.  Pivots go B at a time (modified Gram-Schmidt
+      // regrouped): one pass of dot products of every later vector with
+      // the B pivots as they stand (B independent accumulators); the B x B
+      // Gram matrix G of the pivots from their owners' own dot products;
+      // its Cholesky factor L in every lane (L_nn is the norm of pivot n
+      // after projecting out pivots 0..n-1, as in modified Gram-Schmidt);
+      // then one pass of updates w <- w - P y with y = G^-1 (P^T w), the
+      // projection out of the pivots' span -- for the owner of pivot n the
+      // same solves cut to pivots 0..n-1, which leaves its vector's part
+      // orthogonal to them, of norm L_nn (kept for the growth and the
+      // normalisation after the last pivot).  Slots from nls on hold no
+      // Lyapunov vector (the set has at most 2N vectors, so at most
+      // ceil(2N / 16) slots).
+      //
+      // Ordering: the owners' coefficients for their own and later pivots
+      // are zero, so a source lane is unchanged until every pivot it owns
+      // has been applied.  In the pivots' own slot the updates go pivot by
+      // pivot in decreasing order (an owner is written only by the pivots
+      // before its own), each over all components, so no DPP read follows
+      // the write of its source register closely.
+      constexpr int NLS_MAX = (2 * N + 15) / 16 < V ? (2 * N + 15) / 16 : V;
+      constexpr int PS = B >= 4 ? 1 : 4 / B;  // partial sums per dot product
+      static_for<0, NLS_MAX>([&](auto gc) {
+        constexpr int sj = decltype(gc)::value;  // the pivots' slot
+        if (sj * 16 < n_l) {
+          auto group = [&](auto lc) {
+            constexpr int L = decltype(lc)::value;  // slots sj..L-1 hold Lyapunov vectors
+            static_for<0, 16 / B>([&](auto jc) {
+              constexpr int l0 = decltype(jc)::value * B;  // the first pivot's lane
+              const int j0 = sj * 16 + l0;
+              if (j0 < n_l) {
+                const int nb = n_l - j0 < B ? n_l - j0 : B;  // pivots in this round
+                // two wait states before the first DPP read of w[sj]
+                asm volatile("s_nop 1" : "+v"(w[sj][0]), "+v"(w[sj][1]));
+                double d[V][B][PS];
+#pragma unroll
+                for (int s = 0; s < V; ++s)
+#pragma unroll
+                  for (int m = 0; m < B; ++m)
+#pragma unroll
+                    for (int k = 0; k < PS; ++k) d[s][m][k] = 0.0;
+                static_for<0, D>([&](auto cc) {
+                  constexpr int c = decltype(cc)::value;
+                  static_for<0, B>([&](auto mc) {
+                    constexpr int m = decltype(mc)::value;
+#pragma unroll
+                    for (int s = sj; s < L; ++s)
+                      fmac_bcast_ordered<l0 + m>(d[s][m][c % PS], w[sj][c], w[s][c]);
+                  });
+                });
+                double t[V][B];
+#pragma unroll
+                for (int s = sj; s < L; ++s)
+#pragma unroll
+                  for (int m = 0; m < B; ++m) {
+                    double v = d[s][m][0];
+#pragma unroll
+                    for (int k = 1; k < PS; ++k) v += d[s][m][k];
+                    t[s][m] = v;
+                  }
+                if constexpr (B == 1)
+                  asm volatile("s_nop 1" : "+v"(t[sj][0]));
+                else if constexpr (B == 2)
+                  asm volatile("s_nop 1" : "+v"(t[sj][0]), "+v"(t[sj][1]));
+                else
+                  asm volatile("s_nop 1" : "+v"(t[sj][0]), "+v"(t[sj][1]), "+v"(t[sj][2]), "+v"(t[sj][3]));
+                // Gram matrix (upper triangle): G_mn = p_m . p_n, from the
+                // owner of p_n; identity rows past the last pivot
+                double G[B][B];
+                static_for<0, B>([&](auto nc) {
+                  constexpr int n = decltype(nc)::value;
+                  static_for<0, n + 1>([&](auto mc) {
+                    constexpr int m = decltype(mc)::value;
+                    const double g = bcast<l0 + n>(t[sj][m]);
+                    G[m][n] = n < nb ? g : (m == n ? 1.0 : 0.0);
+                  });
+                });
+                double Lm[B][B], rr[B], iv[B];
+#pragma unroll
+                for (int n = 0; n < B; ++n) {
+                  double r = G[n][n];
+#pragma unroll
+                  for (int k = 0; k < n; ++k) r = __builtin_fma(-Lm[n][k], Lm[n][k], r);
+                  rr[n] = r;
+                  iv[n] = rsqrt_nr(r);
+#pragma unroll
+                  for (int m = n + 1; m < B; ++m) {
+                    double v = G[n][m];
+#pragma unroll
+                    for (int k = 0; k < n; ++k) v = __builtin_fma(-Lm[m][k], Lm[n][k], v);
+                    Lm[m][n] = v * iv[n];
+                  }
+                }
+                // coefficients -y, with y = G^-1 (P^T w) cut to the first
+                // ne pivots: ne = nb for later Lyapunov vectors, the pivot's
+                // index for its owner, 0 before the pivots and outside the set
+                double ny[V][B];
+#pragma unroll
+                for (int s = sj; s < L; ++s) {
+                  const int pos = s * 16 + lane;
+                  int ne = pos < n_l ? nb : 0;
+                  if (s == sj) ne = lane < l0 ? 0 : (lane < l0 + nb ? lane - l0 : ne);
+                  double z[B], y[B];
+#pragma unroll
+                  for (int m = 0; m < B; ++m) {
+                    double v = t[s][m];
+#pragma unroll
+                    for (int k = 0; k < m; ++k) v = __builtin_fma(-Lm[m][k], z[k], v);
+                    z[m] = m < ne ? v * iv[m] : 0.0;
+                  }
+#pragma unroll
+                  for (int m = B - 1; m >= 0; --m) {
+                    double v = z[m];
+#pragma unroll
+                    for (int k = m + 1; k < B; ++k) v = __builtin_fma(-Lm[k][m], y[k], v);
+                    y[m] = v * iv[m];
+                    ny[s][m] = -y[m];
+                  }
+                }
+                {
+                  double o2 = own2[sj];
+#pragma unroll
+                  for (int m = 0; m < B; ++m) o2 = (lane == l0 + m && m < nb) ? rr[m] : o2;
+                  own2[sj] = o2;
+                }
+                // later slots: any order (they are no pivot's source)
+                static_for<0, D>([&](auto cc) {
+                  constexpr int c = decltype(cc)::value;
+                  static_for<0, B>([&](auto mc) {
+                    constexpr int m = decltype(mc)::value;
+#pragma unroll
+                    for (int s = sj + 1; s < L; ++s)
+                      fmac_bcast_ordered<l0 + m>(w[s][c], w[sj][c], ny[s][m]);
+                  });
+                });
+                // the pivots' slot: pivot by pivot, last first
+                static_for<0, B>([&](auto mc) {
+                  constexpr int m = B - 1 - decltype(mc)::value;
+                  static_for<0, D>([&](auto cc) {
+                    constexpr int c = decltype(cc)::value;
+                    fmac_bcast_ordered<l0 + m>(w[sj][c], w[sj][c], ny[sj][m]);
+                  });
+                });
+              }
+            });
+          };
+          static_for<sj + 1, NLS_MAX + 1>([&](auto lc) {
+            if (nls == decltype(lc)::value) group(lc);
+          });
+        }
+      });
+    } else
     static_for<0, V * R>([&](auto gc) {
       constexpr int G = decltype(gc)::value;
       constexpr int rj = G % R, sj = G / R;

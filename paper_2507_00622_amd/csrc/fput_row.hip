@@ -27,9 +27,18 @@ template <int N>
 hipError_t launch_n(int M, const StepArgs &a, hipStream_t s) {
   if (M <= 4) return launch_crow<N>(M, a, s);
   // vector rows: V = ceil(M / 16) slots per lane and one row per orbit
-  // while V N <= 32 (at most 64 doubles of vectors per lane); N = 16 with
-  // more than 32 vectors takes two rows per orbit.  M <= 4N, so V <= 2.
+  // while V N <= 32 (at most 64 doubles of vectors per lane), and for
+  // N = 16 with 33..48 vectors (three slots, 96 doubles: the full Lyapunov
+  // set and N GALI vectors with no slot position unused); N = 16 with more
+  // than 48 vectors takes two rows per orbit.  M <= 4N.
   const int V = (M + 15) / 16;
+  if constexpr (N == 16) {
+    if (V == 3) {
+      const unsigned grid = (unsigned)((a.n + 3) / 4);
+      hipLaunchKernelGGL((fput_row_kernel<16, 3, 1>), dim3(grid), dim3(64), 0, s, a);
+      return hipGetLastError();
+    }
+  }
   if (V * N <= 32) {
     const unsigned grid = (unsigned)((a.n + 3) / 4);
     if (V <= 1) {

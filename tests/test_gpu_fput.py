@@ -88,6 +88,28 @@ def test_fput_lyapunov_gali_parity(env, N, n, T):
     assert np.max(np.abs(g["ln_growth"] - o["ln_growth"])) < 1e-6
 
 
+def test_fput16_four_n_vectors_two_rows(env):
+    # N = 16 with more than 48 vectors runs on two rows per orbit (the
+    # pivots staged in LDS): the full Lyapunov set and 2N GALI vectors
+    torch, P, O = env
+    N, n, T = 16, 13, 40.0
+    say(f"case: FPU N={N} n={n} T={T} Lyapunov (2N) + GALI_2..2N (2N vectors)")
+    so, sg = O.fput(N), P.fput(N)
+    x0 = O.fput_ic(so, S.fput_mode_draws(1300, n))
+    w0 = S.deviation_vectors(1301, n, 2 * N, 2 * N)
+    kw = dict(dt=0.02, T=T, indicators=O.IND_LYAP | O.IND_GALI | O.IND_ENERGY,
+              n_lyap=2 * N, gali_kmax=2 * N)
+    g = run_gpu(env, sg, x0, None, w0, **kw)
+    o = O.integrate(so, x0, O.Run(**kw), w0=w0, threads=8)
+    assert np.array_equal(g["status"], o["status"])
+    le = np.max(np.abs(g["lyap"] - o["lyap"]))
+    ge = log_err(g["gali"], o["gali"], 1e-8)
+    say(f"  state {state_err(g['x_final'], o['x_final']).max():.3g} lyap {le:.3g} gali {ge:.3g}")
+    assert np.max(state_err(g["x_final"], o["x_final"])) < 1e-9
+    assert le < 1e-6 and ge < 1e-6
+    assert np.max(np.abs(g["lyap"].sum(axis=1))) < 1e-9
+
+
 @pytest.mark.parametrize("N", [16, 8])
 def test_fput_sali_ld_early_exit(env, N):
     torch, P, O = env
