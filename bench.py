@@ -148,6 +148,14 @@ def model_flops_fput(N, n_l, m_g, K):
     return per + ck / K
 
 
+def model_flops_quartic(m, sali=True):
+    """The path's flop model for the coupled quartic oscillators with 3
+    degrees of freedom: the state 147 (3 force and Hessian evaluations of
+    27, 4 kicks of 6, the Hessian scaled for the kicks 24, 3 drifts of 6), 90
+    per tangent vector, the SALI pair about 7 per step."""
+    return 147 + 90 * m + (7 if sali else 0)
+
+
 def flops_per_step(N, m_s, n_l, ld, energy, sali, K, system="hh"):
     """Algorithmic FP64 flops of one orbit-step of the lane-per-orbit path
     for Henon-Heiles (FMA = 2, add/mul = 1; sqrt, division, log and
@@ -618,11 +626,14 @@ def bench_batched(args, P, chx, torch, dev):
     accessible section points, E = 0.125), 2^18 coupled-quartic orbits
     (N = 3, eps = 0.1, E = 1) and 2^16 FPU-beta N = 16 orbits in one
     persistent launch sequence, two deviation vectors each, early exit at the
-    first checkpoint with SALI < 1e-8; against three plain launches."""
+    first checkpoint with SALI < 1e-8, T = 1e5 by default; against three
+    plain launches of the same work (one per system, early exit on), and
+    each system alone through the batched form.  value = labelled ICs/s of
+    the mixed batched run."""
     import numpy as np
 
     import seeded_inputs as S
-    T = args.T or 1e4
+    T = args.T or 1e5
     y, py = S.section_points(1004, 1400000)
     x, m = P.hh_section_points(0.125, torch.as_tensor(y, device=dev),
                                torch.as_tensor(py, device=dev))
@@ -634,11 +645,14 @@ def bench_batched(args, P, chx, torch, dev):
     items = [dict(sys=P.henon_heiles(), x0=xh, dt=0.01, T=T),
              dict(sys=P.quartic(3, 0.1), x0=xq, dt=0.01, T=T),
              dict(sys=P.fput(16), x0=xf, dt=0.02, T=T)]
+    names = ["henon-heiles", "quartic-3", "fput-16"]
     n_orbits = sum(int(it["x0"].shape[0]) for it in items)
     ind = chx.IND_SALI | chx.IND_ENERGY
     kw = dict(indicators=ind, seed=1004, early_exit=True, sali_threshold=1e-8,
               steps_per_launch=args.steps_per_launch, block_size=args.block)
     outs_keys = ("status", "label", "t_end")
+    fps = [model_flops_hh(2, 0, False, True, 10), model_flops_quartic(2),
+           model_flops_fput(16, 0, 2, 10)]
     progress(f"batched: {n_orbits} orbits, T={T:g}")
     for _ in range(args.warmup):
         P.integrate_batched(items, outputs=outs_keys, **kw)
@@ -650,25 +664,44 @@ def bench_batched(args, P, chx, torch, dev):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     progress(f"batched: {elapsed / args.steps:.2f} s per pass; plain launches")
-    # three plain launches of the same work
-    t1 = time.perf_counter()
-    ref = []
-    for i, it in enumerate(items):
-        ref.append(P.integrate_ensemble(it["sys"], it["x0"], dt=it["dt"], T=it["T"],
-                                        outputs=outs_keys, indicators=ind, seed=1004 + i,
-                                        early_exit=True, sali_threshold=1e-8))
-    torch.cuda.synchronize()
-    plain = time.perf_counter() - t1
-    agree = [float((a["label"] == b["label"]).float().mean()) for a, b in zip(outs, ref)]
     steps_exec = [int(v) for v in stats["orbit_steps"][:3]]
-    fps = [flops_per_step(2, 2, 0, False, True, True, 10),
-           flops_per_step_quartic(3, 2, False, True, True, 10),
-           flops_per_step_fput(16, 2, 0, False, True, True, 10)]
-    flops = sum(f * s for f, s in zip(fps, steps_exec))
     kern_s = stats["integrate_ms"] * 1e-3
+    flops = sum(f * s for f, s in zip(fps, steps_exec))
     achieved = flops / kern_s
+    # three plain launches of the same work; their useful orbit-steps are
+    # the steps each orbit actually integrated (t_end / dt)
+    plain_s, plain_frac, ref = [], [], []
+    for i, it in enumerate(items):
+        t1 = time.perf_counter()
+        r = P.integrate_ensemble(it["sys"], it["x0"], dt=it["dt"], T=it["T"], outputs=outs_keys,
+                                 indicators=ind, seed=1004 + i, early_exit=True,
+                                 sali_threshold=1e-8)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        ref.append(r)
+        plain_s.append(el)
+        useful = float(torch.round(r["t_end"] / it["dt"]).sum())
+        plain_frac.append(fps[i] * useful / el / PEAK_FP64)
+        progress(f"plain {names[i]}: {el:.2f} s")
+    plain = sum(plain_s)
+    agree = [float((a["label"] == b["label"]).float().mean()) for a, b in zip(outs, ref)]
+    # each system alone through the batched form
+    alone = []
+    for i, it in enumerate(items):
+        t1 = time.perf_counter()
+        _, st1 = P.integrate_batched([it], outputs=outs_keys, **dict(kw, seed=1004 + i))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        s1 = int(st1["orbit_steps"][0])
+        alone.append({"seconds": el, "integrate_s": st1["integrate_ms"] * 1e-3,
+                      "frac": fps[i] * s1 / (st1["integrate_ms"] * 1e-3) / PEAK_FP64,
+                      "threads_per_block": st1["threads_per_block"]})
+        progress(f"batched {names[i]} alone: {el:.2f} s")
     value = n_orbits * args.steps / elapsed
     exited = [int((o["status"] == 4).sum()) for o in outs]
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_batched(args, items, outs, names, T)
     return emit(args, "labelled ICs/s (persistent batched form)", value, "ICs/s", elapsed, "f64", {
         "workload": f"2^20 Henon-Heiles (E=0.125) + 2^18 quartic N=3 + 2^16 FPU-beta N=16, two "
                     f"deviation vectors, early exit at SALI<1e-8, dt 0.01/0.01/0.02, T={T:g}",
@@ -677,14 +710,58 @@ def bench_batched(args, P, chx, torch, dev):
         "executed_orbit_steps_per_s": sum(steps_exec) / kern_s,
         "threads_per_block": stats["threads_per_block"], "blocks": stats["blocks"],
         "launches": stats["launches"], "steps_per_launch": stats["steps_per_launch"],
-        "plain_three_launches_s": plain, "plain_ICs_per_s": n_orbits / plain,
+        "plain_seconds_per_system": plain_s, "plain_three_launches_s": plain,
+        "plain_ICs_per_s": n_orbits / plain,
         "speedup_vs_plain": plain / (elapsed / args.steps),
-        "label_agreement_vs_plain": agree},
+        "label_agreement_vs_plain": agree,
+        "per_system": {names[i]: {"plain_frac": plain_frac[i], "batched_alone": alone[i],
+                                  "flops_per_orbit_step": fps[i]} for i in range(3)}},
         {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
          "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
          "kernel": "chx::batched_kernel", "flops_per_orbit_step": fps,
          "launch_ms": stats["integrate_ms"] / max(stats["launches"], 1),
-         "launches_timed": stats["launches"]}, None)
+         "launches_timed": stats["launches"]}, cpu)
+
+
+def cpu_baseline_batched(args, items, outs, names, T):
+    """The oracle on a strided sample of each system's orbits (192
+    Henon-Heiles, 96 quartic, 24 FPU-16), early exit on, to the same T: its
+    rate in executed orbit-steps/s, and the sample's labels against the
+    batched form's."""
+    import numpy as np
+
+    import seeded_inputs as S
+    from oracle import oracle as O
+    nproc, avail, model = host_cpu()
+    threads = max(1, min(HOST_SHARE, avail))
+    osys = [O.henon_heiles(), O.quartic(3, 0.1), O.fput(16)]
+    counts = [192, 96, 24]
+    tot, el, agree, per = 0, 0.0, 0, {}
+    for i, it in enumerate(items):
+        n = int(it["x0"].shape[0])
+        idx = np.linspace(0, n - 1, counts[i]).astype(int)
+        xs = it["x0"].cpu().numpy()[idx]
+        D = xs.shape[1]
+        # the library's deviation vectors for these orbits (the batched form
+        # draws them from seed + item index)
+        w0 = np.stack([S.deviation_vectors(1004 + i, 1, 2, D, first_ic=int(k))[0] for k in idx])
+        run = O.Run(dt=it["dt"], T=T, indicators=O.IND_SALI | O.IND_ENERGY, K=10,
+                    early_exit=True, sali_threshold=1e-8)
+        t1 = time.perf_counter()
+        o = O.integrate(osys[i], xs, run, w0=w0, threads=threads)
+        d = time.perf_counter() - t1
+        el += d
+        steps = float(np.round(o["t_end"] / it["dt"]).sum())
+        tot += steps
+        lab = outs[i]["label"].cpu().numpy()[idx]
+        agree += int((lab == o["label"]).sum())
+        per[names[i]] = {"orbits": counts[i], "seconds": d,
+                         "label_agreement": float((lab == o["label"]).mean())}
+    return {"value": tot / el, "unit": "orbit-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"192 Henon-Heiles + 96 quartic + 24 FPU-16 orbits strided over the "
+                      f"workload, early exit, T={T:g} ({tot:.3g} executed orbit-steps, {el:.1f} s)",
+            "label_agreement_with_batched": agree / sum(counts), "per_system": per,
+            "host": {"logical_cpus": nproc, "cpus_available": avail, "model": model}}
 
 
 def bench_gate(args, P, chx, torch, dev):
