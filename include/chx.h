@@ -157,8 +157,12 @@ enum {
                            Dormand and Prince that the paper's solvers build on
                            (Functionalities section), fixed step, applied to the
                            state, the variational equations and the LD integrand
-                           as one system; every system, FPU chains with at most
-                           four deviation vectors (else CHX_ERR_UNSUPPORTED) */
+                           as one system; every system.  FPU chains with more than
+                           four deviation vectors keep them in LDS, 1 KB per
+                           vector for a block of four orbits (2 KB adaptive):
+                           a plan needing more than the device's LDS per block
+                           (160 KB on MI355X: every plan up to 4N vectors fits)
+                           gets CHX_ERR_UNSUPPORTED */
   CHX_INT_DOP853_ADAPTIVE = 2 /* the adaptive DOP 8(5) solver of the same
                            section: the same system, each orbit with its own step
                            size chosen from DOP853's embedded error estimate

@@ -19,6 +19,9 @@ namespace chx {
 // (fput_crow_rk.hip, fput_crow_rka.hip).
 hipError_t launch_fput_crow_rk(int ndof, int M, bool adaptive, const StepArgs &a,
                                hipStream_t s);
+// LDS per block of four orbits of the DOP853 FPU kernels with more than four
+// vectors (fput_crow_rkl.hip)
+size_t fput_rkl_lds_bytes(int M, bool adaptive);
 
 namespace host {
 
@@ -165,10 +168,22 @@ chx_status make_plan(const chx_system *sys, const chx_options *opt, Plan *p) {
   p->kmax = kmax;
   p->n_total = (int64_t)nr;
   const int sk = sys->kind;
-  if (o.integrator != CHX_INT_YOSHIDA4 && sk == CHX_SYS_FPUT && p->M > 4)
-    return fail(CHX_ERR_UNSUPPORTED, "DOP853 for FPU chains runs on the component rows: at most four deviation vectors (got %d)", p->M);
+  const bool fput_rk = o.integrator != CHX_INT_YOSHIDA4 && sk == CHX_SYS_FPUT;
+  if (fput_rk && p->M > 4) {
+    // DOP853 for FPU chains with more than four vectors keeps them in LDS:
+    // a block of four orbits needs 1 KB per vector (2 KB adaptive)
+    const size_t need = fput_rkl_lds_bytes(p->M, o.integrator == CHX_INT_DOP853_ADAPTIVE);
+    int dev = 0, lim = 65536;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        lim <= 0)
+      lim = 65536;
+    if (need > (size_t)lim)
+      return fail(CHX_ERR_UNSUPPORTED, "DOP853 for FPU chains with %d deviation vectors needs %zu B of LDS per block of four orbits; the device allows %d", p->M, need, lim);
+  }
   const bool ok = (sk == CHX_SYS_FPUT)
-                      ? fput_row_supported(N, p->M, p->n_l, (o.indicators & CHX_IND_SALI) != 0)
+                      ? (fput_rk ? p->M <= 4 * N
+                                 : fput_row_supported(N, p->M, p->n_l, (o.indicators & CHX_IND_SALI) != 0))
                       : lane_supported(sk, N, p->M);
   if (!ok)
     return fail(CHX_ERR_UNSUPPORTED, "system kind %d with ndof %d and %d deviation vectors is not supported", sk, N, p->M);

@@ -1,9 +1,12 @@
-// fput_crow_rk.hip -- launcher of the fixed-step DOP853 component-row
-// kernels for FPU chains (N = 2..16, up to four deviation vectors).
+// fput_crow_rk.hip -- launcher of the DOP853 component-row kernels for FPU
+// chains (N = 2..16): up to four deviation vectors in registers here, more
+// in LDS (fput_crow_rkl.hip).
 #include "fput_crow_rk.h"
 
 namespace chx {
 hipError_t launch_fput_crow_rka(int ndof, int M, const StepArgs &a, hipStream_t s);
+// more than four vectors: the vectors in LDS (fput_crow_rkl.hip)
+hipError_t launch_fput_crow_rkl(int ndof, bool adaptive, const StepArgs &a, hipStream_t s);
 
 namespace {
 template <int N>
@@ -25,6 +28,7 @@ hipError_t launch_rk(int M, const StepArgs &a, hipStream_t s) {
 hipError_t launch_fput_crow_rk(int ndof, int M, bool adaptive, const StepArgs &a,
                                hipStream_t s) {
   if (a.n == 0) return hipSuccess;
+  if (M > 4) return launch_fput_crow_rkl(ndof, adaptive, a, s);
   if (adaptive) return launch_fput_crow_rka(ndof, M, a, s);
   switch (ndof) {
   case 2: return launch_rk<2>(M, a, s);

@@ -99,13 +99,15 @@ def test_bad_options(kw, msg):
 
 
 def test_dop853_fpu_vector_limit():
-    # FPU chains run DOP853 on the component rows: at most four vectors
-    for integ in ("dop853", "dop853_adaptive"):
-        with pytest.raises(chx.ChxError) as e:
-            chx.integrate_ensemble(P.fput(4), np.zeros((2, 8)), dt=0.01, T=1.0,
-                                   indicators=chx.IND_SALI | chx.IND_LYAP, n_lyap=3,
-                                   integrator=integ)
-        assert e.value.status == chx.ERR_UNSUPPORTED and "four" in str(e.value)
+    # FPU chains with more than four vectors run DOP853 with the vectors in
+    # LDS, 1 KB per vector per block of four orbits (2 KB adaptive): without
+    # a device the limit taken is 64 KB, so 4N = 64 vectors at N = 16 fit
+    # the fixed-step solver but not the adaptive one
+    with pytest.raises(chx.ChxError) as e:
+        chx.integrate_ensemble(P.fput(16), np.zeros((2, 32)), dt=0.01, T=1.0,
+                               indicators=chx.IND_GALI | chx.IND_LYAP, gali_kmax=32,
+                               n_lyap=32, integrator="dop853_adaptive")
+    assert e.value.status == chx.ERR_UNSUPPORTED and "LDS" in str(e.value)
     with pytest.raises(chx.ChxError) as e:
         chx.integrate_batched([dict(sys=P.henon_heiles(), x0=hh_x0(4), dt=0.01, T=1.0)],
                               indicators=chx.IND_SALI, integrator="dop853")

@@ -178,3 +178,61 @@ def test_fput_dop853_edges_resume_blocks(env):
         e.close()
         for k in g:
             assert np.array_equal(g[k], r[k], equal_nan=True), (integ, k)
+
+
+# More than four vectors: the component rows keep them in LDS.  The full
+# Lyapunov spectrum (2N vectors) under both DOP853 solvers, at N = 8 with
+# the SALI/GALI set beside it (3N vectors) and at N = 16 (2N vectors).
+@pytest.mark.parametrize("integ", ["dop853", "dop853_adaptive"])
+@pytest.mark.parametrize("N,gali", [(8, True), (16, False)])
+def test_fput_dop853_full_spectrum_lds(env, N, gali, integ):
+    torch, P, O = env
+    n, T = 23, 40.0  # ragged: the last block of four orbits has three
+    say(f"case: FPU N={N} {integ}, 2N Lyapunov vectors{' + N GALI' if gali else ''}, "
+        f"n={n}, T={T}")
+    so, sg = O.fput(N), P.fput(N)
+    x0 = O.fput_ic(so, S.fput_mode_draws(1600 + N, n))
+    ind = O.IND_LYAP | O.IND_ENERGY
+    kw = dict(dt=0.02, T=T, n_lyap=2 * N)
+    w0 = None
+    if gali:
+        ind |= O.IND_SALI | O.IND_GALI
+        kw["gali_kmax"] = N
+        w0 = S.deviation_vectors(1700 + N, n, N, 2 * N)
+    kw["indicators"] = ind
+    if integ == "dop853_adaptive":
+        kw.update(rtol=1e-10, atol=1e-10)
+    g = run_gpu(env, sg, x0, None, w0, integrator=integ, **kw)
+    o = O.integrate(so, x0, oracle_run(O, integ, **kw), w0=w0, threads=8)
+    E = np.array([O.hamiltonian(so, x) for x in x0])
+    assert np.array_equal(g["status"], o["status"])
+    sel = np.ones(n, bool)
+    if integ == "dop853_adaptive":
+        sel = (g["steps"][:, 0] == o["steps_accepted"]) & (g["steps"][:, 1] == o["steps_rejected"])
+        say("  same step counts", sel.sum(), "of", n, "steps/orbit", g["steps"][:, 0].mean())
+        assert sel.sum() >= 0.95 * n
+    le = np.max(np.abs(g["lyap"][sel] - o["lyap"][sel]))
+    say(f"  lyap {le:.3g}")
+    compare(g, o, sel, E, 1e-9, integ)
+    assert le < 1e-6
+    assert np.max(np.abs(g["energy_err"][sel] - o["energy_err"][sel]) / np.maximum(1.0, E[sel])) < 1e-10
+
+
+def test_fput_dop853_lds_resume_and_launch_split(env):
+    # the LDS kernels write their vectors back at every launch end: split
+    # launches give the same bits as one
+    torch, P, O = env
+    say("case: FPU N=8 DOP853 (LDS vectors): launches of 70 steps against one")
+    so, sg = O.fput(8), P.fput(8)
+    n = 9
+    x0 = O.fput_ic(so, S.fput_mode_draws(1800, n))
+    dev = torch.device("cuda:0")
+    kw = dict(dt=0.02, T=6.0, indicators=O.IND_LYAP | O.IND_ENERGY, n_lyap=16,
+              integrator="dop853")
+    one = run_gpu(env, sg, x0, **kw)
+    e = P.Ensemble(sg, torch.as_tensor(x0, device=dev), steps_per_launch=70, **kw)
+    e.advance()
+    r = {k: v.cpu().numpy() for k, v in e.results().items()}
+    e.close()
+    for k in one:
+        assert np.array_equal(one[k], r[k], equal_nan=True), k
