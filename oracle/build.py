@@ -15,6 +15,13 @@ CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
           "-std=c11", "-Wall", "-Wextra", "-Werror"]
 
 
+# AddressSanitizer + UndefinedBehaviorSanitizer build of the same source (a
+# checking build: load it with the sanitizer runtime preloaded, e.g.
+# LD_PRELOAD=$(gcc -print-file-name=libasan.so), and run the oracle's tests)
+SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+            "-fno-omit-frame-pointer", "-g"]
+
+
 def build(force=True, extra=()):
     """Compile oracle/chx_oracle.c into oracle/libchx_oracle.so."""
     if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
@@ -27,4 +34,5 @@ def build(force=True, extra=()):
 
 
 if __name__ == "__main__":
-    print(build())
+    import sys
+    print(build(extra=SANITIZE if "--sanitize" in sys.argv else ()))
