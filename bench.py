@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64 = 78.6e12  # MI355X FP64 vector peak, FLOP/s (FMA = 2)
+PEAK_BF16 = 2.5e15  # MI355X dense BF16 matrix peak, FLOP/s
 
 # The benchmarked integration kernel: the HBM traffic recorded in profiles/
 # applies only while the kernel's machine code (its gfx950 instructions and
@@ -154,6 +155,17 @@ def model_flops_quartic(m, sali=True):
     27, 4 kicks of 6, the Hessian scaled for the kicks 24, 3 drifts of 6), 90
     per tangent vector, the SALI pair about 7 per step."""
     return 147 + 90 * m + (7 if sali else 0)
+
+
+def mlp_train_flops_per_row(padded=False):
+    """Flops of the gate's products for one row in one training epoch: the
+    forward pass 6 -> 256 -> 256 -> 2, the weight gradients of the three
+    layers and the activation gradients of the two hidden layers (the input
+    needs none).  padded=True counts the products as the matrix cores run
+    them, on 16 inputs and 16 logits."""
+    i, h, o = (16, 256, 16) if padded else (6, 256, 2)
+    layers = i * h + h * h + h * o
+    return 2 * layers + 2 * layers + 2 * (o * h + h * h)
 
 
 def flops_per_step(N, m_s, n_l, ld, energy, sali, K, system="hh"):
@@ -835,6 +847,17 @@ def bench_gate(args, P, chx, torch, dev):
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
             "kernel": "chx::lane_kernel<SysHH, 2, false, 2>", "flops_per_orbit_step": fps,
             "launch_ms": None, "launches_timed": None}
+    # the perceptron's training against the BF16 matrix peak: the products'
+    # algorithmic flops over the whole training time (every kernel of the
+    # pass and the gaps between launches included)
+    mlp_fl = mlp_train_flops_per_row() * n_train * epochs
+    roof_mlp = {"bound": "mfma", "achieved": mlp_fl / t_train / 1e12,
+                "peak": PEAK_BF16 / 1e12, "unit": "TFLOP/s",
+                "frac": mlp_fl / t_train / PEAK_BF16, "traffic": None,
+                "kernel": "chx::gemm_tile_kernel (training pass, all kernels)",
+                "flops_per_row_epoch": mlp_train_flops_per_row(),
+                "executed_flops_per_row_epoch": mlp_train_flops_per_row(True),
+                "time_basis": "whole training call"}
     return emit(args, "labelled ICs/s (learned gate + fallback)", value, "ICs/s", elapsed,
                 "f64+bf16", {
                     "workload": f"Henon-Heiles E=0.125 2048x2048 section grid, labels by SALI<1e-8 "
@@ -850,7 +873,8 @@ def bench_gate(args, P, chx, torch, dev):
                     "ms_fallback": st["ms_fallback"],
                     "label_generation_s": t_label, "train_s": t_train, "epochs": epochs,
                     "epoch_loss": [float(v) for v in losses],
-                    "train_chaotic_fraction": float((lab == 1).float().mean())},
+                    "train_chaotic_fraction": float((lab == 1).float().mean()),
+                    "roofline_mlp_training": roof_mlp},
                 roof, None)
 
 

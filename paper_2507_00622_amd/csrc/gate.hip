@@ -87,6 +87,7 @@ struct Acts {
   uint16_t *X, *A1b, *A2b, *dZ3b, *dZ2b, *dZ1b;
   float *Z1, *Z2, *Z3, *dZ3, *dA2, *dZ2, *dA1, *dZ1;
   float *part;  // column-sum partials
+  float *work;  // split-K parts of the weight gradients
   int64_t *rows;
 };
 
@@ -109,6 +110,7 @@ bool alloc_acts(Scratch &S, int64_t B, bool backward, Acts *a) {
     a->dZ1b = S.get<uint16_t>(B * MLP_H);
     a->rows = S.get<int64_t>(B);
     a->part = S.get<float>((size_t)mlp_colsum_blocks((int)B) * MLP_H);
+    a->work = S.get<float>(MLP_SPLITK_WORK);
   }
   return S.err == hipSuccess;
 }
@@ -142,25 +144,25 @@ hipError_t backward(chx_gate *g, const Acts &a, int B, const int8_t *labels, con
     return e;
   // layer 3
   if ((e = mlp_gemm(a.A2b, 1, MLP_H, a.dZ3b, MLP_OUTP, 1, gr + MLP_W3, MLP_OUTP, MLP_H, MLP_OUTP,
-                    B, nullptr, 0, s)))
+                    B, nullptr, 0, s, a.work, MLP_SPLITK_WORK)))
     return e;
   if ((e = mlp_colsum(a.dZ3, B, MLP_OUTP, MLP_OUTP, gr + MLP_B3, a.part, s))) return e;
   if ((e = mlp_gemm(a.dZ3b, MLP_OUTP, 1, pb + MLP_W3, 1, MLP_OUTP, a.dA2, MLP_H, B, MLP_H,
-                    MLP_OUTP, nullptr, 0, s)))
+                    MLP_OUTP, nullptr, 0, s, a.work, MLP_SPLITK_WORK)))
     return e;
   // layer 2
   if ((e = mlp_gelu_back(a.dA2, a.Z2, a.dZ2, a.dZ2b, (int64_t)B * MLP_H, s))) return e;
   if ((e = mlp_gemm(a.A1b, 1, MLP_H, a.dZ2b, MLP_H, 1, gr + MLP_W2, MLP_H, MLP_H, MLP_H, B,
-                    nullptr, 0, s)))
+                    nullptr, 0, s, a.work, MLP_SPLITK_WORK)))
     return e;
   if ((e = mlp_colsum(a.dZ2, B, MLP_H, MLP_H, gr + MLP_B2, a.part, s))) return e;
   if ((e = mlp_gemm(a.dZ2b, MLP_H, 1, pb + MLP_W2, 1, MLP_H, a.dA1, MLP_H, B, MLP_H, MLP_H,
-                    nullptr, 0, s)))
+                    nullptr, 0, s, a.work, MLP_SPLITK_WORK)))
     return e;
   // layer 1
   if ((e = mlp_gelu_back(a.dA1, a.Z1, a.dZ1, a.dZ1b, (int64_t)B * MLP_H, s))) return e;
   if ((e = mlp_gemm(a.X, 1, MLP_INP, a.dZ1b, MLP_H, 1, gr + MLP_W1, MLP_H, MLP_INP, MLP_H, B,
-                    nullptr, 0, s)))
+                    nullptr, 0, s, a.work, MLP_SPLITK_WORK)))
     return e;
   return mlp_colsum(a.dZ1, B, MLP_H, MLP_H, gr + MLP_B1, a.part, s);
 }
@@ -286,6 +288,8 @@ chx_status chx_gate_train(chx_gate *g, const float *features, const int8_t *labe
   }
   GCHK(mlp_fill(loss, c.epochs, 0.f, s), "clear loss");
   const int64_t nbatch = (n + B - 1) / B;
+  // the BF16 copy of the weights; each AdamW step refreshes it
+  GCHK(mlp_to_bf16(g->p, g->pb, MLP_NPARAM, s), "weights to bf16");
   for (int ep = 0; ep < c.epochs; ++ep) {
     // epoch permutation i -> (pa i + pc) mod n with pa coprime to n
     const uint64_t key = mix64(c.seed ^ mix64(0x6a7e0000ull + (uint64_t)ep));
@@ -298,18 +302,16 @@ chx_status chx_gate_train(chx_gate *g, const float *features, const int8_t *labe
       const int Bp = (int)round16(rows);
       GCHK(mlp_batch_rows(n, start, Bp, pa, pc, a.rows, s), "batch rows");
       GCHK(mlp_batch_input(feat, a.rows, Bp, n, g->mean, g->istd, a.X, s), "batch input");
-      GCHK(mlp_to_bf16(g->p, g->pb, MLP_NPARAM, s), "weights to bf16");
       GCHK(forward(g, a, Bp, s), "forward");
       GCHK(backward(g, a, Bp, lab, a.rows, n, 1.0f / (float)rows, loss + ep, s), "backward");
       g->t += 1;
       const double bc1 = 1.0 - pow((double)c.beta1, (double)g->t);
       const double bc2 = 1.0 - pow((double)c.beta2, (double)g->t);
-      GCHK(mlp_adamw(g->p, g->g, g->m, g->v, g->mask, MLP_NPARAM, c.lr, c.beta1, c.beta2, c.eps,
-                     c.weight_decay, (float)bc1, (float)bc2, s),
+      GCHK(mlp_adamw(g->p, g->pb, g->g, g->m, g->v, g->mask, MLP_NPARAM, c.lr, c.beta1, c.beta2,
+                     c.eps, c.weight_decay, (float)bc1, (float)bc2, s),
            "AdamW");
     }
   }
-  GCHK(mlp_to_bf16(g->p, g->pb, MLP_NPARAM, s), "weights to bf16");
   std::vector<float> hl((size_t)c.epochs);
   if (c.epochs > 0) GCHK(hipMemcpyAsync(hl.data(), loss, sizeof(float) * c.epochs, hipMemcpyDeviceToHost, s), "read loss");
   GCHK(hipStreamSynchronize(s), "synchronise");

@@ -21,9 +21,14 @@ constexpr int64_t MLP_W3 = MLP_B2 + MLP_H;
 constexpr int64_t MLP_B3 = MLP_W3 + (int64_t)MLP_H * MLP_OUTP;
 constexpr int64_t MLP_NPARAM = MLP_B3 + MLP_OUTP;
 
+// C = A B (+ bias) (+ C): BF16 operands at any strides, FP32 result.
+// work (work_len floats, may be null) holds split-K partial products.
 hipError_t mlp_gemm(const uint16_t *A, int64_t a_r, int64_t a_c, const uint16_t *B, int64_t b_r,
                     int64_t b_c, float *C, int64_t ldc, int M, int N, int K, const float *bias,
-                    int accumulate, hipStream_t s);
+                    int accumulate, hipStream_t s, float *work = nullptr, int64_t work_len = 0);
+// split-K workspace of the training pass (floats): up to 16 parts of the
+// 256 x 256 weight gradient
+constexpr int64_t MLP_SPLITK_WORK = (int64_t)16 * MLP_H * MLP_H;
 hipError_t mlp_gelu(const float *Z, uint16_t *Ab, int64_t n, hipStream_t s);
 hipError_t mlp_gelu_back(const float *dA, const float *Z, float *dZ, uint16_t *dZb, int64_t n,
                          hipStream_t s);
@@ -42,9 +47,11 @@ hipError_t gate_select(int64_t n, const int *status, const int8_t *label1, const
                        hipStream_t s);
 hipError_t gate_scatter(int64_t n2, const int64_t *orbit, const int8_t *label2, int8_t *label,
                         hipStream_t s);
-hipError_t mlp_adamw(float *p, const float *g, float *m, float *v, const uint8_t *mask, int64_t n,
-                     float lr, float b1, float b2, float eps, float wd, float bc1, float bc2,
-                     hipStream_t s);
+// AdamW on the FP32 masters p (entries with mask set); pb receives their
+// BF16 copies.
+hipError_t mlp_adamw(float *p, uint16_t *pb, const float *g, float *m, float *v,
+                     const uint8_t *mask, int64_t n, float lr, float b1, float b2, float eps,
+                     float wd, float bc1, float bc2, hipStream_t s);
 hipError_t mlp_to_bf16(const float *x, uint16_t *y, int64_t n, hipStream_t s);
 hipError_t mlp_batch_input(const float *feat, const int64_t *rows, int B, int64_t n_valid,
                            const float *mean, const float *istd, uint16_t *X, hipStream_t s);

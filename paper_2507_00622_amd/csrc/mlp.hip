@@ -30,39 +30,168 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // C[M][N] (fp32, row stride ldc) = A B (+ bias[col]) (+ C if accumulate),
-// A(i,k) = A[i*a_r + k*a_c], B(k,j) = B[k*b_r + j*b_c], both BF16.
-// One wavefront per 16x16 tile of C; M, N, K multiples of 16.
-__global__ void __launch_bounds__(256) gemm_bf16_kernel(const uint16_t *A, int64_t a_r,
+// A(i,k) = A[i*a_r + k*a_c], B(k,j) = B[k*b_r + j*b_c], both BF16; M, N, K
+// multiples of 16.  A block of 4 wavefronts computes a BM x BN tile of C,
+// (64, 64), (16, 64) or (64, 16) (rows past M are not stored).  K goes in
+// chunks of 32: the block stages the chunk of A (BM x 32) and of B
+// (32 x BN) in LDS with k contiguous (As[i][k], Bs[j][k], rows padded to 40
+// elements against bank conflicts), reading global memory along whichever
+// index has unit stride, 8 elements (16 bytes) per thread where VEC says the
+// addresses allow it; rows past M and k past K are staged as zeros.  Each
+// wavefront takes its 16 x 16 tiles' fragments from LDS (4 consecutive k
+// per lane, one 8-byte read) and issues v_mfma_f32_16x16x16bf16_1k per tile
+// and 16 k: lane l holds A[l % 16][4 (l / 16) + e], B[4 (l / 16) + e][l % 16]
+// and, after, D[4 (l / 16) + r][l % 16].  Split K: block z of gridDim.z
+// takes chunks [z cpc, (z + 1) cpc) and, when gridDim.z > 1, writes its
+// partial tile to work[z][M][N]; a second kernel adds the parts in order of
+// z (deterministic) with the bias and the accumulation.
+constexpr int GBK = 32, GPAD = 40;
+
+template <int BM, int BN, bool VEC>
+__global__ void __launch_bounds__(256) gemm_tile_kernel(const uint16_t *A, int64_t a_r,
                                                         int64_t a_c, const uint16_t *B,
                                                         int64_t b_r, int64_t b_c, float *C,
                                                         int64_t ldc, int M, int N, int K,
-                                                        const float *bias, int accumulate) {
-  const int wave = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
-  const int lane = threadIdx.x & 63;
-  const int tiles_n = N / 16;
-  const int tm = wave / tiles_n, tn = wave % tiles_n;
-  if (tm * 16 >= M) return;
-  const int row0 = tm * 16, col0 = tn * 16;
+                                                        int cpc, const float *bias,
+                                                        int accumulate, float *work) {
+  // wavefronts: (64, 64) 2 x 2 of 2 x 2 tiles; (64, 16) 4 x 1 and (16, 64)
+  // 1 x 4 of one tile
+  constexpr int WGM = BM == 64 && BN == 64 ? 2 : (BM == 64 ? 4 : 1);
+  constexpr int WGN = 4 / WGM;
+  constexpr int TM = BM / (16 * WGM), TN = BN / (16 * WGN);
+  __shared__ __align__(16) uint16_t As[BM][GPAD];
+  __shared__ __align__(16) uint16_t Bs[BN][GPAD];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = wave / WGN, wn = wave % WGN;
+  const int row0 = blockIdx.y * BM, col0 = blockIdx.x * BN;
+  const int kbeg = blockIdx.z * cpc * GBK;
+  const int kend = min(K, kbeg + cpc * GBK);
   const int li = lane & 15, lk = 4 * (lane >> 4);
-  float4_t acc = {0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    short4_t a, b;
+  float4_t acc[TM][TN];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      a[e] = (short)A[(int64_t)(row0 + li) * a_r + (int64_t)(k0 + lk + e) * a_c];
-      b[e] = (short)B[(int64_t)(k0 + lk + e) * b_r + (int64_t)(col0 + li) * b_c];
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) acc[a][b] = (float4_t){0.f, 0.f, 0.f, 0.f};
+  // This thread's run of 8 elements of the A chunk and of the B chunk (at
+  // most one each: BM * 32 / 8 <= 256 runs).  A: (i, kk) along k when
+  // a_c == 1, else along i; B: (j, kk) along k when b_r == 1, else along j.
+  // M and K are multiples of 16 and runs start at multiples of 8, so a run
+  // is wholly inside or wholly outside the matrix.
+  constexpr int RA = BM * GBK / 8, RB = BN * GBK / 8;
+  const bool a_k = a_c == 1, b_k = b_r == 1;
+  const int ai = a_k ? tid / (GBK / 8) : (tid % (BM / 8)) * 8;
+  const int ak = a_k ? (tid % (GBK / 8)) * 8 : tid / (BM / 8);
+  const int bj = b_k ? tid / (GBK / 8) : (tid % (BN / 8)) * 8;
+  const int bk = b_k ? (tid % (GBK / 8)) * 8 : tid / (BN / 8);
+  const int64_t a_step = a_k ? 1 : a_r, b_step = b_k ? 1 : b_c;
+  auto load_run = [](const uint16_t *src, int64_t step, bool vec) {
+    uint4 v;
+    if (vec && step == 1) {
+      v = *(const uint4 *)src;
+    } else {
+      uint16_t *h = (uint16_t *)&v;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) h[e] = src[(int64_t)e * step];
     }
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
-  }
-  // lane holds D[4*(lane/16) + r][lane % 16]
+    return v;
+  };
+  auto load_a = [&](int k0) {
+    if (tid < RA && row0 + ai < M && k0 + ak < K)
+      return load_run(A + (int64_t)(row0 + ai) * a_r + (int64_t)(k0 + ak) * a_c, a_step, VEC);
+    return make_uint4(0, 0, 0, 0);
+  };
+  auto load_b = [&](int k0) {
+    if (tid < RB && k0 + bk < K)
+      return load_run(B + (int64_t)(k0 + bk) * b_r + (int64_t)(col0 + bj) * b_c, b_step, VEC);
+    return make_uint4(0, 0, 0, 0);
+  };
+  uint4 va = load_a(kbeg), vb = load_b(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += GBK) {
+    if (tid < RA) {
+      if (a_k) {
+        *(uint4 *)&As[ai][ak] = va;
+      } else {
+        const uint16_t *h = (const uint16_t *)&va;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int i = row0 + lk + r, j = col0 + li;
-    float v = acc[r];
-    if (bias) v += bias[j];
-    float *dst = C + (int64_t)i * ldc + j;
-    *dst = accumulate ? *dst + v : v;
+        for (int e = 0; e < 8; ++e) As[ai + e][ak] = h[e];
+      }
+    }
+    if (tid < RB) {
+      if (b_k) {
+        *(uint4 *)&Bs[bj][bk] = vb;
+      } else {
+        const uint16_t *h = (const uint16_t *)&vb;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) Bs[bj + e][bk] = h[e];
+      }
+    }
+    __syncthreads();
+    // the next chunk's loads go out before this chunk's products
+    if (k0 + GBK < kend) {
+      va = load_a(k0 + GBK);
+      vb = load_b(k0 + GBK);
+    }
+#pragma unroll
+    for (int kk = 0; kk < GBK; kk += 16) {
+      short4_t af[TM], bfr[TN];
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+        af[a] = *(const short4_t *)&As[(wm * TM + a) * 16 + li][kk + lk];
+#pragma unroll
+      for (int b = 0; b < TN; ++b)
+        bfr[b] = *(const short4_t *)&Bs[(wn * TN + b) * 16 + li][kk + lk];
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[a], bfr[b], acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();
   }
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = row0 + (wm * TM + a) * 16 + lk + r, j = col0 + (wn * TN + b) * 16 + li;
+        if (i >= M) continue;
+        float v = acc[a][b][r];
+        if (gridDim.z > 1) {
+          work[((int64_t)blockIdx.z * M + i) * N + j] = v;
+        } else {
+          if (bias) v += bias[j];
+          float *dst = C + (int64_t)i * ldc + j;
+          *dst = accumulate ? *dst + v : v;
+        }
+      }
+}
+
+// t = t + p[0] + p[stride] + ... + p[(count - 1) stride], added in that
+// order; the loads go out 8 at a time ahead of the additions.
+__device__ __forceinline__ float ordered_sum(float t, const float *p, int64_t stride, int count) {
+  int c = 0;
+  for (; c + 8 <= count; c += 8) {
+    float v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = p[(int64_t)(c + e) * stride];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) t += v[e];
+  }
+  for (; c < count; ++c) t += p[(int64_t)c * stride];
+  return t;
+}
+
+// C[i][j] (+)= sum_z work[z][i][j] (+ bias[j]), the parts added in order.
+__global__ void gemm_splitk_sum_kernel(const float *work, int S, int M, int N, float *C,
+                                       int64_t ldc, const float *bias, int accumulate) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)M * N) return;
+  const int i = (int)(t / N), j = (int)(t % N);
+  float v = ordered_sum(0.f, work + t, (int64_t)M * N, S);
+  if (bias) v += bias[j];
+  float *dst = C + (int64_t)i * ldc + j;
+  *dst = accumulate ? *dst + v : v;
 }
 
 __device__ __forceinline__ float gelu(float z) {
@@ -148,8 +277,8 @@ __global__ void __launch_bounds__(256) colsum_part_kernel(const float *dZ, int B
   int r1 = r0 + CS_ROWS;
   if (r1 > B) r1 = B;
   float acc = 0.f;
-  if (j < ncol)
-    for (int r = r0 + w; r < r1; r += 4) acc += dZ[(int64_t)r * ld + j];
+  if (j < ncol && r0 + w < r1)
+    acc = ordered_sum(0.f, dZ + (int64_t)(r0 + w) * ld + j, 4 * ld, (r1 - r0 - w + 3) / 4);
   ws[w][lane] = acc;
   __syncthreads();
   if (w == 0 && j < ncol)
@@ -158,9 +287,7 @@ __global__ void __launch_bounds__(256) colsum_part_kernel(const float *dZ, int B
 __global__ void colsum_final_kernel(const float *part, int nrb, int ncol, float *db) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= ncol) return;
-  float t = 0.f;
-  for (int k = 0; k < nrb; ++k) t += part[(int64_t)k * ncol + j];
-  db[j] = t;
+  db[j] = ordered_sum(0.f, part + j, ncol, nrb);
 }
 
 __global__ void fill_f32_kernel(float *p, int64_t n, float v) {
@@ -223,9 +350,9 @@ __global__ void zero_u64_kernel(unsigned long long *p, int n) {
 }
 
 // AdamW on the FP32 masters; mask[i] = 0 keeps padded entries at zero.
-__global__ void adamw_kernel(float *p, const float *g, float *m, float *v, const uint8_t *mask,
-                             int64_t n, float lr, float b1, float b2, float eps, float wd,
-                             float bc1, float bc2) {
+__global__ void adamw_kernel(float *p, uint16_t *pb, const float *g, float *m, float *v,
+                             const uint8_t *mask, int64_t n, float lr, float b1, float b2,
+                             float eps, float wd, float bc1, float bc2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n || !mask[i]) return;
   const float gi = g[i];
@@ -234,7 +361,9 @@ __global__ void adamw_kernel(float *p, const float *g, float *m, float *v, const
   m[i] = mi;
   v[i] = vi;
   const float mh = mi / bc1, vh = vi / bc2;
-  p[i] = p[i] - lr * (mh / (sqrtf(vh) + eps) + wd * p[i]);
+  const float pn = p[i] - lr * (mh / (sqrtf(vh) + eps) + wd * p[i]);
+  p[i] = pn;
+  pb[i] = f2bf(pn);
 }
 
 __global__ void to_bf16_kernel(const float *x, uint16_t *y, int64_t n) {
@@ -391,11 +520,44 @@ inline unsigned nb(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t);
 
 hipError_t mlp_gemm(const uint16_t *A, int64_t a_r, int64_t a_c, const uint16_t *B, int64_t b_r,
                     int64_t b_c, float *C, int64_t ldc, int M, int N, int K, const float *bias,
-                    int accumulate, hipStream_t s) {
-  if (M % 16 || N % 16 || K % 16) return hipErrorInvalidValue;
-  const int64_t waves = (int64_t)(M / 16) * (N / 16);
-  hipLaunchKernelGGL(gemm_bf16_kernel, dim3(nb(waves * 64)), dim3(256), 0, s, A, a_r, a_c, B,
-                     b_r, b_c, C, ldc, M, N, K, bias, accumulate);
+                    int accumulate, hipStream_t s, float *work, int64_t work_len) {
+  if (M <= 0 || N <= 0 || K <= 0 || M % 16 || N % 16 || K % 16) return hipErrorInvalidValue;
+  // (64, 64) tiles where N allows, (16, 64) for a 16-row product, else
+  // (64, 16)
+  const int BN = N % 64 == 0 ? 64 : 16;
+  const int BM = BN == 64 && M == 16 ? 16 : 64;
+  const int64_t gm = (M + BM - 1) / BM, gn = N / BN;
+  if (gm > 65535) return hipErrorInvalidValue;
+  // split K (a workspace given) until about 256 blocks, each part at least
+  // two chunks of 32
+  const int chunks = (K + GBK - 1) / GBK;
+  int S = 1;
+  while (work && gm * gn * S < 256 && chunks >= 4 * S && (int64_t)2 * S * M * N <= work_len)
+    S *= 2;
+  const int cpc = (chunks + S - 1) / S;
+  // 16-byte loads when every run of 8 along the unit stride is aligned
+  auto al = [](const void *p, int64_t s1, int64_t s2) {
+    const int64_t st = s1 == 1 ? s2 : s1;
+    return ((uintptr_t)p % 16 == 0) && (st % 8 == 0);
+  };
+  const bool vec = al(A, a_r, a_c) && al(B, b_c, b_r);
+  const dim3 grid((unsigned)gn, (unsigned)gm, (unsigned)S);
+#define CHX_GEMM_LAUNCH(bm, bn)                                                                  \
+  do {                                                                                          \
+    if (vec)                                                                                    \
+      hipLaunchKernelGGL((gemm_tile_kernel<bm, bn, true>), grid, dim3(256), 0, s, A, a_r, a_c,  \
+                         B, b_r, b_c, C, ldc, M, N, K, cpc, bias, accumulate, work);            \
+    else                                                                                        \
+      hipLaunchKernelGGL((gemm_tile_kernel<bm, bn, false>), grid, dim3(256), 0, s, A, a_r, a_c, \
+                         B, b_r, b_c, C, ldc, M, N, K, cpc, bias, accumulate, work);            \
+  } while (0)
+  if (BN == 16) CHX_GEMM_LAUNCH(64, 16);
+  else if (BM == 16) CHX_GEMM_LAUNCH(16, 64);
+  else CHX_GEMM_LAUNCH(64, 64);
+#undef CHX_GEMM_LAUNCH
+  if (S > 1)
+    hipLaunchKernelGGL(gemm_splitk_sum_kernel, dim3(nb((int64_t)M * N)), dim3(256), 0, s, work, S,
+                       M, N, C, ldc, bias, accumulate);
   return hipGetLastError();
 }
 
@@ -446,11 +608,11 @@ hipError_t gate_scatter(int64_t n2, const int64_t *orbit, const int8_t *label2, 
   hipLaunchKernelGGL(gate_scatter_kernel, dim3(nb(n2)), dim3(256), 0, s, n2, orbit, label2, label);
   return hipGetLastError();
 }
-hipError_t mlp_adamw(float *p, const float *g, float *m, float *v, const uint8_t *mask, int64_t n,
-                     float lr, float b1, float b2, float eps, float wd, float bc1, float bc2,
-                     hipStream_t s) {
-  hipLaunchKernelGGL(adamw_kernel, dim3(nb(n)), dim3(256), 0, s, p, g, m, v, mask, n, lr, b1, b2,
-                     eps, wd, bc1, bc2);
+hipError_t mlp_adamw(float *p, uint16_t *pb, const float *g, float *m, float *v,
+                     const uint8_t *mask, int64_t n, float lr, float b1, float b2, float eps,
+                     float wd, float bc1, float bc2, hipStream_t s) {
+  hipLaunchKernelGGL(adamw_kernel, dim3(nb(n)), dim3(256), 0, s, p, pb, g, m, v, mask, n, lr, b1,
+                     b2, eps, wd, bc1, bc2);
   return hipGetLastError();
 }
 hipError_t mlp_to_bf16(const float *x, uint16_t *y, int64_t n, hipStream_t s) {

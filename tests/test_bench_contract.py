@@ -61,6 +61,13 @@ def test_dop853_tableau_pattern_matches_the_oracle():
     assert int((b != 0).sum()) == bench.DOP853_B_NNZ
 
 
+def test_mlp_training_flop_model():
+    # products of one row: forward 2 (6*256 + 256*256 + 256*2), the same
+    # for the weight gradients, activation gradients 2 (2*256 + 256*256)
+    assert bench.mlp_train_flops_per_row() == 135168 + 135168 + 132096
+    assert bench.mlp_train_flops_per_row(True) == 147456 + 147456 + 139264
+
+
 def test_fput_and_quartic_flop_models():
     assert bench.flops_per_step_fput(16, 16, 32, False, True, True, 10) == pytest.approx(26202.0)
     assert bench.flops_per_step_fput(8, 8, 16, False, True, True, 10) == pytest.approx(5999.6)

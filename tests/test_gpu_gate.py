@@ -118,12 +118,16 @@ def test_forward_matches_oracle(env):
     g.close()
 
 
-def test_gradient_matches_oracle(env):
+# 4104 rows: a ragged batch (not a multiple of 16; the products' K is not a
+# multiple of their 32-deep chunks) split over K; 40 rows: fewer rows than
+# one 64-row tile
+@pytest.mark.parametrize("n", [4096 + 8, 40])
+def test_gradient_matches_oracle(env, n):
     torch, P, M, O = env
-    say("case: gate gradient vs oracle")
+    say(f"case: gate gradient vs oracle, {n} rows")
     g = P.Gate(1)
     p = random_params(M, 4, scale=0.7)
-    F = random_features(5, 4096 + 8)  # ragged: not a multiple of 16
+    F = random_features(5, n)
     y = (np.random.default_rng(6).random(len(F)) < 0.4).astype(np.int8)
     y[::97] = -1  # ignored rows
     mu, istd = M.zscore_stats(F.astype(np.float64))
