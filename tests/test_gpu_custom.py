@@ -351,3 +351,71 @@ def test_custom_general_four_dof_and_lds_limit(env):
     with pytest.raises(P.ChxError, match="LDS"):
         run_gpu(env, sg, x0, None, None, integrator="dop853_adaptive", dt=0.1, T=1.0,
                 indicators=O.IND_LYAP | O.IND_SALI, n_lyap=6, rtol=1e-9, atol=1e-9)
+
+
+# any number of uncoupled oscillators written as a general field over T
+HARMONIC_N_GENERAL = r"""
+#define NQ CHX_CUSTOM_NDOF
+template <class T>
+__device__ void chx_field(const T *x, T *f, const double *prm) {
+  for (int i = 0; i < NQ; ++i) {
+    f[i] = x[NQ + i];
+    f[NQ + i] = -(prm[i] * prm[i]) * x[i];
+  }
+}
+__device__ double chx_hamiltonian(const double *x, const double *prm) {
+  double h = 0.0;
+  for (int i = 0; i < NQ; ++i)
+    h += 0.5 * (x[NQ + i] * x[NQ + i] + prm[i] * prm[i] * x[i] * x[i]);
+  return h;
+}
+"""
+
+
+# ndof 8, the largest a user system may have: the separable form with the
+# full Lyapunov set (2N = 16 vectors + the SALI pair) on Yoshida-4 and with
+# two vectors on both DOP853 solvers (the adaptive one at its 1 KB of LDS per
+# orbit); the general form with two vectors on DOP853
+@pytest.mark.parametrize("integ", ["yoshida4", "dop853", "dop853_adaptive"])
+def test_custom_quartic_eight_dof(env, integ):
+    torch, P, O = env
+    say(f"case: custom quartic N=8 (eps=0.1), {integ}, T=5")
+    so = O.quartic(8, 0.1)
+    x0 = O.quartic_ic(so, S.quartic_draws(80, 64, 8))
+    w0 = S.deviation_vectors(81, len(x0), 2, 16)
+    extra = dict(rtol=1e-10, atol=1e-10) if integ == "dop853_adaptive" else {}
+    if integ == "yoshida4":
+        ind, more = ALL, dict(gali_kmax=2, n_lyap=16)
+    else:
+        ind, more = O.IND_SALI | O.IND_LD | O.IND_ENERGY, {}
+    kw = dict(dt=0.05 if integ == "dop853_adaptive" else 0.01, T=5.0, indicators=ind,
+              **more, **extra)
+    g = run_gpu(env, P.custom(8, QUARTIC_N, params=[0.1]), x0, None, w0, integrator=integ, **kw)
+    o = O.integrate(so, x0, oracle_run(O, integ, **kw), w0=w0, threads=8)
+    assert np.array_equal(g["status"], o["status"])
+    sel = o["status"] == 0
+    if integ == "dop853_adaptive":
+        same = sel & (g["steps"][:, 0] == o["steps_accepted"]) & (
+            g["steps"][:, 1] == o["steps_rejected"])
+        assert same.sum() >= 0.99 * sel.sum()
+        sel = same
+    compare(g, o, sel, 1e-3 if integ == "dop853_adaptive" else 1e-9, f"quartic8 {integ}")
+    if integ == "yoshida4":
+        # the full spectrum of a Hamiltonian flow sums to zero
+        assert np.max(np.abs(g["lyap"][sel].sum(axis=1))) < 1e-9
+
+
+def test_custom_general_eight_dof(env):
+    torch, P, O = env
+    om = [0.6, 0.8, 1.0, 1.2, 1.4, 1.7, 2.0, 2.3]
+    say("case: general harmonic N=8, dop853, SALI + LD + energy, T=5")
+    so = O.harmonic(om)
+    rng = np.random.default_rng(82)
+    x0 = rng.uniform(-1.0, 1.0, size=(64, 16))
+    w0 = S.deviation_vectors(83, len(x0), 2, 16)
+    kw = dict(dt=0.01, T=5.0, indicators=O.IND_SALI | O.IND_LD | O.IND_ENERGY)
+    g = run_gpu(env, P.custom_general(8, HARMONIC_N_GENERAL, params=om), x0, None, w0,
+                integrator="dop853", **kw)
+    o = O.integrate(so, x0, oracle_run(O, "dop853", **kw), w0=w0, threads=8)
+    assert np.array_equal(g["status"], o["status"])
+    compare(g, o, np.ones(len(x0), bool), 1e-9, "harmonic8 general")
