@@ -2,6 +2,7 @@
 // four deviation vectors, vector rows (up to 4N vectors) otherwise.
 #include "fput_crow.h"
 #include "fput_row.h"
+#include "fput_row2.h"
 
 namespace chx {
 
@@ -30,8 +31,17 @@ hipError_t launch_n(int M, const StepArgs &a, hipStream_t s) {
   // while V N <= 32 (at most 64 doubles of vectors per lane), and for
   // N = 16 with 33..48 vectors (three slots, 96 doubles: the full Lyapunov
   // set and N GALI vectors with no slot position unused); N = 16 with more
-  // than 48 vectors takes two rows per orbit.  M <= 4N.
+  // than 48 vectors takes two rows per orbit; N = 8 with 17..24 vectors
+  // (the full Lyapunov set and N GALI vectors) puts two orbits in a row,
+  // three slots of eight positions each.  M <= 4N.
   const int V = (M + 15) / 16;
+  if constexpr (N == 8) {
+    if (M > 16 && M <= 24) {
+      const unsigned grid = (unsigned)((a.n + 7) / 8);
+      hipLaunchKernelGGL((fput_row2_kernel<8, 3>), dim3(grid), dim3(64), 0, s, a);
+      return hipGetLastError();
+    }
+  }
   if constexpr (N == 16) {
     if (V == 3) {
       const unsigned grid = (unsigned)((a.n + 3) / 4);

@@ -110,6 +110,49 @@ def test_fput16_four_n_vectors_two_rows(env):
     assert np.max(np.abs(g["lyap"].sum(axis=1))) < 1e-9
 
 
+# N = 8 with 17..24 vectors runs two orbits per row: the full Lyapunov set
+# with the SALI pair in the third slot (18 vectors, with LD and an early
+# exit), and a partial Lyapunov set (12: its second slot half full) with 8
+# GALI vectors (20)
+@pytest.mark.parametrize("case", ["lyap16_sali", "lyap12_gali8"])
+def test_fput8_two_orbits_per_row(env, case):
+    torch, P, O = env
+    N, n, T = 8, 45, 60.0
+    say(f"case: FPU N=8 two orbits per row, {case}, n={n}, T={T}")
+    so, sg = O.fput(N), P.fput(N)
+    x0 = O.fput_ic(so, S.fput_mode_draws(1400, n))
+    if case == "lyap16_sali":
+        kw = dict(dt=0.02, T=T, indicators=O.IND_LYAP | O.IND_SALI | O.IND_LD | O.IND_ENERGY,
+                  n_lyap=16)
+        w0 = S.deviation_vectors(1401, n, 2, 2 * N)
+    else:
+        kw = dict(dt=0.02, T=T, indicators=O.IND_LYAP | O.IND_GALI | O.IND_ENERGY,
+                  n_lyap=12, gali_kmax=8)
+        w0 = S.deviation_vectors(1402, n, 8, 2 * N)
+    g = run_gpu(env, sg, x0, None, w0, **kw)
+    o = O.integrate(so, x0, O.Run(**kw), w0=w0, threads=8)
+    assert np.array_equal(g["status"], o["status"])
+    se = state_err(g["x_final"], o["x_final"]).max()
+    le = np.max(np.abs(g["lyap"] - o["lyap"]))
+    say(f"  state {se:.3g} lyap {le:.3g}")
+    assert se < 1e-9 and le < 1e-6
+    assert np.max(np.abs(g["ln_growth"] - o["ln_growth"])) < 1e-6
+    if case == "lyap16_sali":
+        assert np.max(np.abs(g["lyap"].sum(axis=1))) < 1e-9
+        assert log_err(g["sali_min"], o["sali_min"], 1e-12) < 1e-6
+        assert np.max(np.abs(g["ld"] / o["ld"] - 1)) < 1e-9
+        # a threshold inside the SALI minima of these orbits (0.13 .. 1.2 by
+        # T = 60), so that some of them stop early
+        kw2 = dict(kw, early_exit=True, sali_threshold=0.34)
+        g2 = run_gpu(env, sg, x0, None, w0, **kw2)
+        o2 = O.integrate(so, x0, O.Run(**kw2), w0=w0, threads=8)
+        say("  exited:", int(np.sum(o2["status"] == O.ST_EXITED)))
+        assert np.array_equal(g2["status"], o2["status"])
+        assert np.array_equal(g2["t_end"], o2["t_end"])
+    else:
+        assert log_err(g["gali"], o["gali"], 1e-8) < 1e-6
+
+
 @pytest.mark.parametrize("N", [16, 8])
 def test_fput_sali_ld_early_exit(env, N):
     torch, P, O = env
