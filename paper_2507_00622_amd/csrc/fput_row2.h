@@ -277,8 +277,8 @@ __global__ void __launch_bounds__(64, 2) fput_row2_kernel(const StepArgs a) {
     // 0x3 writes lanes 0-7 of a row from lane j % 8, bank_mask 0xc lanes
     // 8-15 from lane 8 + j % 8), so no pivot goes through memory and no
     // wait is exposed; pivots are unrolled (the lane is an immediate).  Per
-    // pivot: dot products of every later vector with it (two partial sums
-    // per half), |w_j|^2 from the owner's own dot product, the
+    // pivot: dot products of every later vector with it (four partial
+    // sums), |w_j|^2 from the owner's own dot product, the
     // coefficients, then w_k -= (w_j . w_k / |w_j|^2) w_j.  The owner's
     // coefficient is zero, so its source registers keep their values
     // during its pass.  Ordering: each update pass writes a register that
@@ -291,10 +291,15 @@ __global__ void __launch_bounds__(64, 2) fput_row2_kernel(const StepArgs a) {
 #pragma unroll
     for (int s = 0; s < V; ++s) own2[s] = 1.0;
     constexpr int NLS_MAX = (2 * N + G - 1) / G < V ? (2 * N + G - 1) / G : V;
-    const int nls = (n_l + G - 1) / G;  // slots holding Lyapunov vectors
+    // n_l taken afresh here, so that the compiler forms the pivots'
+    // comparisons with it in each checkpoint instead of keeping sixteen of
+    // them in scalar registers through the step loop
+    int nlg = n_l;
+    asm volatile("" : "+s"(nlg));
+    const int nls = (nlg + G - 1) / G;  // slots holding Lyapunov vectors
     static_for<0, NLS_MAX>([&](auto jc) {
       constexpr int sj = decltype(jc)::value;  // the pivots' slot
-      if (sj * G < n_l) {
+      if (sj * G < nlg) {
         // slots sj..L-1 hold Lyapunov vectors (code per possible L, chosen
         // by a uniform branch)
         auto group = [&](auto lc) {
@@ -306,28 +311,28 @@ __global__ void __launch_bounds__(64, 2) fput_row2_kernel(const StepArgs a) {
             // owner's own norm
             constexpr int s1 = lj == G - 1 ? sj + 1 : sj;
             const int pj = sj * G + lj;
-            if (pj < n_l) {
+            if (pj < nlg) {
               // two wait states before the first DPP read of w[sj]
               asm volatile("s_nop 1" : "+v"(w[sj][0]), "+v"(w[sj][1]));
-              // two partial sums per vector; the first half row's pass
+              // four partial sums per vector; the first half row's pass
               // writes lanes 0-7 of them, the second's (16 or more
               // instructions later) lanes 8-15
-              double d[V][2];
+              double d[V][4];
 #pragma unroll
-              for (int s = 0; s < V; ++s) d[s][0] = d[s][1] = 0.0;
+              for (int s = 0; s < V; ++s) d[s][0] = d[s][1] = d[s][2] = d[s][3] = 0.0;
               static_for<0, D>([&](auto cc) {
                 constexpr int i = decltype(cc)::value;
 #pragma unroll
-                for (int s = s1; s < L; ++s) fmac_lo<lj>(d[s][i & 1], w[sj][i], w[s][i]);
+                for (int s = s1; s < L; ++s) fmac_lo<lj>(d[s][i & 3], w[sj][i], w[s][i]);
               });
               static_for<0, D>([&](auto cc) {
                 constexpr int i = decltype(cc)::value;
 #pragma unroll
-                for (int s = s1; s < L; ++s) fmac_hi<G + lj>(d[s][i & 1], w[sj][i], w[s][i]);
+                for (int s = s1; s < L; ++s) fmac_hi<G + lj>(d[s][i & 3], w[sj][i], w[s][i]);
               });
               double t[V];
 #pragma unroll
-              for (int s = s1; s < L; ++s) t[s] = d[s][0] + d[s][1];
+              for (int s = s1; s < L; ++s) t[s] = (d[s][0] + d[s][1]) + (d[s][2] + d[s][3]);
               if constexpr (s1 != sj) t[sj] = norm2_4<D>(w[sj]);
               // |w_j|^2: the owner's own dot product, to its group
               double r2 = t[sj];
@@ -342,7 +347,7 @@ __global__ void __launch_bounds__(64, 2) fput_row2_kernel(const StepArgs a) {
 #pragma unroll
               for (int s = s1; s < L; ++s) {
                 const int pos = s * G + c;
-                nd[s] = (pos > pj && pos < n_l) ? t[s] * ni2 : 0.0;
+                nd[s] = (pos > pj && pos < nlg) ? t[s] * ni2 : 0.0;
               }
               static_for<0, D>([&](auto cc) {
                 constexpr int i = decltype(cc)::value;
