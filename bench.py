@@ -443,7 +443,7 @@ def bench_fput(args, P, chx, torch, dev):
                                 f"dt={dt}, T={T:g}",
                     "orbits": 2 * n, "steps_per_orbit": n_steps, "steps_per_launch": spl,
                     "per_N": {str(N): {"kernel": ("chx::fput_row_kernel<16, 3, 1, 1>" if N == 16
-                                                  else "chx::fput_row2_kernel<8, 3>"),
+                                                  else "chx::fput_rowpair_kernel<8>"),
                                        "flops_per_orbit_step": v["fps"],
                                        "flops_per_orbit_step_executed": v["fps_exec"],
                                        "launch_ms": v["ms"],

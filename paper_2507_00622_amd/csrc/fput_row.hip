@@ -2,7 +2,7 @@
 // four deviation vectors, vector rows (up to 4N vectors) otherwise.
 #include "fput_crow.h"
 #include "fput_row.h"
-#include "fput_row2.h"
+#include "fput_rowpair.h"
 
 namespace chx {
 
@@ -32,13 +32,14 @@ hipError_t launch_n(int M, const StepArgs &a, hipStream_t s) {
   // N = 16 with 33..48 vectors (three slots, 96 doubles: the full Lyapunov
   // set and N GALI vectors with no slot position unused); N = 16 with more
   // than 48 vectors takes two rows per orbit; N = 8 with 17..24 vectors
-  // (the full Lyapunov set and N GALI vectors) puts two orbits in a row,
-  // three slots of eight positions each.  M <= 4N.
+  // of which at most N SALI/GALI (the full Lyapunov spectrum and N GALI
+  // vectors) puts two orbits in a row, each orbit's Lyapunov set filling one
+  // slot.  M <= 4N.
   const int V = (M + 15) / 16;
   if constexpr (N == 8) {
-    if (M > 16 && M <= 24) {
+    if (M > 16 && M <= 24 && a.m_s <= 8) {
       const unsigned grid = (unsigned)((a.n + 7) / 8);
-      hipLaunchKernelGGL((fput_row2_kernel<8, 3>), dim3(grid), dim3(64), 0, s, a);
+      hipLaunchKernelGGL((fput_rowpair_kernel<8>), dim3(grid), dim3(64), 0, s, a);
       return hipGetLastError();
     }
   }

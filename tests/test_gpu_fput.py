@@ -153,6 +153,29 @@ def test_fput8_two_orbits_per_row(env, case):
         assert log_err(g["gali"], o["gali"], 1e-8) < 1e-6
 
 
+# N = 8 with more than N SALI/GALI vectors stays on one orbit per row (two
+# slots of 16): GALI_2..2N with the full spectrum (32 vectors) and with half
+# of it (24)
+@pytest.mark.parametrize("n_lyap", [16, 8])
+def test_fput8_gali_2n_one_orbit_per_row(env, n_lyap):
+    torch, P, O = env
+    N, n, T = 8, 29, 40.0
+    say(f"case: FPU N=8 Lyapunov ({n_lyap}) + GALI_2..2N, n={n}, T={T}")
+    so, sg = O.fput(N), P.fput(N)
+    x0 = O.fput_ic(so, S.fput_mode_draws(1410, n))
+    w0 = S.deviation_vectors(1411, n, 2 * N, 2 * N)
+    kw = dict(dt=0.02, T=T, indicators=O.IND_LYAP | O.IND_GALI | O.IND_ENERGY,
+              n_lyap=n_lyap, gali_kmax=2 * N)
+    g = run_gpu(env, sg, x0, None, w0, **kw)
+    o = O.integrate(so, x0, O.Run(**kw), w0=w0, threads=8)
+    assert np.array_equal(g["status"], o["status"])
+    le = np.max(np.abs(g["lyap"] - o["lyap"]))
+    ge = log_err(g["gali"], o["gali"], 1e-8)
+    say(f"  state {state_err(g['x_final'], o['x_final']).max():.3g} lyap {le:.3g} gali {ge:.3g}")
+    assert np.max(state_err(g["x_final"], o["x_final"])) < 1e-9
+    assert le < 1e-6 and ge < 1e-6
+
+
 @pytest.mark.parametrize("N", [16, 8])
 def test_fput_sali_ld_early_exit(env, N):
     torch, P, O = env
