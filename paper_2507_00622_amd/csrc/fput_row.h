@@ -320,7 +320,12 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
     double own2[V];  // |w|^2 of this lane's slot when it was the pivot
 #pragma unroll
     for (int s = 0; s < V; ++s) own2[s] = 1.0;
-    const int nls = (n_l + 16 * R - 1) / (16 * R);  // slots holding Lyapunov vectors
+    // n_l taken afresh here, so that the compiler forms the pivots'
+    // comparisons with it in each checkpoint instead of keeping them in
+    // scalar registers through the step loop (where they spill)
+    int nlg = n_l;
+    asm volatile("" : "+s"(nlg));
+    const int nls = (nlg + 16 * R - 1) / (16 * R);  // slots holding Lyapunov vectors
     if constexpr (R == 1) {
       // One row per orbit: the pivots are read straight from their owners'
       // registers.  The dot products and the updates take component c of
@@ -350,14 +355,14 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
       constexpr int PS = B >= 4 ? 1 : 4 / B;  // partial sums per dot product
       static_for<0, NLS_MAX>([&](auto gc) {
         constexpr int sj = decltype(gc)::value;  // the pivots' slot
-        if (sj * 16 < n_l) {
+        if (sj * 16 < nlg) {
           auto group = [&](auto lc) {
             constexpr int L = decltype(lc)::value;  // slots sj..L-1 hold Lyapunov vectors
             static_for<0, 16 / B>([&](auto jc) {
               constexpr int l0 = decltype(jc)::value * B;  // the first pivot's lane
               const int j0 = sj * 16 + l0;
-              if (j0 < n_l) {
-                const int nb = n_l - j0 < B ? n_l - j0 : B;  // pivots in this round
+              if (j0 < nlg) {
+                const int nb = nlg - j0 < B ? nlg - j0 : B;  // pivots in this round
                 // two wait states before the first DPP read of w[sj]
                 asm volatile("s_nop 1" : "+v"(w[sj][0]), "+v"(w[sj][1]));
                 double d[V][B][PS];
@@ -426,7 +431,7 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
 #pragma unroll
                 for (int s = sj; s < L; ++s) {
                   const int pos = s * 16 + lane;
-                  int ne = pos < n_l ? nb : 0;
+                  int ne = pos < nlg ? nb : 0;
                   if (s == sj) ne = lane < l0 ? 0 : (lane < l0 + nb ? lane - l0 : ne);
                   double z[B], y[B];
 #pragma unroll
