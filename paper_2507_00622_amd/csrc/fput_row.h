@@ -93,6 +93,45 @@ __device__ __forceinline__ double row_sum(double s) {
   return s;
 }
 
+// Values that only checkpoints touch (SALI minimum and last value, time of
+// chaos, energy error, H0, end time, growth mantissas and exponents): in
+// registers, or (S) in LDS between checkpoints, [field][lane] of the 64
+// lanes, read and written with volatile accesses so that the compiler does
+// not carry them in registers through the step loop anyway.
+template <bool S, int V>
+struct CkptVals {
+  enum { SMIN2, SLAST2, TCH, EERR, H0, TEND, GM, ND = GM + V };
+  volatile double *d;  // LDS [ND][64] when S
+  volatile int *e;     // LDS [V][64] when S
+  double rd[S ? 1 : ND];
+  int re[S ? 1 : V];
+  int t;
+  __device__ __forceinline__ double get(int f) const {
+    if constexpr (S) return d[f * 64 + t];
+    else return rd[f];
+  }
+  __device__ __forceinline__ void set(int f, double v) {
+    if constexpr (S) d[f * 64 + t] = v;
+    else rd[f] = v;
+  }
+  __device__ __forceinline__ int gete(int s) const {
+    if constexpr (S) return e[s * 64 + t];
+    else return re[s];
+  }
+  __device__ __forceinline__ void sete(int s, int v) {
+    if constexpr (S) e[s * 64 + t] = v;
+    else re[s] = v;
+  }
+  // growth of slot s's vector by the squared norm r2
+  __device__ __forceinline__ void grow_slot(int s, double r2) {
+    double m = get(GM + s);
+    int x = gete(s);
+    grow(m, x, r2);
+    set(GM + s, m);
+    sete(s, x);
+  }
+};
+
 }  // namespace fputrow
 
 // R rows per orbit (R = 1: four orbits per wavefront; R = 2: two).  Every
@@ -102,13 +141,23 @@ __device__ __forceinline__ double row_sum(double s) {
 // pos = (s R + r) 16 + l -- the rows interleave, so the Lyapunov set (the
 // first positions) is spread over all rows of the orbit.
 // B: Gram-Schmidt pivots per round (one-row layouts).
-template <int N, int V, int R, int B = 1>
-__global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
+// STASH: N = 16 with three slots keeps the checkpoint-only values in LDS,
+// which lets two wavefronts share a SIMD (the vectors alone are 192 VGPRs).
+template <int N, int V, int R, int B = 1,
+          bool STASH = (N == 16 && V == 3 && R == 1)>
+__global__ void __launch_bounds__(64, STASH ? 2 : 1) fput_row_kernel(const StepArgs a) {
   using namespace fputrow;
   constexpr int D = 2 * N;
   constexpr int OPW = 4 / R;  // orbits per wavefront
   constexpr int CPL = (D + 15) / 16;  // pivot components per lane
   __shared__ __align__(16) double piv[R == 1 ? 1 : OPW][16][CPL];
+  using CV = CkptVals<STASH, V>;
+  __shared__ double cvd[STASH ? (int)CV::ND : 1][64];
+  __shared__ int cve[STASH ? V : 1][64];
+  CV cv;
+  cv.d = &cvd[0][0];
+  cv.e = &cve[0][0];
+  cv.t = threadIdx.x;
   const int lane = threadIdx.x & 15, row = threadIdx.x >> 4;
   const int ow = row / R, ro = row % R;
   const int64_t o = (int64_t)blockIdx.x * OPW + ow;
@@ -119,26 +168,30 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
   const int n_l = a.n_l, m_s = a.m_s, M = n_l + m_s;
   const double kk = a.prm[0], al = a.prm[1], be = a.prm[2];
 
+  // vector index in the ensemble layout of slot s, -1 = unused slot
+  auto vk_of = [&](int s) {
+    const int pos = (s * R + ro) * 16 + lane;
+    return pos < n_l ? m_s + pos : (pos < M ? pos - n_l : -1);
+  };
   double q = mass ? a.x[lane * P + oo] : 0.0;
   double p = mass ? a.x[(N + lane) * P + oo] : 0.0;
-  double w[V][D], gm[V];
-  int ge[V];
-  int vk[V];  // vector index in the ensemble layout, -1 = unused slot
+  double w[V][D];
 #pragma unroll
   for (int s = 0; s < V; ++s) {
-    const int pos = (s * R + ro) * 16 + lane;
-    vk[s] = pos < n_l ? m_s + pos : (pos < M ? pos - n_l : -1);
-    const int64_t k = vk[s] < 0 ? 0 : vk[s];
+    const int vk = vk_of(s);
+    const int64_t k = vk < 0 ? 0 : vk;
 #pragma unroll
-    for (int c = 0; c < D; ++c) w[s][c] = vk[s] < 0 ? 0.0 : a.w[(k * D + c) * P + oo];
-    gm[s] = vk[s] < 0 ? 1.0 : a.gm[k * P + oo];
-    ge[s] = vk[s] < 0 ? 0 : a.ge[k * P + oo];
+    for (int c = 0; c < D; ++c) w[s][c] = vk < 0 ? 0.0 : a.w[(k * D + c) * P + oo];
+    cv.set(CV::GM + s, vk < 0 ? 1.0 : a.gm[k * P + oo]);
+    cv.sete(s, vk < 0 ? 0 : a.ge[k * P + oo]);
   }
   double ld = a.sc[SC_LD * P + oo], gprev = a.sc[SC_GPREV * P + oo];
-  double smin2 = a.sc[SC_SALI_MIN2 * P + oo], slast2 = a.sc[SC_SALI_LAST2 * P + oo];
-  double tch = a.sc[SC_T_CHAOS * P + oo], eerr = a.sc[SC_EERR * P + oo];
-  const double H0 = a.sc[SC_H0 * P + oo];
-  double tend = a.sc[SC_T_END * P + oo];
+  cv.set(CV::SMIN2, a.sc[SC_SALI_MIN2 * P + oo]);
+  cv.set(CV::SLAST2, a.sc[SC_SALI_LAST2 * P + oo]);
+  cv.set(CV::TCH, a.sc[SC_T_CHAOS * P + oo]);
+  cv.set(CV::EERR, a.sc[SC_EERR * P + oo]);
+  cv.set(CV::H0, a.sc[SC_H0 * P + oo]);
+  cv.set(CV::TEND, a.sc[SC_T_END * P + oo]);
   int st = CHX_ORBIT_OK;
 
   const double dt = a.dt;
@@ -253,7 +306,7 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
   // Checkpoint at t; returns false when the orbit stops.  Every decision is
   // taken on values that are identical in all lanes of the orbit's rows.
   auto checkpoint = [&](double t) {
-    tend = t;
+    cv.set(CV::TEND, t);
     const bool bad = !(__builtin_isfinite(q) && __builtin_isfinite(p));
     const uint64_t bb = __ballot(bad);
     if ((bb >> (16 * row)) & 0xFFFFull) {
@@ -271,7 +324,7 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
         const double inv = rsqrt_nr(r2);
 #pragma unroll
         for (int c = 0; c < D; ++c) w[s][c] *= inv;
-        grow(gm[s], ge[s], r2);
+        cv.grow_slot(s, r2);
       }
     }
     double s2 = 0.0;
@@ -300,9 +353,9 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
         // lane 0 of the pair's row to every lane of the orbit
         s2 = __shfl(s2, (ow * R + r0) * 16, 64);
       }
-      slast2 = s2;
-      smin2 = __builtin_fmin(smin2, s2);
-      if (s2 < a.thr2 && __builtin_isnan(tch)) tch = t;
+      cv.set(CV::SLAST2, s2);
+      cv.set(CV::SMIN2, __builtin_fmin(cv.get(CV::SMIN2), s2));
+      if (s2 < a.thr2 && __builtin_isnan(cv.get(CV::TCH))) cv.set(CV::TCH, t);
     }
     // Lyapunov set: modified Gram-Schmidt in vector order.  The pivot's
     // owner stages the vector as it stands (orthogonal to the earlier
@@ -555,7 +608,7 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
     for (int s = 0; s < V; ++s) {
       if ((s * R + ro) * 16 + lane < n_l) {
         const double inv = rsqrt_nr(own2[s]);
-        grow(gm[s], ge[s], own2[s]);
+        cv.grow_slot(s, own2[s]);
 #pragma unroll
         for (int c = 0; c < D; ++c) w[s][c] *= inv;
       }
@@ -575,7 +628,7 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
       if (mass) e = __builtin_fma(0.5 * p, p, e);
       if (N == 16 && lane == 15) e += spring(dr);
       const double Hs = row_sum(e);
-      eerr = __builtin_fmax(eerr, __builtin_fabs(Hs - H0));
+      cv.set(CV::EERR, __builtin_fmax(cv.get(CV::EERR), __builtin_fabs(Hs - cv.get(CV::H0))));
     }
     if (escaped) {
       st = CHX_ORBIT_ESCAPED;
@@ -595,22 +648,23 @@ __global__ void __launch_bounds__(64) fput_row_kernel(const StepArgs a) {
     }
 #pragma unroll
     for (int s = 0; s < V; ++s) {
-      if (vk[s] >= 0) {
-        const int64_t k = vk[s];
+      const int vk = vk_of(s);
+      if (vk >= 0) {
+        const int64_t k = vk;
 #pragma unroll
         for (int c = 0; c < D; ++c) a.w[(k * D + c) * P + ob] = w[s][c];
-        a.gm[k * P + ob] = gm[s];
-        a.ge[k * P + ob] = ge[s];
+        a.gm[k * P + ob] = cv.get(CV::GM + s);
+        a.ge[k * P + ob] = cv.gete(s);
       }
     }
     if (lane == 0 && ro == 0) {
       a.sc[SC_LD * P + ob] = ld;
       a.sc[SC_GPREV * P + ob] = gprev;
-      a.sc[SC_SALI_MIN2 * P + ob] = smin2;
-      a.sc[SC_SALI_LAST2 * P + ob] = slast2;
-      a.sc[SC_T_CHAOS * P + ob] = tch;
-      a.sc[SC_EERR * P + ob] = eerr;
-      a.sc[SC_T_END * P + ob] = tend;
+      a.sc[SC_SALI_MIN2 * P + ob] = cv.get(CV::SMIN2);
+      a.sc[SC_SALI_LAST2 * P + ob] = cv.get(CV::SLAST2);
+      a.sc[SC_T_CHAOS * P + ob] = cv.get(CV::TCH);
+      a.sc[SC_EERR * P + ob] = cv.get(CV::EERR);
+      a.sc[SC_T_END * P + ob] = cv.get(CV::TEND);
       a.st[ob] = st;
     }
   };
