@@ -442,7 +442,7 @@ def bench_fput(args, P, chx, torch, dev):
                                 f"3N deviation vectors (2N Lyapunov by MGS/10 + N GALI), "
                                 f"dt={dt}, T={T:g}",
                     "orbits": 2 * n, "steps_per_orbit": n_steps, "steps_per_launch": spl,
-                    "per_N": {str(N): {"kernel": ("chx::fput_row_kernel<16, 3, 1, 1>" if N == 16
+                    "per_N": {str(N): {"kernel": ("chx::fput_row_kernel<16, 3, 1, 1, true>" if N == 16
                                                   else "chx::fput_rowpair_kernel<8>"),
                                        "flops_per_orbit_step": v["fps"],
                                        "flops_per_orbit_step_executed": v["fps_exec"],
@@ -453,7 +453,7 @@ def bench_fput(args, P, chx, torch, dev):
                               for N, v in per_n.items()}},
                 {"bound": "alu", "achieved": r["achieved"] / 1e12, "peak": PEAK_FP64 / 1e12,
                  "unit": "TFLOP/s", "frac": r["achieved"] / PEAK_FP64, "traffic": None,
-                 "kernel": "chx::fput_row_kernel<16, 3, 1, 1>", "flops_per_orbit_step": r["fps"],
+                 "kernel": "chx::fput_row_kernel<16, 3, 1, 1, true>", "flops_per_orbit_step": r["fps"],
                  "flops_per_orbit_step_executed": r["fps_exec"],
                  "launch_ms": r["ms"], "launches_timed": r["launches"]}, cpu)
 
