@@ -112,9 +112,11 @@ def test_fput16_four_n_vectors_two_rows(env):
 
 # N = 8 with 17..24 vectors runs two orbits per row: the full Lyapunov set
 # with the SALI pair in the third slot (18 vectors, with LD and an early
-# exit), and a partial Lyapunov set (12: its second slot half full) with 8
-# GALI vectors (20)
-@pytest.mark.parametrize("case", ["lyap16_sali", "lyap12_gali8"])
+# exit), a partial Lyapunov set (12: its second slot half full) with 8 GALI
+# vectors (20), and the full set with 8 GALI vectors and an escape radius
+# that stops 14 of the 45 orbits at different times (rows whose orbits stop
+# apart)
+@pytest.mark.parametrize("case", ["lyap16_sali", "lyap12_gali8", "lyap16_gali8_escape"])
 def test_fput8_two_orbits_per_row(env, case):
     torch, P, O = env
     N, n, T = 8, 45, 60.0
@@ -125,18 +127,25 @@ def test_fput8_two_orbits_per_row(env, case):
         kw = dict(dt=0.02, T=T, indicators=O.IND_LYAP | O.IND_SALI | O.IND_LD | O.IND_ENERGY,
                   n_lyap=16)
         w0 = S.deviation_vectors(1401, n, 2, 2 * N)
-    else:
+    elif case == "lyap12_gali8":
         kw = dict(dt=0.02, T=T, indicators=O.IND_LYAP | O.IND_GALI | O.IND_ENERGY,
                   n_lyap=12, gali_kmax=8)
+        w0 = S.deviation_vectors(1402, n, 8, 2 * N)
+    else:
+        kw = dict(dt=0.02, T=T, indicators=O.IND_LYAP | O.IND_GALI | O.IND_ENERGY,
+                  n_lyap=16, gali_kmax=8, escape_r2=40.0)
         w0 = S.deviation_vectors(1402, n, 8, 2 * N)
     g = run_gpu(env, sg, x0, None, w0, **kw)
     o = O.integrate(so, x0, O.Run(**kw), w0=w0, threads=8)
     assert np.array_equal(g["status"], o["status"])
+    assert np.array_equal(g["t_end"], o["t_end"])
     se = state_err(g["x_final"], o["x_final"]).max()
     le = np.max(np.abs(g["lyap"] - o["lyap"]))
-    say(f"  state {se:.3g} lyap {le:.3g}")
+    say(f"  escaped {int(np.sum(o['status'] == O.ST_ESCAPED))}, state {se:.3g} lyap {le:.3g}")
     assert se < 1e-9 and le < 1e-6
     assert np.max(np.abs(g["ln_growth"] - o["ln_growth"])) < 1e-6
+    if case == "lyap16_gali8_escape":
+        assert np.sum(o["status"] == O.ST_ESCAPED) == 14
     if case == "lyap16_sali":
         assert np.max(np.abs(g["lyap"].sum(axis=1))) < 1e-9
         assert log_err(g["sali_min"], o["sali_min"], 1e-12) < 1e-6
