@@ -85,7 +85,7 @@ struct Scratch {
 // Activations of one pass over up to B rows.
 struct Acts {
   uint16_t *X, *A1b, *A2b, *dZ3b, *dZ2b, *dZ1b;
-  float *Z1, *Z2, *Z3, *dZ3, *dA2, *dZ2, *dA1, *dZ1;
+  float *Z1, *Z2, *Z3, *dZ3, *dZ2, *dZ1;
   float *part;  // column-sum partials
   float *work;  // split-K parts of the weight gradients
   int64_t *rows;
@@ -102,10 +102,8 @@ bool alloc_acts(Scratch &S, int64_t B, bool backward, Acts *a) {
   if (backward) {
     a->dZ3 = S.get<float>(B * MLP_OUTP);
     a->dZ3b = S.get<uint16_t>(B * MLP_OUTP);
-    a->dA2 = S.get<float>(B * MLP_H);
     a->dZ2 = S.get<float>(B * MLP_H);
     a->dZ2b = S.get<uint16_t>(B * MLP_H);
-    a->dA1 = S.get<float>(B * MLP_H);
     a->dZ1 = S.get<float>(B * MLP_H);
     a->dZ1b = S.get<uint16_t>(B * MLP_H);
     a->rows = S.get<int64_t>(B);
@@ -121,14 +119,13 @@ hipError_t forward(const chx_gate *g, const Acts &a, int B, hipStream_t s) {
   const uint16_t *pb = g->pb;
   const float *p = g->p;
   hipError_t e;
+  // Z = X W + b and its GELU in BF16, from the product's epilogue
   if ((e = mlp_gemm(a.X, MLP_INP, 1, pb + MLP_W1, MLP_H, 1, a.Z1, MLP_H, B, MLP_H, MLP_INP,
-                    p + MLP_B1, 0, s)))
+                    p + MLP_B1, 0, s, nullptr, 0, EPI_GELU, a.A1b)))
     return e;
-  if ((e = mlp_gelu(a.Z1, a.A1b, (int64_t)B * MLP_H, s))) return e;
   if ((e = mlp_gemm(a.A1b, MLP_H, 1, pb + MLP_W2, MLP_H, 1, a.Z2, MLP_H, B, MLP_H, MLP_H,
-                    p + MLP_B2, 0, s)))
+                    p + MLP_B2, 0, s, nullptr, 0, EPI_GELU, a.A2b)))
     return e;
-  if ((e = mlp_gelu(a.Z2, a.A2b, (int64_t)B * MLP_H, s))) return e;
   return mlp_gemm(a.A2b, MLP_H, 1, pb + MLP_W3, MLP_OUTP, 1, a.Z3, MLP_OUTP, B, MLP_OUTP, MLP_H,
                   p + MLP_B3, 0, s);
 }
@@ -147,20 +144,19 @@ hipError_t backward(chx_gate *g, const Acts &a, int B, const int8_t *labels, con
                     B, nullptr, 0, s, a.work, MLP_SPLITK_WORK)))
     return e;
   if ((e = mlp_colsum(a.dZ3, B, MLP_OUTP, MLP_OUTP, gr + MLP_B3, a.part, s))) return e;
-  if ((e = mlp_gemm(a.dZ3b, MLP_OUTP, 1, pb + MLP_W3, 1, MLP_OUTP, a.dA2, MLP_H, B, MLP_H,
-                    MLP_OUTP, nullptr, 0, s, a.work, MLP_SPLITK_WORK)))
+  // dA2 = dZ3 W3^T, taken straight to dZ2 = dA2 GELU'(Z2) by the epilogue
+  if ((e = mlp_gemm(a.dZ3b, MLP_OUTP, 1, pb + MLP_W3, 1, MLP_OUTP, a.dZ2, MLP_H, B, MLP_H,
+                    MLP_OUTP, nullptr, 0, s, nullptr, 0, EPI_GELU_BACK, a.dZ2b, a.Z2)))
     return e;
   // layer 2
-  if ((e = mlp_gelu_back(a.dA2, a.Z2, a.dZ2, a.dZ2b, (int64_t)B * MLP_H, s))) return e;
   if ((e = mlp_gemm(a.A1b, 1, MLP_H, a.dZ2b, MLP_H, 1, gr + MLP_W2, MLP_H, MLP_H, MLP_H, B,
                     nullptr, 0, s, a.work, MLP_SPLITK_WORK)))
     return e;
   if ((e = mlp_colsum(a.dZ2, B, MLP_H, MLP_H, gr + MLP_B2, a.part, s))) return e;
-  if ((e = mlp_gemm(a.dZ2b, MLP_H, 1, pb + MLP_W2, 1, MLP_H, a.dA1, MLP_H, B, MLP_H, MLP_H,
-                    nullptr, 0, s, a.work, MLP_SPLITK_WORK)))
+  if ((e = mlp_gemm(a.dZ2b, MLP_H, 1, pb + MLP_W2, 1, MLP_H, a.dZ1, MLP_H, B, MLP_H, MLP_H,
+                    nullptr, 0, s, nullptr, 0, EPI_GELU_BACK, a.dZ1b, a.Z1)))
     return e;
   // layer 1
-  if ((e = mlp_gelu_back(a.dA1, a.Z1, a.dZ1, a.dZ1b, (int64_t)B * MLP_H, s))) return e;
   if ((e = mlp_gemm(a.X, 1, MLP_INP, a.dZ1b, MLP_H, 1, gr + MLP_W1, MLP_H, MLP_INP, MLP_H, B,
                     nullptr, 0, s, a.work, MLP_SPLITK_WORK)))
     return e;
@@ -300,8 +296,8 @@ chx_status chx_gate_train(chx_gate *g, const float *features, const int8_t *labe
       const int64_t start = b * B;
       const int64_t rows = (n - start) < B ? (n - start) : B;
       const int Bp = (int)round16(rows);
-      GCHK(mlp_batch_rows(n, start, Bp, pa, pc, a.rows, s), "batch rows");
-      GCHK(mlp_batch_input(feat, a.rows, Bp, n, g->mean, g->istd, a.X, s), "batch input");
+      GCHK(mlp_batch_rows_input(n, start, Bp, pa, pc, a.rows, feat, g->mean, g->istd, a.X, s),
+           "batch rows and input");
       GCHK(forward(g, a, Bp, s), "forward");
       GCHK(backward(g, a, Bp, lab, a.rows, n, 1.0f / (float)rows, loss + ep, s), "backward");
       g->t += 1;

@@ -23,15 +23,17 @@ constexpr int64_t MLP_NPARAM = MLP_B3 + MLP_OUTP;
 
 // C = A B (+ bias) (+ C): BF16 operands at any strides, FP32 result.
 // work (work_len floats, may be null) holds split-K partial products.
+// Epilogues (no accumulate): EPI_GELU also stores GELU(C) in BF16 to Cb;
+// EPI_GELU_BACK turns the product dA into dZ = dA GELU'(Zaux) in C and
+// stores its BF16 copy to Cb (Cb, Zaux with C's row stride).
+enum { EPI_NONE = 0, EPI_GELU = 1, EPI_GELU_BACK = 2 };
 hipError_t mlp_gemm(const uint16_t *A, int64_t a_r, int64_t a_c, const uint16_t *B, int64_t b_r,
                     int64_t b_c, float *C, int64_t ldc, int M, int N, int K, const float *bias,
-                    int accumulate, hipStream_t s, float *work = nullptr, int64_t work_len = 0);
+                    int accumulate, hipStream_t s, float *work = nullptr, int64_t work_len = 0,
+                    int epi = EPI_NONE, uint16_t *Cb = nullptr, const float *Zaux = nullptr);
 // split-K workspace of the training pass (floats): up to 16 parts of the
 // 256 x 256 weight gradient
 constexpr int64_t MLP_SPLITK_WORK = (int64_t)16 * MLP_H * MLP_H;
-hipError_t mlp_gelu(const float *Z, uint16_t *Ab, int64_t n, hipStream_t s);
-hipError_t mlp_gelu_back(const float *dA, const float *Z, float *dZ, uint16_t *dZb, int64_t n,
-                         hipStream_t s);
 hipError_t mlp_softmax_ce(const float *Z3, const int8_t *labels, const int64_t *rows, int B,
                           int64_t n_valid, float inv, float *dZ3, uint16_t *dZ3b, float *loss_sum,
                           hipStream_t s);
@@ -61,7 +63,10 @@ hipError_t mlp_feature_stats(const float *feat, int64_t n, float *mean, float *i
 hipError_t mlp_infer_out(const float *Z3, int B, float *pc, float *conf, hipStream_t s);
 hipError_t mlp_features(const double *x0, const double *ld, const double *lg, double t, int64_t n,
                         float *out, hipStream_t s);
-hipError_t mlp_batch_rows(int64_t n, int64_t start, int B, uint64_t a, uint64_t c,
-                          int64_t *rows, hipStream_t s);
+// rows of one batch of the epoch's permutation i -> (a i + c) mod n (-1 past
+// n) to rows, and their z-scored features (BF16, padded to 16) to X
+hipError_t mlp_batch_rows_input(int64_t n, int64_t start, int B, uint64_t a, uint64_t c,
+                                int64_t *rows, const float *feat, const float *mean,
+                                const float *istd, uint16_t *X, hipStream_t s);
 
 }  // namespace chx

@@ -29,31 +29,57 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+// erf(z / sqrt 2) given e = exp(-z^2 / 2): Abramowitz and Stegun 7.1.26,
+// erf(x) = 1 - (a1 t + ... + a5 t^5) exp(-x^2), t = 1 / (1 + p x) for x >= 0
+// (absolute error at most 1.5e-7), odd in x.  Free of branches, so the 16
+// activations of a lane in the product's epilogue interleave.
+__device__ __forceinline__ float erf_scaled(float z, float e) {
+  const float x = fabsf(z) * 0.70710678118654752f;
+  const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * x);
+  const float poly =
+      t * (0.254829592f +
+           t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
+  return copysignf(1.0f - poly * e, z);
+}
+__device__ __forceinline__ float gelu(float z) {
+  return 0.5f * z * (1.0f + erf_scaled(z, __expf(-0.5f * z * z)));
+}
+__device__ __forceinline__ float gelu_grad(float z) {
+  const float e = __expf(-0.5f * z * z);
+  return 0.5f * (1.0f + erf_scaled(z, e)) + z * 0.39894228040143268f * e;
+}
+
 // C[M][N] (fp32, row stride ldc) = A B (+ bias[col]) (+ C if accumulate),
 // A(i,k) = A[i*a_r + k*a_c], B(k,j) = B[k*b_r + j*b_c], both BF16; M, N, K
 // multiples of 16.  A block of 4 wavefronts computes a BM x BN tile of C,
 // (64, 64), (16, 64) or (64, 16) (rows past M are not stored).  K goes in
-// chunks of 32: the block stages the chunk of A (BM x 32) and of B
-// (32 x BN) in LDS with k contiguous (As[i][k], Bs[j][k], rows padded to 40
-// elements against bank conflicts), reading global memory along whichever
-// index has unit stride, 8 elements (16 bytes) per thread where VEC says the
-// addresses allow it; rows past M and k past K are staged as zeros.  Each
+// chunks of 64: the block stages the chunk of A (BM x 64) and of B
+// (64 x BN) in LDS with k contiguous (As[i][k], Bs[j][k], rows padded to
+// 72 elements against bank conflicts), reading global memory along
+// whichever index has unit stride, 8 elements (16 bytes) per load where VEC
+// says the addresses allow it, the next chunk's loads in flight during this
+// chunk's products; rows past M are staged as zeros, k past the end of the
+// block's K range is neither staged nor multiplied.  Each
 // wavefront takes its 16 x 16 tiles' fragments from LDS (4 consecutive k
 // per lane, one 8-byte read) and issues v_mfma_f32_16x16x16bf16_1k per tile
 // and 16 k: lane l holds A[l % 16][4 (l / 16) + e], B[4 (l / 16) + e][l % 16]
 // and, after, D[4 (l / 16) + r][l % 16].  Split K: block z of gridDim.z
 // takes chunks [z cpc, (z + 1) cpc) and, when gridDim.z > 1, writes its
 // partial tile to work[z][M][N]; a second kernel adds the parts in order of
-// z (deterministic) with the bias and the accumulation.
-constexpr int GBK = 32, GPAD = 40;
+// z (deterministic) with the bias and the accumulation.  Epilogues (no
+// split): EPI_GELU stores Z = AB + bias and its activation GELU(Z) in BF16
+// to Cb; EPI_GELU_BACK takes the product as dA and stores
+// dZ = dA GELU'(Zaux) and its BF16 copy to Cb (Zaux, Cb with C's row stride).
+constexpr int GBK = 64, GPAD = GBK + 8;
 
-template <int BM, int BN, bool VEC>
+template <int BM, int BN, bool VEC, int EPI>
 __global__ void __launch_bounds__(256) gemm_tile_kernel(const uint16_t *A, int64_t a_r,
                                                         int64_t a_c, const uint16_t *B,
                                                         int64_t b_r, int64_t b_c, float *C,
                                                         int64_t ldc, int M, int N, int K,
                                                         int cpc, const float *bias,
-                                                        int accumulate, float *work) {
+                                                        int accumulate, float *work,
+                                                        uint16_t *Cb, const float *Zaux) {
   // wavefronts: (64, 64) 2 x 2 of 2 x 2 tiles; (64, 16) 4 x 1 and (16, 64)
   // 1 x 4 of one tile
   constexpr int WGM = BM == 64 && BN == 64 ? 2 : (BM == 64 ? 4 : 1);
@@ -72,18 +98,25 @@ __global__ void __launch_bounds__(256) gemm_tile_kernel(const uint16_t *A, int64
   for (int a = 0; a < TM; ++a)
 #pragma unroll
     for (int b = 0; b < TN; ++b) acc[a][b] = (float4_t){0.f, 0.f, 0.f, 0.f};
-  // This thread's run of 8 elements of the A chunk and of the B chunk (at
-  // most one each: BM * 32 / 8 <= 256 runs).  A: (i, kk) along k when
-  // a_c == 1, else along i; B: (j, kk) along k when b_r == 1, else along j.
+  // Runs of 8 elements of the A chunk and of the B chunk, run t of A being
+  // (i, kk) along k when a_c == 1, else along i (B alike: (j, kk) along k
+  // when b_r == 1, else along j); thread tid takes runs tid, tid + 256, ...
   // M and K are multiples of 16 and runs start at multiples of 8, so a run
   // is wholly inside or wholly outside the matrix.
   constexpr int RA = BM * GBK / 8, RB = BN * GBK / 8;
+  constexpr int NA = (RA + 255) / 256, NB = (RB + 255) / 256;
   const bool a_k = a_c == 1, b_k = b_r == 1;
-  const int ai = a_k ? tid / (GBK / 8) : (tid % (BM / 8)) * 8;
-  const int ak = a_k ? (tid % (GBK / 8)) * 8 : tid / (BM / 8);
-  const int bj = b_k ? tid / (GBK / 8) : (tid % (BN / 8)) * 8;
-  const int bk = b_k ? (tid % (GBK / 8)) * 8 : tid / (BN / 8);
   const int64_t a_step = a_k ? 1 : a_r, b_step = b_k ? 1 : b_c;
+  auto run_a = [&](int q, int &i, int &k) {
+    const int t = tid + 256 * q;
+    i = a_k ? t / (GBK / 8) : (t % (BM / 8)) * 8;
+    k = a_k ? (t % (GBK / 8)) * 8 : t / (BM / 8);
+  };
+  auto run_b = [&](int q, int &j, int &k) {
+    const int t = tid + 256 * q;
+    j = b_k ? t / (GBK / 8) : (t % (BN / 8)) * 8;
+    k = b_k ? (t % (GBK / 8)) * 8 : t / (BN / 8);
+  };
   auto load_run = [](const uint16_t *src, int64_t step, bool vec) {
     uint4 v;
     if (vec && step == 1) {
@@ -95,44 +128,64 @@ __global__ void __launch_bounds__(256) gemm_tile_kernel(const uint16_t *A, int64
     }
     return v;
   };
-  auto load_a = [&](int k0) {
-    if (tid < RA && row0 + ai < M && k0 + ak < K)
-      return load_run(A + (int64_t)(row0 + ai) * a_r + (int64_t)(k0 + ak) * a_c, a_step, VEC);
-    return make_uint4(0, 0, 0, 0);
-  };
-  auto load_b = [&](int k0) {
-    if (tid < RB && k0 + bk < K)
-      return load_run(B + (int64_t)(k0 + bk) * b_r + (int64_t)(col0 + bj) * b_c, b_step, VEC);
-    return make_uint4(0, 0, 0, 0);
-  };
-  uint4 va = load_a(kbeg), vb = load_b(kbeg);
-  for (int k0 = kbeg; k0 < kend; k0 += GBK) {
-    if (tid < RA) {
-      if (a_k) {
-        *(uint4 *)&As[ai][ak] = va;
-      } else {
-        const uint16_t *h = (const uint16_t *)&va;
+  uint4 va[NA], vb[NB];
+  // every run of the chunk at k0 goes out before any is waited for
+  auto load = [&](int k0) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) As[ai + e][ak] = h[e];
+    for (int q = 0; q < NA; ++q) {
+      int i, k;
+      run_a(q, i, k);
+      va[q] = (tid + 256 * q < RA && row0 + i < M && k0 + k < kend)
+                  ? load_run(A + (int64_t)(row0 + i) * a_r + (int64_t)(k0 + k) * a_c, a_step, VEC)
+                  : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      int j, k;
+      run_b(q, j, k);
+      vb[q] = (tid + 256 * q < RB && k0 + k < kend)
+                  ? load_run(B + (int64_t)(k0 + k) * b_r + (int64_t)(col0 + j) * b_c, b_step, VEC)
+                  : make_uint4(0, 0, 0, 0);
+    }
+  };
+  load(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += GBK) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      if (tid + 256 * q >= RA) continue;
+      int i, k;
+      run_a(q, i, k);
+      if (k0 + k >= kend) continue;
+      if (a_k) {
+        *(uint4 *)&As[i][k] = va[q];
+      } else {
+        const uint16_t *h = (const uint16_t *)&va[q];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) As[i + e][k] = h[e];
       }
     }
-    if (tid < RB) {
-      if (b_k) {
-        *(uint4 *)&Bs[bj][bk] = vb;
-      } else {
-        const uint16_t *h = (const uint16_t *)&vb;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) Bs[bj + e][bk] = h[e];
+    for (int q = 0; q < NB; ++q) {
+      if (tid + 256 * q >= RB) continue;
+      int j, k;
+      run_b(q, j, k);
+      if (k0 + k >= kend) continue;
+      if (b_k) {
+        *(uint4 *)&Bs[j][k] = vb[q];
+      } else {
+        const uint16_t *h = (const uint16_t *)&vb[q];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) Bs[j + e][k] = h[e];
       }
     }
     __syncthreads();
     // the next chunk's loads go out before this chunk's products
-    if (k0 + GBK < kend) {
-      va = load_a(k0 + GBK);
-      vb = load_b(k0 + GBK);
-    }
+    if (k0 + GBK < kend) load(k0 + GBK);
+    // the products stop at the end of the staged k (a multiple of 16)
+    const int kn = min(GBK, kend - k0);
 #pragma unroll
     for (int kk = 0; kk < GBK; kk += 16) {
+      if (kk >= kn) break;
       short4_t af[TM], bfr[TN];
 #pragma unroll
       for (int a = 0; a < TM; ++a)
@@ -148,6 +201,36 @@ __global__ void __launch_bounds__(256) gemm_tile_kernel(const uint16_t *A, int64
     }
     __syncthreads();
   }
+  if (gridDim.z > 1) {
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int b = 0; b < TN; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = row0 + (wm * TM + a) * 16 + lk + r, j = col0 + (wn * TN + b) * 16 + li;
+          if (i < M) work[((int64_t)blockIdx.z * M + i) * N + j] = acc[a][b][r];
+        }
+    return;
+  }
+  // every load of the epilogue (bias, Zaux or the C accumulated onto) goes
+  // out before its first store, so one wait covers them all
+  float x[TM][TN][4];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) {
+      const int j = col0 + (wn * TN + b) * 16 + li;
+      const float bj = bias ? bias[j] : 0.f;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = row0 + (wm * TM + a) * 16 + lk + r;
+        const int64_t e = (int64_t)i * ldc + j;
+        if (bias) acc[a][b][r] += bj;
+        if constexpr (EPI == EPI_GELU_BACK) x[a][b][r] = i < M ? Zaux[e] : 0.f;
+        else if constexpr (EPI == EPI_NONE) x[a][b][r] = (accumulate && i < M) ? C[e] : 0.f;
+      }
+    }
 #pragma unroll
   for (int a = 0; a < TM; ++a)
 #pragma unroll
@@ -156,13 +239,17 @@ __global__ void __launch_bounds__(256) gemm_tile_kernel(const uint16_t *A, int64
       for (int r = 0; r < 4; ++r) {
         const int i = row0 + (wm * TM + a) * 16 + lk + r, j = col0 + (wn * TN + b) * 16 + li;
         if (i >= M) continue;
-        float v = acc[a][b][r];
-        if (gridDim.z > 1) {
-          work[((int64_t)blockIdx.z * M + i) * N + j] = v;
+        const float v = acc[a][b][r];
+        const int64_t e = (int64_t)i * ldc + j;
+        if constexpr (EPI == EPI_GELU) {
+          C[e] = v;
+          Cb[e] = f2bf(gelu(v));
+        } else if constexpr (EPI == EPI_GELU_BACK) {
+          const float g = v * gelu_grad(x[a][b][r]);
+          C[e] = g;
+          Cb[e] = f2bf(g);
         } else {
-          if (bias) v += bias[j];
-          float *dst = C + (int64_t)i * ldc + j;
-          *dst = accumulate ? *dst + v : v;
+          C[e] = accumulate ? x[a][b][r] + v : v;
         }
       }
 }
@@ -194,30 +281,6 @@ __global__ void gemm_splitk_sum_kernel(const float *work, int S, int M, int N, f
   *dst = accumulate ? *dst + v : v;
 }
 
-__device__ __forceinline__ float gelu(float z) {
-  return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
-}
-__device__ __forceinline__ float gelu_grad(float z) {
-  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
-         z * 0.39894228040143268f * expf(-0.5f * z * z);
-}
-
-// A = GELU(Z) as BF16 (and FP32 Z kept for the backward pass)
-__global__ void gelu_kernel(const float *Z, uint16_t *Ab, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) Ab[i] = f2bf(gelu(Z[i]));
-}
-
-// dZ = dA * GELU'(Z), as FP32 and BF16
-__global__ void gelu_back_kernel(const float *dA, const float *Z, float *dZ, uint16_t *dZb,
-                                 int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) {
-    const float g = dA[i] * gelu_grad(Z[i]);
-    dZ[i] = g;
-    dZb[i] = f2bf(g);
-  }
-}
 
 // Softmax cross-entropy over logits Z3[r][0..1] (row stride 16).  Row r
 // reads label labels[src], src = rows ? rows[r] : r; rows with src outside
@@ -499,13 +562,21 @@ __global__ void features_kernel(const double *x0, const double *ld, const double
 
 // Rows of one batch: positions start .. start+B-1 of the epoch's
 // permutation i -> (a i + c) mod n (a coprime with n, so it is one);
-// positions at or past n are padding (-1).
-__global__ void batch_rows_kernel(int64_t n, int64_t start, int B, uint64_t a, uint64_t c,
-                                  int64_t *rows) {
+// positions at or past n are padding (-1). Each row's z-scored features go
+// to X in the same pass.
+__global__ void batch_rows_input_kernel(int64_t n, int64_t start, int B, uint64_t a, uint64_t c,
+                                        int64_t *rows, const float *feat, const float *mean,
+                                        const float *istd, uint16_t *X) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= B) return;
   const int64_t i = start + r;
-  rows[r] = i < n ? (int64_t)((a * (uint64_t)i + c) % (uint64_t)n) : -1;
+  const int64_t src = i < n ? (int64_t)((a * (uint64_t)i + c) % (uint64_t)n) : -1;
+  rows[r] = src;
+  const bool ok = src >= 0;
+  for (int k = 0; k < MLP_INP; ++k) {
+    const float v = (ok && k < MLP_IN) ? (feat[src * MLP_IN + k] - mean[k]) * istd[k] : 0.f;
+    X[r * MLP_INP + k] = f2bf(v);
+  }
 }
 
 // p[i] *= mask[i] (keeps padded entries at zero after a load)
@@ -520,7 +591,8 @@ inline unsigned nb(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t);
 
 hipError_t mlp_gemm(const uint16_t *A, int64_t a_r, int64_t a_c, const uint16_t *B, int64_t b_r,
                     int64_t b_c, float *C, int64_t ldc, int M, int N, int K, const float *bias,
-                    int accumulate, hipStream_t s, float *work, int64_t work_len) {
+                    int accumulate, hipStream_t s, float *work, int64_t work_len, int epi,
+                    uint16_t *Cb, const float *Zaux) {
   if (M <= 0 || N <= 0 || K <= 0 || M % 16 || N % 16 || K % 16) return hipErrorInvalidValue;
   // (64, 64) tiles where N allows, (16, 64) for a 16-row product, else
   // (64, 16)
@@ -529,10 +601,14 @@ hipError_t mlp_gemm(const uint16_t *A, int64_t a_r, int64_t a_c, const uint16_t 
   const int64_t gm = (M + BM - 1) / BM, gn = N / BN;
   if (gm > 65535) return hipErrorInvalidValue;
   // split K (a workspace given) until about 256 blocks, each part at least
-  // two chunks of 32
+  // two chunks
   const int chunks = (K + GBK - 1) / GBK;
+  if (epi < EPI_NONE || epi > EPI_GELU_BACK ||
+      (epi != EPI_NONE && (!Cb || (epi == EPI_GELU_BACK && !Zaux) || accumulate)))
+    return hipErrorInvalidValue;
   int S = 1;
-  while (work && gm * gn * S < 256 && chunks >= 4 * S && (int64_t)2 * S * M * N <= work_len)
+  while (epi == EPI_NONE && work && gm * gn * S < 256 && chunks >= 4 * S &&
+         (int64_t)2 * S * M * N <= work_len)
     S *= 2;
   const int cpc = (chunks + S - 1) / S;
   // 16-byte loads when every run of 8 along the unit stride is aligned
@@ -542,34 +618,35 @@ hipError_t mlp_gemm(const uint16_t *A, int64_t a_r, int64_t a_c, const uint16_t 
   };
   const bool vec = al(A, a_r, a_c) && al(B, b_c, b_r);
   const dim3 grid((unsigned)gn, (unsigned)gm, (unsigned)S);
-#define CHX_GEMM_LAUNCH(bm, bn)                                                                  \
+#define CHX_GEMM_GO(bm, bn, v, ep)                                                               \
+  hipLaunchKernelGGL((gemm_tile_kernel<bm, bn, v, ep>), grid, dim3(256), 0, s, A, a_r, a_c, B,   \
+                     b_r, b_c, C, ldc, M, N, K, cpc, bias, accumulate, work, Cb, Zaux)
+#define CHX_GEMM_LAUNCH(bm, bn, ep)                                                              \
   do {                                                                                          \
-    if (vec)                                                                                    \
-      hipLaunchKernelGGL((gemm_tile_kernel<bm, bn, true>), grid, dim3(256), 0, s, A, a_r, a_c,  \
-                         B, b_r, b_c, C, ldc, M, N, K, cpc, bias, accumulate, work);            \
-    else                                                                                        \
-      hipLaunchKernelGGL((gemm_tile_kernel<bm, bn, false>), grid, dim3(256), 0, s, A, a_r, a_c, \
-                         B, b_r, b_c, C, ldc, M, N, K, cpc, bias, accumulate, work);            \
+    if (vec) CHX_GEMM_GO(bm, bn, true, ep);                                                     \
+    else CHX_GEMM_GO(bm, bn, false, ep);                                                        \
   } while (0)
-  if (BN == 16) CHX_GEMM_LAUNCH(64, 16);
-  else if (BM == 16) CHX_GEMM_LAUNCH(16, 64);
-  else CHX_GEMM_LAUNCH(64, 64);
+  // the activation epilogues exist for the 256-wide layers only
+  if (BN == 16) {
+    if (epi != EPI_NONE) return hipErrorInvalidValue;
+    CHX_GEMM_LAUNCH(64, 16, EPI_NONE);
+  } else if (BM == 16) {
+    if (epi == EPI_GELU) CHX_GEMM_LAUNCH(16, 64, EPI_GELU);
+    else if (epi == EPI_GELU_BACK) CHX_GEMM_LAUNCH(16, 64, EPI_GELU_BACK);
+    else CHX_GEMM_LAUNCH(16, 64, EPI_NONE);
+  } else {
+    if (epi == EPI_GELU) CHX_GEMM_LAUNCH(64, 64, EPI_GELU);
+    else if (epi == EPI_GELU_BACK) CHX_GEMM_LAUNCH(64, 64, EPI_GELU_BACK);
+    else CHX_GEMM_LAUNCH(64, 64, EPI_NONE);
+  }
 #undef CHX_GEMM_LAUNCH
+#undef CHX_GEMM_GO
   if (S > 1)
     hipLaunchKernelGGL(gemm_splitk_sum_kernel, dim3(nb((int64_t)M * N)), dim3(256), 0, s, work, S,
                        M, N, C, ldc, bias, accumulate);
   return hipGetLastError();
 }
 
-hipError_t mlp_gelu(const float *Z, uint16_t *Ab, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(gelu_kernel, dim3(nb(n)), dim3(256), 0, s, Z, Ab, n);
-  return hipGetLastError();
-}
-hipError_t mlp_gelu_back(const float *dA, const float *Z, float *dZ, uint16_t *dZb, int64_t n,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(gelu_back_kernel, dim3(nb(n)), dim3(256), 0, s, dA, Z, dZ, dZb, n);
-  return hipGetLastError();
-}
 hipError_t mlp_softmax_ce(const float *Z3, const int8_t *labels, const int64_t *rows, int B,
                           int64_t n_valid, float inv, float *dZ3, uint16_t *dZ3b, float *loss_sum,
                           hipStream_t s) {
@@ -651,9 +728,11 @@ hipError_t mlp_apply_mask(float *p, const uint8_t *mask, int64_t n, hipStream_t 
   hipLaunchKernelGGL(apply_mask_kernel, dim3(nb(n)), dim3(256), 0, s, p, mask, n);
   return hipGetLastError();
 }
-hipError_t mlp_batch_rows(int64_t n, int64_t start, int B, uint64_t a, uint64_t c,
-                          int64_t *rows, hipStream_t s) {
-  hipLaunchKernelGGL(batch_rows_kernel, dim3(nb(B)), dim3(256), 0, s, n, start, B, a, c, rows);
+hipError_t mlp_batch_rows_input(int64_t n, int64_t start, int B, uint64_t a, uint64_t c,
+                                int64_t *rows, const float *feat, const float *mean,
+                                const float *istd, uint16_t *X, hipStream_t s) {
+  hipLaunchKernelGGL(batch_rows_input_kernel, dim3(nb(B)), dim3(256), 0, s, n, start, B, a, c,
+                     rows, feat, mean, istd, X);
   return hipGetLastError();
 }
 
