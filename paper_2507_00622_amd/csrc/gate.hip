@@ -19,6 +19,7 @@ struct chx_gate {
   float *p = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
   uint8_t *mask = nullptr;
   uint16_t *pb = nullptr;   // BF16 copy of p
+  uint16_t *pbT = nullptr;  // BF16 copy of the weights, transposed
   float *mean = nullptr;    // [16] z-score mean (first 6 used)
   float *istd = nullptr;    // [16] inverse standard deviation
   double *partials = nullptr;
@@ -82,31 +83,31 @@ struct Scratch {
   }
 };
 
-// Activations of one pass over up to B rows.
+// Activations of one pass over up to B rows: inference (the products'
+// FP32 outputs Z) or training (the activation gradients).
 struct Acts {
   uint16_t *X, *A1b, *A2b, *dZ3b, *dZ2b, *dZ1b;
   float *Z1, *Z2, *Z3, *dZ3, *dZ2, *dZ1;
   float *part;  // column-sum partials
   float *work;  // split-K parts of the weight gradients
-  int64_t *rows;
 };
 
 bool alloc_acts(Scratch &S, int64_t B, bool backward, Acts *a) {
   memset(a, 0, sizeof *a);
   a->X = S.get<uint16_t>(B * MLP_INP);
-  a->Z1 = S.get<float>(B * MLP_H);
   a->A1b = S.get<uint16_t>(B * MLP_H);
-  a->Z2 = S.get<float>(B * MLP_H);
   a->A2b = S.get<uint16_t>(B * MLP_H);
-  a->Z3 = S.get<float>(B * MLP_OUTP);
-  if (backward) {
+  if (!backward) {
+    a->Z1 = S.get<float>(B * MLP_H);
+    a->Z2 = S.get<float>(B * MLP_H);
+    a->Z3 = S.get<float>(B * MLP_OUTP);
+  } else {
     a->dZ3 = S.get<float>(B * MLP_OUTP);
     a->dZ3b = S.get<uint16_t>(B * MLP_OUTP);
     a->dZ2 = S.get<float>(B * MLP_H);
     a->dZ2b = S.get<uint16_t>(B * MLP_H);
     a->dZ1 = S.get<float>(B * MLP_H);
     a->dZ1b = S.get<uint16_t>(B * MLP_H);
-    a->rows = S.get<int64_t>(B);
     a->part = S.get<float>((size_t)mlp_colsum_blocks((int)B) * MLP_H);
     a->work = S.get<float>(MLP_SPLITK_WORK);
   }
@@ -130,32 +131,51 @@ hipError_t forward(const chx_gate *g, const Acts &a, int B, hipStream_t s) {
                   p + MLP_B3, 0, s);
 }
 
-// Loss and gradient of one batch into g->g; rows (or identity) pick the
-// labels; inv = 1 / (rows in the batch mean).
-hipError_t backward(chx_gate *g, const Acts &a, int B, const int8_t *labels, const int64_t *rows,
-                    int64_t n_valid, float inv, float *loss_sum, hipStream_t s) {
-  const uint16_t *pb = g->pb;
+// Loss and gradient of one batch of B rows (multiple of 16) into g->g: the
+// rows at positions start .. start + B - 1 of the permutation
+// i -> (pa i + pc) mod n (padding at or past n) and their labels; inv = 1 /
+// (rows in the batch mean).  One launch does the rows' forward and
+// backward passes; the weight gradients are products over the batch's rows
+// and the bias gradients column sums.
+hipError_t batch_grad(chx_gate *g, const Acts &a, int B, const float *feat, const int8_t *labels,
+                      int64_t n, int64_t start, uint64_t pa, uint64_t pc, float inv,
+                      float *loss_sum, hipStream_t s) {
+  MlpRowsArgs r;
+  r.n = n;
+  r.start = start;
+  r.a = pa;
+  r.c = pc;
+  r.feat = feat;
+  r.mean = g->mean;
+  r.istd = g->istd;
+  r.labels = labels;
+  r.inv = inv;
+  r.p = g->p;
+  r.pb = g->pb;
+  r.pbT = g->pbT;
+  r.X = a.X;
+  r.A1b = a.A1b;
+  r.A2b = a.A2b;
+  r.dZ3b = a.dZ3b;
+  r.dZ2b = a.dZ2b;
+  r.dZ1b = a.dZ1b;
+  r.dZ3 = a.dZ3;
+  r.dZ2 = a.dZ2;
+  r.dZ1 = a.dZ1;
+  r.loss_sum = loss_sum;
   float *gr = g->g;
   hipError_t e;
-  if ((e = mlp_softmax_ce(a.Z3, labels, rows, B, n_valid, inv, a.dZ3, a.dZ3b, loss_sum, s)))
-    return e;
+  if ((e = mlp_train_rows(r, B, s))) return e;
   // layer 3
   if ((e = mlp_gemm(a.A2b, 1, MLP_H, a.dZ3b, MLP_OUTP, 1, gr + MLP_W3, MLP_OUTP, MLP_H, MLP_OUTP,
                     B, nullptr, 0, s, a.work, MLP_SPLITK_WORK)))
     return e;
   if ((e = mlp_colsum(a.dZ3, B, MLP_OUTP, MLP_OUTP, gr + MLP_B3, a.part, s))) return e;
-  // dA2 = dZ3 W3^T, taken straight to dZ2 = dA2 GELU'(Z2) by the epilogue
-  if ((e = mlp_gemm(a.dZ3b, MLP_OUTP, 1, pb + MLP_W3, 1, MLP_OUTP, a.dZ2, MLP_H, B, MLP_H,
-                    MLP_OUTP, nullptr, 0, s, nullptr, 0, EPI_GELU_BACK, a.dZ2b, a.Z2)))
-    return e;
   // layer 2
   if ((e = mlp_gemm(a.A1b, 1, MLP_H, a.dZ2b, MLP_H, 1, gr + MLP_W2, MLP_H, MLP_H, MLP_H, B,
                     nullptr, 0, s, a.work, MLP_SPLITK_WORK)))
     return e;
   if ((e = mlp_colsum(a.dZ2, B, MLP_H, MLP_H, gr + MLP_B2, a.part, s))) return e;
-  if ((e = mlp_gemm(a.dZ2b, MLP_H, 1, pb + MLP_W2, 1, MLP_H, a.dZ1, MLP_H, B, MLP_H, MLP_H,
-                    nullptr, 0, s, nullptr, 0, EPI_GELU_BACK, a.dZ1b, a.Z1)))
-    return e;
   // layer 1
   if ((e = mlp_gemm(a.X, 1, MLP_INP, a.dZ1b, MLP_H, 1, gr + MLP_W1, MLP_H, MLP_INP, MLP_H, B,
                     nullptr, 0, s, a.work, MLP_SPLITK_WORK)))
@@ -217,6 +237,7 @@ chx_status chx_gate_create(uint64_t seed, chx_gate **out) {
   al(&g->g, sizeof(float) * MLP_NPARAM);
   al(&g->mask, MLP_NPARAM);
   al(&g->pb, sizeof(uint16_t) * MLP_NPARAM);
+  al(&g->pbT, sizeof(uint16_t) * MLP_NPARAM);
   al(&g->mean, sizeof(float) * 16);
   al(&g->istd, sizeof(float) * 16);
   al(&g->partials, sizeof(double) * MLP_STAT_BLOCKS * 2 * MLP_IN);
@@ -226,7 +247,7 @@ chx_status chx_gate_create(uint64_t seed, chx_gate **out) {
   if (e == hipSuccess) e = mlp_fill(g->g, MLP_NPARAM, 0.f, nullptr);
   if (e == hipSuccess) e = mlp_fill(g->mean, 16, 0.f, nullptr);
   if (e == hipSuccess) e = mlp_fill(g->istd, 16, 1.f, nullptr);
-  if (e == hipSuccess) e = mlp_to_bf16(g->p, g->pb, MLP_NPARAM, nullptr);
+  if (e == hipSuccess) e = mlp_weights_bf16(g->p, g->pb, g->pbT, nullptr);
   if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
   if (e != hipSuccess) {
     chx_gate_destroy(g);
@@ -240,7 +261,8 @@ void chx_gate_destroy(chx_gate *g) {
   if (!g) return;
   (void)hipDeviceSynchronize();
   for (void *p : {(void *)g->p, (void *)g->m, (void *)g->v, (void *)g->g, (void *)g->mask,
-                  (void *)g->pb, (void *)g->mean, (void *)g->istd, (void *)g->partials})
+                  (void *)g->pb, (void *)g->pbT, (void *)g->mean, (void *)g->istd,
+                  (void *)g->partials})
     if (p) (void)hipFree(p);
   delete g;
 }
@@ -285,7 +307,7 @@ chx_status chx_gate_train(chx_gate *g, const float *features, const int8_t *labe
   GCHK(mlp_fill(loss, c.epochs, 0.f, s), "clear loss");
   const int64_t nbatch = (n + B - 1) / B;
   // the BF16 copy of the weights; each AdamW step refreshes it
-  GCHK(mlp_to_bf16(g->p, g->pb, MLP_NPARAM, s), "weights to bf16");
+  GCHK(mlp_weights_bf16(g->p, g->pb, g->pbT, s), "weights to bf16");
   for (int ep = 0; ep < c.epochs; ++ep) {
     // epoch permutation i -> (pa i + pc) mod n with pa coprime to n
     const uint64_t key = mix64(c.seed ^ mix64(0x6a7e0000ull + (uint64_t)ep));
@@ -296,14 +318,13 @@ chx_status chx_gate_train(chx_gate *g, const float *features, const int8_t *labe
       const int64_t start = b * B;
       const int64_t rows = (n - start) < B ? (n - start) : B;
       const int Bp = (int)round16(rows);
-      GCHK(mlp_batch_rows_input(n, start, Bp, pa, pc, a.rows, feat, g->mean, g->istd, a.X, s),
-           "batch rows and input");
-      GCHK(forward(g, a, Bp, s), "forward");
-      GCHK(backward(g, a, Bp, lab, a.rows, n, 1.0f / (float)rows, loss + ep, s), "backward");
+      GCHK(batch_grad(g, a, Bp, feat, lab, n, start, pa, pc, 1.0f / (float)rows, loss + ep, s),
+           "batch gradient");
       g->t += 1;
       const double bc1 = 1.0 - pow((double)c.beta1, (double)g->t);
       const double bc2 = 1.0 - pow((double)c.beta2, (double)g->t);
-      GCHK(mlp_adamw(g->p, g->pb, g->g, g->m, g->v, g->mask, MLP_NPARAM, c.lr, c.beta1, c.beta2,
+      GCHK(mlp_adamw(g->p, g->pb, g->pbT, g->g, g->m, g->v, g->mask, MLP_NPARAM, c.lr, c.beta1,
+                     c.beta2,
                      c.eps, c.weight_decay, (float)bc1, (float)bc2, s),
            "AdamW");
     }
@@ -335,9 +356,7 @@ chx_status chx_gate_grad(chx_gate *g, const float *features, const int8_t *label
   if (!alloc_acts(S, Bp, true, &a)) return dev_fail(S.err, "allocate buffers");
   GCHK(mlp_fill(loss, 1, 0.f, s), "clear loss");
   GCHK(mlp_fill(g->g, MLP_NPARAM, 0.f, s), "clear gradient");
-  GCHK(mlp_batch_input(feat, nullptr, Bp, n, g->mean, g->istd, a.X, s), "input");
-  GCHK(forward(g, a, Bp, s), "forward");
-  GCHK(backward(g, a, Bp, lab, nullptr, n, 1.0f / (float)n, loss, s), "backward");
+  GCHK(batch_grad(g, a, Bp, feat, lab, n, 0, 1, 0, 1.0f / (float)n, loss, s), "gradient");
   float hl = 0.f;
   GCHK(hipMemcpyAsync(&hl, loss, sizeof hl, hipMemcpyDeviceToHost, s), "read loss");
   if (grad_out)
@@ -394,7 +413,7 @@ chx_status chx_gate_set(chx_gate *g, const float *params, const float *mean, con
     GCHK(mlp_apply_mask(g->p, g->mask, MLP_NPARAM, nullptr), "mask params");
     GCHK(mlp_fill(g->m, MLP_NPARAM, 0.f, nullptr), "clear moments");
     GCHK(mlp_fill(g->v, MLP_NPARAM, 0.f, nullptr), "clear moments");
-    GCHK(mlp_to_bf16(g->p, g->pb, MLP_NPARAM, nullptr), "weights to bf16");
+    GCHK(mlp_weights_bf16(g->p, g->pb, g->pbT, nullptr), "weights to bf16");
     g->t = 0;
   }
   if ((mean == nullptr) != (istd == nullptr))

@@ -34,9 +34,24 @@ hipError_t mlp_gemm(const uint16_t *A, int64_t a_r, int64_t a_c, const uint16_t 
 // split-K workspace of the training pass (floats): up to 16 parts of the
 // 256 x 256 weight gradient
 constexpr int64_t MLP_SPLITK_WORK = (int64_t)16 * MLP_H * MLP_H;
-hipError_t mlp_softmax_ce(const float *Z3, const int8_t *labels, const int64_t *rows, int B,
-                          int64_t n_valid, float inv, float *dZ3, uint16_t *dZ3b, float *loss_sum,
-                          hipStream_t s);
+// The row-local part of a training batch of B rows (multiple of 16): rows
+// (a i + c) mod n of the batch positions start + i (-1 at or past n), their
+// z-scored inputs, the forward pass, softmax cross-entropy against labels
+// (gradient scaled by inv, loss added to loss_sum) and the activation
+// gradients; A1, A2, dZ3, dZ2, dZ1 (and X) are left for the weight
+// gradients.  pbT: the weights' transposed BF16 copy (mlp_weights_bf16).
+struct MlpRowsArgs {
+  int64_t n, start;
+  uint64_t a, c;
+  const float *feat, *mean, *istd;
+  const int8_t *labels;
+  float inv;
+  const float *p;
+  const uint16_t *pb, *pbT;
+  uint16_t *X, *A1b, *A2b, *dZ3b, *dZ2b, *dZ1b;
+  float *dZ3, *dZ2, *dZ1, *loss_sum;
+};
+hipError_t mlp_train_rows(const MlpRowsArgs &r, int B, hipStream_t s);
 hipError_t mlp_apply_mask(float *p, const uint8_t *mask, int64_t n, hipStream_t s);
 // column sums of a B x ncol matrix; part holds mlp_colsum_blocks(B) * ncol floats
 int mlp_colsum_blocks(int B);
@@ -50,11 +65,14 @@ hipError_t gate_select(int64_t n, const int *status, const int8_t *label1, const
 hipError_t gate_scatter(int64_t n2, const int64_t *orbit, const int8_t *label2, int8_t *label,
                         hipStream_t s);
 // AdamW on the FP32 masters p (entries with mask set); pb receives their
-// BF16 copies.
-hipError_t mlp_adamw(float *p, uint16_t *pb, const float *g, float *m, float *v,
+// BF16 copies and pbT the weights' transposed BF16 copies.
+hipError_t mlp_adamw(float *p, uint16_t *pb, uint16_t *pbT, const float *g, float *m, float *v,
                      const uint8_t *mask, int64_t n, float lr, float b1, float b2, float eps,
                      float wd, float bc1, float bc2, hipStream_t s);
-hipError_t mlp_to_bf16(const float *x, uint16_t *y, int64_t n, hipStream_t s);
+// pb = BF16 of all MLP_NPARAM parameters, pbT = BF16 of the weights
+// transposed (W1T[256][16], W2T[256][256], W3T[16][256] at the offsets of
+// W1, W2, W3)
+hipError_t mlp_weights_bf16(const float *p, uint16_t *pb, uint16_t *pbT, hipStream_t s);
 hipError_t mlp_batch_input(const float *feat, const int64_t *rows, int B, int64_t n_valid,
                            const float *mean, const float *istd, uint16_t *X, hipStream_t s);
 hipError_t mlp_init_params(float *p, uint8_t *mask, uint64_t seed, hipStream_t s);
@@ -63,10 +81,5 @@ hipError_t mlp_feature_stats(const float *feat, int64_t n, float *mean, float *i
 hipError_t mlp_infer_out(const float *Z3, int B, float *pc, float *conf, hipStream_t s);
 hipError_t mlp_features(const double *x0, const double *ld, const double *lg, double t, int64_t n,
                         float *out, hipStream_t s);
-// rows of one batch of the epoch's permutation i -> (a i + c) mod n (-1 past
-// n) to rows, and their z-scored features (BF16, padded to 16) to X
-hipError_t mlp_batch_rows_input(int64_t n, int64_t start, int B, uint64_t a, uint64_t c,
-                                int64_t *rows, const float *feat, const float *mean,
-                                const float *istd, uint16_t *X, hipStream_t s);
 
 }  // namespace chx

@@ -282,46 +282,222 @@ __global__ void gemm_splitk_sum_kernel(const float *work, int S, int M, int N, f
 }
 
 
-// Softmax cross-entropy over logits Z3[r][0..1] (row stride 16).  Row r
-// reads label labels[src], src = rows ? rows[r] : r; rows with src outside
-// [0, n_valid) are padding.  Labels other than 0 and 1, and padding rows,
-// contribute neither loss nor gradient.  Writes the loss sum (atomic) and
-// dZ3 = (softmax - onehot) * inv in columns 0..1 (zero elsewhere), FP32 and
-// BF16.
-__global__ void softmax_ce_kernel(const float *Z3, const int8_t *labels, const int64_t *rows,
-                                  int B, int64_t n_valid, float inv, float *dZ3,
-                                  uint16_t *dZ3b, float *loss_sum) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  float l = 0.f;
-  if (r < B) {
-    const int64_t src = rows ? rows[r] : r;
-    const int y = (src >= 0 && src < n_valid) ? (int)labels[src] : -1;
-    float g0 = 0.f, g1 = 0.f;
-    if (y == 0 || y == 1) {
-      const float a = Z3[r * 16 + 0], b = Z3[r * 16 + 1];
-      const float m = fmaxf(a, b);
-      const float ea = expf(a - m), eb = expf(b - m), s = ea + eb;
-      const float pa = ea / s, pb = eb / s;
-      // -log softmax_y = log(s) - (z_y - m)
-      l = logf(s) - ((y ? b : a) - m);
-      g0 = (pa - (y == 0 ? 1.f : 0.f)) * inv;
-      g1 = (pb - (y == 1 ? 1.f : 0.f)) * inv;
-    }
-    for (int c = 0; c < 16; ++c) {
-      const float g = c == 0 ? g0 : (c == 1 ? g1 : 0.f);
-      dZ3[r * 16 + c] = g;
-      dZ3b[r * 16 + c] = f2bf(g);
+// Position of weight entry i in the transposed BF16 weights (W1T[256][16],
+// W2T[256][256], W3T[16][256], at the offsets of W1, W2, W3); -1 for biases.
+__device__ __forceinline__ int64_t mlp_tpos(int64_t i) {
+  if (i < MLP_B1) return MLP_W1 + (i % MLP_H) * MLP_INP + i / MLP_H;
+  if (i >= MLP_W2 && i < MLP_B2) {
+    const int64_t o = i - MLP_W2;
+    return MLP_W2 + (o % MLP_H) * MLP_H + o / MLP_H;
+  }
+  if (i >= MLP_W3 && i < MLP_B3) {
+    const int64_t o = i - MLP_W3;
+    return MLP_W3 + (o % MLP_OUTP) * MLP_H + o / MLP_OUTP;
+  }
+  return -1;
+}
+
+// The row-local part of one training batch, 16 rows per block of 4
+// wavefronts (the weight gradients, sums over all rows, follow as products):
+//   rows: batch position i -> (a i + c) mod n (-1 at or past n), z-scored
+//     BF16 inputs X;
+//   Z1 = X W1 + b1, A1 = GELU(Z1); Z2 = A1 W2 + b2, A2 = GELU(Z2);
+//   Z3 = A2 W3 + b3; softmax cross-entropy on the two logits: dZ3 =
+//     (softmax - onehot(label)) inv, the loss summed into loss_sum (rows
+//     without a label 0 or 1 contribute nothing);
+//   dZ2 = (dZ3 W3^T) GELU'(Z2); dZ1 = (dZ2 W2^T) GELU'(Z1).
+// Wavefront w computes columns 64w .. 64w + 63 of the 256-wide layers (four
+// 16 x 16 tiles) and keeps Z1, Z2 in registers; the activation entering
+// each product waits in LDS (16 x 256 BF16).  The forward products read
+// the transposed BF16 weights WT, the backward ones the weights W, so that
+// each lane's MFMA operand (4 consecutive k of one column) is one 8-byte
+// load; the MFMAs run over k in ascending order as in gemm_tile_kernel, so
+// the products equal those of separate gemm_tile_kernel launches bit for
+// bit.  The logits and the softmax are the first wavefront's.  Outputs for
+// the weight gradients: X, A1, A2 and dZ3, dZ2, dZ1 (FP32 and BF16),
+// row-major.
+constexpr int TR_LD = MLP_H + 8;  // LDS row of a 256-wide BF16 activation
+__global__ void __launch_bounds__(256) train_rows_kernel(const MlpRowsArgs t) {
+  __shared__ __align__(16) uint16_t Xs[16][24];
+  __shared__ __align__(16) uint16_t Gs[16][24];
+  __shared__ __align__(16) uint16_t As[16][TR_LD];
+  __shared__ float Zs[16][17];
+  __shared__ int64_t srcs[16];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lq = lane >> 4;
+  const int64_t r0 = (int64_t)blockIdx.x * 16;
+  const int cw = wave * 64;
+  const float4_t zero = {0.f, 0.f, 0.f, 0.f};
+  // the weight operands do not depend on the rows: W2's and W3's go out
+  // first, W2's backward ones once the forward product is done, each in
+  // flight under the work before its product
+  short4_t wf[MLP_H / 16][4], w3f[MLP_H / 16], w3b[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+    w3b[b] = *(const short4_t *)&t.pb[MLP_W3 + (int64_t)(cw + 16 * b + li) * MLP_OUTP + 4 * lq];
+#pragma unroll
+  for (int ks = 0; ks < MLP_H / 16; ++ks) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      wf[ks][b] = *(const short4_t *)&t.pbT[MLP_W2 + (int64_t)(cw + 16 * b + li) * MLP_H +
+                                            16 * ks + 4 * lq];
+    w3f[ks] = *(const short4_t *)&t.pbT[MLP_W3 + (int64_t)li * MLP_H + 16 * ks + 4 * lq];
+  }
+  {
+    const int i = tid >> 4, k = tid & 15;
+    const int64_t pos = t.start + r0 + i;
+    const int64_t src =
+        pos < t.n ? (int64_t)((t.a * (uint64_t)pos + t.c) % (uint64_t)t.n) : -1;
+    if (k == 0) srcs[i] = src;
+    const float v =
+        (src >= 0 && k < MLP_IN) ? (t.feat[src * MLP_IN + k] - t.mean[k]) * t.istd[k] : 0.f;
+    const uint16_t h = f2bf(v);
+    Xs[i][k] = h;
+    t.X[(r0 + i) * MLP_INP + k] = h;
+  }
+  __syncthreads();
+  // layer 1 (one k-step)
+  float4_t z1[4], z2[4];
+  {
+    const short4_t x = *(const short4_t *)&Xs[li][4 * lq];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int j = cw + 16 * b + li;
+      const short4_t w = *(const short4_t *)&t.pbT[MLP_W1 + (int64_t)j * MLP_INP + 4 * lq];
+      z1[b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, w, zero, 0, 0, 0);
     }
   }
-  // block reduction of the loss
-  __shared__ float part[4];
-  for (int off = 32; off > 0; off >>= 1) l += __shfl_down(l, off, 64);
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = l;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int j = cw + 16 * b + li;
+    const float bj = t.p[MLP_B1 + j];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 4 * lq + r;
+      z1[b][r] += bj;
+      const uint16_t h = f2bf(gelu(z1[b][r]));
+      As[i][j] = h;
+      t.A1b[(r0 + i) * MLP_H + j] = h;
+    }
+  }
   __syncthreads();
-  if (threadIdx.x == 0 && loss_sum) {
-    float t = 0.f;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += part[w];
-    atomicAdd(loss_sum, t);
+  // layer 2
+#pragma unroll
+  for (int b = 0; b < 4; ++b) z2[b] = zero;
+#pragma unroll
+  for (int ks = 0; ks < MLP_H / 16; ++ks) {
+    const short4_t x = *(const short4_t *)&As[li][16 * ks + 4 * lq];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      z2[b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, wf[ks][b], z2[b], 0, 0, 0);
+  }
+#pragma unroll
+  for (int ks = 0; ks < MLP_H / 16; ++ks)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      wf[ks][b] = *(const short4_t *)&t.pb[MLP_W2 + (int64_t)(cw + 16 * b + li) * MLP_H +
+                                           16 * ks + 4 * lq];
+  uint16_t h2[4][4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int j = cw + 16 * b + li;
+    const float bj = t.p[MLP_B2 + j];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      z2[b][r] += bj;
+      h2[b][r] = f2bf(gelu(z2[b][r]));
+      t.A2b[(r0 + 4 * lq + r) * MLP_H + j] = h2[b][r];
+    }
+  }
+  __syncthreads();  // every wavefront has read A1
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) As[4 * lq + r][cw + 16 * b + li] = h2[b][r];
+  __syncthreads();
+  // logits (first wavefront)
+  if (wave == 0) {
+    float4_t z3 = zero;
+#pragma unroll
+    for (int ks = 0; ks < MLP_H / 16; ++ks) {
+      const short4_t x = *(const short4_t *)&As[li][16 * ks + 4 * lq];
+      z3 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, w3f[ks], z3, 0, 0, 0);
+    }
+    const float bj = t.p[MLP_B3 + li];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Zs[4 * lq + r][li] = z3[r] + bj;
+  }
+  __syncthreads();
+  // softmax cross-entropy, one lane per row (first wavefront)
+  if (wave == 0) {
+    float l = 0.f;
+    if (lane < 16) {
+      const int i = lane;
+      const int64_t src = srcs[i];
+      const int y = (src >= 0 && src < t.n) ? (int)t.labels[src] : -1;
+      float g0 = 0.f, g1 = 0.f;
+      if (y == 0 || y == 1) {
+        const float za = Zs[i][0], zb = Zs[i][1];
+        const float m = fmaxf(za, zb);
+        const float ea = expf(za - m), eb = expf(zb - m), s = ea + eb;
+        const float pa = ea / s, pb = eb / s;
+        // -log softmax_y = log(s) - (z_y - m)
+        l = logf(s) - ((y ? zb : za) - m);
+        g0 = (pa - (y == 0 ? 1.f : 0.f)) * t.inv;
+        g1 = (pb - (y == 1 ? 1.f : 0.f)) * t.inv;
+      }
+      for (int c = 0; c < MLP_OUTP; ++c) {
+        const float g = c == 0 ? g0 : (c == 1 ? g1 : 0.f);
+        const uint16_t h = f2bf(g);
+        t.dZ3[(r0 + i) * MLP_OUTP + c] = g;
+        t.dZ3b[(r0 + i) * MLP_OUTP + c] = h;
+        Gs[i][c] = h;
+      }
+    }
+    for (int off = 8; off > 0; off >>= 1) l += __shfl_down(l, off, 64);
+    if (lane == 0 && t.loss_sum) atomicAdd(t.loss_sum, l);
+  }
+  __syncthreads();
+  // dZ2 = (dZ3 W3^T) GELU'(Z2) (one k-step); its BF16 copy replaces A2
+  {
+    const short4_t x = *(const short4_t *)&Gs[li][4 * lq];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int j = cw + 16 * b + li;
+      const float4_t d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, w3b[b], zero, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 4 * lq + r;
+        const float g = d[r] * gelu_grad(z2[b][r]);
+        const uint16_t h = f2bf(g);
+        t.dZ2[(r0 + i) * MLP_H + j] = g;
+        t.dZ2b[(r0 + i) * MLP_H + j] = h;
+        As[i][j] = h;
+      }
+    }
+  }
+  __syncthreads();
+  // dZ1 = (dZ2 W2^T) GELU'(Z1)
+  float4_t d1[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) d1[b] = zero;
+#pragma unroll
+  for (int ks = 0; ks < MLP_H / 16; ++ks) {
+    const short4_t x = *(const short4_t *)&As[li][16 * ks + 4 * lq];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      d1[b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, wf[ks][b], d1[b], 0, 0, 0);
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int j = cw + 16 * b + li;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 4 * lq + r;
+      const float g = d1[b][r] * gelu_grad(z1[b][r]);
+      t.dZ1[(r0 + i) * MLP_H + j] = g;
+      t.dZ1b[(r0 + i) * MLP_H + j] = f2bf(g);
+    }
   }
 }
 
@@ -413,9 +589,9 @@ __global__ void zero_u64_kernel(unsigned long long *p, int n) {
 }
 
 // AdamW on the FP32 masters; mask[i] = 0 keeps padded entries at zero.
-__global__ void adamw_kernel(float *p, uint16_t *pb, const float *g, float *m, float *v,
-                             const uint8_t *mask, int64_t n, float lr, float b1, float b2,
-                             float eps, float wd, float bc1, float bc2) {
+__global__ void adamw_kernel(float *p, uint16_t *pb, uint16_t *pbT, const float *g, float *m,
+                             float *v, const uint8_t *mask, int64_t n, float lr, float b1,
+                             float b2, float eps, float wd, float bc1, float bc2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n || !mask[i]) return;
   const float gi = g[i];
@@ -426,12 +602,21 @@ __global__ void adamw_kernel(float *p, uint16_t *pb, const float *g, float *m, f
   const float mh = mi / bc1, vh = vi / bc2;
   const float pn = p[i] - lr * (mh / (sqrtf(vh) + eps) + wd * p[i]);
   p[i] = pn;
-  pb[i] = f2bf(pn);
+  const uint16_t h = f2bf(pn);
+  pb[i] = h;
+  const int64_t ti = mlp_tpos(i);
+  if (ti >= 0) pbT[ti] = h;
 }
 
-__global__ void to_bf16_kernel(const float *x, uint16_t *y, int64_t n) {
+// BF16 copies of the parameters: pb in their own layout, pbT the weights
+// transposed
+__global__ void weights_bf16_kernel(const float *p, uint16_t *pb, uint16_t *pbT) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = f2bf(x[i]);
+  if (i >= MLP_NPARAM) return;
+  const uint16_t h = f2bf(p[i]);
+  pb[i] = h;
+  const int64_t ti = mlp_tpos(i);
+  if (ti >= 0) pbT[ti] = h;
 }
 
 // X[r][0..15] = BF16 of the z-scored features of row rows[r] (zero pad;
@@ -560,24 +745,6 @@ __global__ void features_kernel(const double *x0, const double *ld, const double
   out[i * 6 + 5] = (float)(lg[i * 2 + 1] / t);
 }
 
-// Rows of one batch: positions start .. start+B-1 of the epoch's
-// permutation i -> (a i + c) mod n (a coprime with n, so it is one);
-// positions at or past n are padding (-1). Each row's z-scored features go
-// to X in the same pass.
-__global__ void batch_rows_input_kernel(int64_t n, int64_t start, int B, uint64_t a, uint64_t c,
-                                        int64_t *rows, const float *feat, const float *mean,
-                                        const float *istd, uint16_t *X) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= B) return;
-  const int64_t i = start + r;
-  const int64_t src = i < n ? (int64_t)((a * (uint64_t)i + c) % (uint64_t)n) : -1;
-  rows[r] = src;
-  const bool ok = src >= 0;
-  for (int k = 0; k < MLP_INP; ++k) {
-    const float v = (ok && k < MLP_IN) ? (feat[src * MLP_IN + k] - mean[k]) * istd[k] : 0.f;
-    X[r * MLP_INP + k] = f2bf(v);
-  }
-}
 
 // p[i] *= mask[i] (keeps padded entries at zero after a load)
 __global__ void apply_mask_kernel(float *p, const uint8_t *mask, int64_t n) {
@@ -647,11 +814,9 @@ hipError_t mlp_gemm(const uint16_t *A, int64_t a_r, int64_t a_c, const uint16_t 
   return hipGetLastError();
 }
 
-hipError_t mlp_softmax_ce(const float *Z3, const int8_t *labels, const int64_t *rows, int B,
-                          int64_t n_valid, float inv, float *dZ3, uint16_t *dZ3b, float *loss_sum,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(softmax_ce_kernel, dim3(nb(B)), dim3(256), 0, s, Z3, labels, rows, B, n_valid,
-                     inv, dZ3, dZ3b, loss_sum);
+hipError_t mlp_train_rows(const MlpRowsArgs &r, int B, hipStream_t s) {
+  if (B <= 0 || B % 16) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(train_rows_kernel, dim3((unsigned)(B / 16)), dim3(256), 0, s, r);
   return hipGetLastError();
 }
 int mlp_colsum_blocks(int B) { return (B + CS_ROWS - 1) / CS_ROWS; }
@@ -685,15 +850,15 @@ hipError_t gate_scatter(int64_t n2, const int64_t *orbit, const int8_t *label2, 
   hipLaunchKernelGGL(gate_scatter_kernel, dim3(nb(n2)), dim3(256), 0, s, n2, orbit, label2, label);
   return hipGetLastError();
 }
-hipError_t mlp_adamw(float *p, uint16_t *pb, const float *g, float *m, float *v,
+hipError_t mlp_adamw(float *p, uint16_t *pb, uint16_t *pbT, const float *g, float *m, float *v,
                      const uint8_t *mask, int64_t n, float lr, float b1, float b2, float eps,
                      float wd, float bc1, float bc2, hipStream_t s) {
-  hipLaunchKernelGGL(adamw_kernel, dim3(nb(n)), dim3(256), 0, s, p, pb, g, m, v, mask, n, lr, b1,
-                     b2, eps, wd, bc1, bc2);
+  hipLaunchKernelGGL(adamw_kernel, dim3(nb(n)), dim3(256), 0, s, p, pb, pbT, g, m, v, mask, n, lr,
+                     b1, b2, eps, wd, bc1, bc2);
   return hipGetLastError();
 }
-hipError_t mlp_to_bf16(const float *x, uint16_t *y, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(to_bf16_kernel, dim3(nb(n)), dim3(256), 0, s, x, y, n);
+hipError_t mlp_weights_bf16(const float *p, uint16_t *pb, uint16_t *pbT, hipStream_t s) {
+  hipLaunchKernelGGL(weights_bf16_kernel, dim3(nb(MLP_NPARAM)), dim3(256), 0, s, p, pb, pbT);
   return hipGetLastError();
 }
 hipError_t mlp_batch_input(const float *feat, const int64_t *rows, int B, int64_t n_valid,
@@ -726,13 +891,6 @@ hipError_t mlp_features(const double *x0, const double *ld, const double *lg, do
 }
 hipError_t mlp_apply_mask(float *p, const uint8_t *mask, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(apply_mask_kernel, dim3(nb(n)), dim3(256), 0, s, p, mask, n);
-  return hipGetLastError();
-}
-hipError_t mlp_batch_rows_input(int64_t n, int64_t start, int B, uint64_t a, uint64_t c,
-                                int64_t *rows, const float *feat, const float *mean,
-                                const float *istd, uint16_t *X, hipStream_t s) {
-  hipLaunchKernelGGL(batch_rows_input_kernel, dim3(nb(B)), dim3(256), 0, s, n, start, B, a, c,
-                     rows, feat, mean, istd, X);
   return hipGetLastError();
 }
 
