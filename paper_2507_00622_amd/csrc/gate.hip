@@ -87,9 +87,9 @@ struct Scratch {
 // FP32 outputs Z) or training (the activation gradients).
 struct Acts {
   uint16_t *X, *A1b, *A2b, *dZ3b, *dZ2b, *dZ1b;
-  float *Z1, *Z2, *Z3, *dZ3, *dZ2, *dZ1;
-  float *part;  // column-sum partials
-  float *work;  // split-K parts of the weight gradients
+  float *Z1, *Z2, *Z3;
+  float *bpart;  // per 16-row block: column sums of dZ1 | dZ2 | dZ3
+  float *work;   // split-K parts of the weight gradients
 };
 
 bool alloc_acts(Scratch &S, int64_t B, bool backward, Acts *a) {
@@ -102,13 +102,10 @@ bool alloc_acts(Scratch &S, int64_t B, bool backward, Acts *a) {
     a->Z2 = S.get<float>(B * MLP_H);
     a->Z3 = S.get<float>(B * MLP_OUTP);
   } else {
-    a->dZ3 = S.get<float>(B * MLP_OUTP);
     a->dZ3b = S.get<uint16_t>(B * MLP_OUTP);
-    a->dZ2 = S.get<float>(B * MLP_H);
     a->dZ2b = S.get<uint16_t>(B * MLP_H);
-    a->dZ1 = S.get<float>(B * MLP_H);
     a->dZ1b = S.get<uint16_t>(B * MLP_H);
-    a->part = S.get<float>((size_t)mlp_colsum_blocks((int)B) * MLP_H);
+    a->bpart = S.get<float>((size_t)(B / 16) * MLP_BIAS_COLS);
     a->work = S.get<float>(MLP_SPLITK_WORK);
   }
   return S.err == hipSuccess;
@@ -135,8 +132,9 @@ hipError_t forward(const chx_gate *g, const Acts &a, int B, hipStream_t s) {
 // rows at positions start .. start + B - 1 of the permutation
 // i -> (pa i + pc) mod n (padding at or past n) and their labels; inv = 1 /
 // (rows in the batch mean).  One launch does the rows' forward and
-// backward passes; the weight gradients are products over the batch's rows
-// and the bias gradients column sums.
+// backward passes and their blocks' column sums; the weight gradients are
+// products over the batch's rows, the bias gradients the sums of the
+// blocks' column sums.
 hipError_t batch_grad(chx_gate *g, const Acts &a, int B, const float *feat, const int8_t *labels,
                       int64_t n, int64_t start, uint64_t pa, uint64_t pc, float inv,
                       float *loss_sum, hipStream_t s) {
@@ -159,28 +157,21 @@ hipError_t batch_grad(chx_gate *g, const Acts &a, int B, const float *feat, cons
   r.dZ3b = a.dZ3b;
   r.dZ2b = a.dZ2b;
   r.dZ1b = a.dZ1b;
-  r.dZ3 = a.dZ3;
-  r.dZ2 = a.dZ2;
-  r.dZ1 = a.dZ1;
+  r.bpart = a.bpart;
   r.loss_sum = loss_sum;
   float *gr = g->g;
   hipError_t e;
   if ((e = mlp_train_rows(r, B, s))) return e;
-  // layer 3
+  if ((e = mlp_bias_grad(a.bpart, B / 16, gr, s))) return e;
+  // weight gradients A^T dZ, layer 3, 2, 1
   if ((e = mlp_gemm(a.A2b, 1, MLP_H, a.dZ3b, MLP_OUTP, 1, gr + MLP_W3, MLP_OUTP, MLP_H, MLP_OUTP,
                     B, nullptr, 0, s, a.work, MLP_SPLITK_WORK)))
     return e;
-  if ((e = mlp_colsum(a.dZ3, B, MLP_OUTP, MLP_OUTP, gr + MLP_B3, a.part, s))) return e;
-  // layer 2
   if ((e = mlp_gemm(a.A1b, 1, MLP_H, a.dZ2b, MLP_H, 1, gr + MLP_W2, MLP_H, MLP_H, MLP_H, B,
                     nullptr, 0, s, a.work, MLP_SPLITK_WORK)))
     return e;
-  if ((e = mlp_colsum(a.dZ2, B, MLP_H, MLP_H, gr + MLP_B2, a.part, s))) return e;
-  // layer 1
-  if ((e = mlp_gemm(a.X, 1, MLP_INP, a.dZ1b, MLP_H, 1, gr + MLP_W1, MLP_H, MLP_INP, MLP_H, B,
-                    nullptr, 0, s, a.work, MLP_SPLITK_WORK)))
-    return e;
-  return mlp_colsum(a.dZ1, B, MLP_H, MLP_H, gr + MLP_B1, a.part, s);
+  return mlp_gemm(a.X, 1, MLP_INP, a.dZ1b, MLP_H, 1, gr + MLP_W1, MLP_H, MLP_INP, MLP_H, B,
+                  nullptr, 0, s, a.work, MLP_SPLITK_WORK);
 }
 
 // p(chaotic) and confidence of n rows of device features.

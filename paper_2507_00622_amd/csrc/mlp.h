@@ -20,6 +20,8 @@ constexpr int64_t MLP_B2 = MLP_W2 + (int64_t)MLP_H * MLP_H;
 constexpr int64_t MLP_W3 = MLP_B2 + MLP_H;
 constexpr int64_t MLP_B3 = MLP_W3 + (int64_t)MLP_H * MLP_OUTP;
 constexpr int64_t MLP_NPARAM = MLP_B3 + MLP_OUTP;
+// bias-gradient columns of a training block's partial sums (b1 | b2 | b3)
+constexpr int MLP_BIAS_COLS = 2 * MLP_H + MLP_OUTP;
 
 // C = A B (+ bias) (+ C): BF16 operands at any strides, FP32 result.
 // work (work_len floats, may be null) holds split-K partial products.
@@ -38,8 +40,10 @@ constexpr int64_t MLP_SPLITK_WORK = (int64_t)16 * MLP_H * MLP_H;
 // (a i + c) mod n of the batch positions start + i (-1 at or past n), their
 // z-scored inputs, the forward pass, softmax cross-entropy against labels
 // (gradient scaled by inv, loss added to loss_sum) and the activation
-// gradients; A1, A2, dZ3, dZ2, dZ1 (and X) are left for the weight
-// gradients.  pbT: the weights' transposed BF16 copy (mlp_weights_bf16).
+// gradients; X, A1, A2, dZ3, dZ2, dZ1 (BF16) are left for the weight
+// gradients and each 16-row block's column sums of dZ1 | dZ2 | dZ3 in
+// bpart[B / 16][MLP_BIAS_COLS] for mlp_bias_grad.  pbT: the weights'
+// transposed BF16 copy (mlp_weights_bf16).
 struct MlpRowsArgs {
   int64_t n, start;
   uint64_t a, c;
@@ -49,14 +53,12 @@ struct MlpRowsArgs {
   const float *p;
   const uint16_t *pb, *pbT;
   uint16_t *X, *A1b, *A2b, *dZ3b, *dZ2b, *dZ1b;
-  float *dZ3, *dZ2, *dZ1, *loss_sum;
+  float *bpart, *loss_sum;
 };
 hipError_t mlp_train_rows(const MlpRowsArgs &r, int B, hipStream_t s);
+// grad's b1, b2, b3 = the sums of the nblk blocks' partials (in order)
+hipError_t mlp_bias_grad(const float *bpart, int nblk, float *grad, hipStream_t s);
 hipError_t mlp_apply_mask(float *p, const uint8_t *mask, int64_t n, hipStream_t s);
-// column sums of a B x ncol matrix; part holds mlp_colsum_blocks(B) * ncol floats
-int mlp_colsum_blocks(int B);
-hipError_t mlp_colsum(const float *dZ, int B, int ncol, int64_t ld, float *db, float *part,
-                      hipStream_t s);
 hipError_t mlp_fill(float *p, int64_t n, float v, hipStream_t s);
 hipError_t gate_select(int64_t n, const int *status, const int8_t *label1, const float *pc,
                        const float *conf, float conf_min, int8_t *label, uint8_t *source,

@@ -314,15 +314,19 @@ __device__ __forceinline__ int64_t mlp_tpos(int64_t i) {
 // load; the MFMAs run over k in ascending order as in gemm_tile_kernel, so
 // the products equal those of separate gemm_tile_kernel launches bit for
 // bit.  The logits and the softmax are the first wavefront's.  Outputs for
-// the weight gradients: X, A1, A2 and dZ3, dZ2, dZ1 (FP32 and BF16),
-// row-major.
+// the weight gradients: X, A1, A2, dZ3, dZ2, dZ1 (BF16, row-major); for the
+// bias gradients the block's column sums of dZ1, dZ2, dZ3 (FP32: per lane
+// its 4 rows in order, then the 4 lane groups in order; dZ3's 16 rows in
+// order) to bpart[block][b1 256 | b2 256 | b3 16].
 constexpr int TR_LD = MLP_H + 8;  // LDS row of a 256-wide BF16 activation
 __global__ void __launch_bounds__(256) train_rows_kernel(const MlpRowsArgs t) {
   __shared__ __align__(16) uint16_t Xs[16][24];
   __shared__ __align__(16) uint16_t Gs[16][24];
   __shared__ __align__(16) uint16_t As[16][TR_LD];
   __shared__ float Zs[16][17];
+  __shared__ float Ps2[4][MLP_H], Ps1[4][MLP_H];  // column sums per lane group
   __shared__ int64_t srcs[16];
+  float *bp = t.bpart + (int64_t)blockIdx.x * MLP_BIAS_COLS;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lq = lane >> 4;
   const int64_t r0 = (int64_t)blockIdx.x * 16;
@@ -449,15 +453,20 @@ __global__ void __launch_bounds__(256) train_rows_kernel(const MlpRowsArgs t) {
       for (int c = 0; c < MLP_OUTP; ++c) {
         const float g = c == 0 ? g0 : (c == 1 ? g1 : 0.f);
         const uint16_t h = f2bf(g);
-        t.dZ3[(r0 + i) * MLP_OUTP + c] = g;
         t.dZ3b[(r0 + i) * MLP_OUTP + c] = h;
         Gs[i][c] = h;
+        Zs[i][c] = g;
       }
     }
     for (int off = 8; off > 0; off >>= 1) l += __shfl_down(l, off, 64);
     if (lane == 0 && t.loss_sum) atomicAdd(t.loss_sum, l);
   }
   __syncthreads();
+  if (tid < MLP_OUTP) {
+    float sum = 0.f;
+    for (int i = 0; i < 16; ++i) sum += Zs[i][tid];
+    bp[2 * MLP_H + tid] = sum;
+  }
   // dZ2 = (dZ3 W3^T) GELU'(Z2) (one k-step); its BF16 copy replaces A2
   {
     const short4_t x = *(const short4_t *)&Gs[li][4 * lq];
@@ -465,18 +474,21 @@ __global__ void __launch_bounds__(256) train_rows_kernel(const MlpRowsArgs t) {
     for (int b = 0; b < 4; ++b) {
       const int j = cw + 16 * b + li;
       const float4_t d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, w3b[b], zero, 0, 0, 0);
+      float sum = 0.f;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = 4 * lq + r;
         const float g = d[r] * gelu_grad(z2[b][r]);
         const uint16_t h = f2bf(g);
-        t.dZ2[(r0 + i) * MLP_H + j] = g;
+        sum += g;
         t.dZ2b[(r0 + i) * MLP_H + j] = h;
         As[i][j] = h;
       }
+      Ps2[lq][j] = sum;
     }
   }
   __syncthreads();
+  bp[MLP_H + tid] = ((Ps2[0][tid] + Ps2[1][tid]) + Ps2[2][tid]) + Ps2[3][tid];
   // dZ1 = (dZ2 W2^T) GELU'(Z1)
   float4_t d1[4];
 #pragma unroll
@@ -491,42 +503,42 @@ __global__ void __launch_bounds__(256) train_rows_kernel(const MlpRowsArgs t) {
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
     const int j = cw + 16 * b + li;
+    float sum = 0.f;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = 4 * lq + r;
       const float g = d1[b][r] * gelu_grad(z1[b][r]);
-      t.dZ1[(r0 + i) * MLP_H + j] = g;
+      sum += g;
       t.dZ1b[(r0 + i) * MLP_H + j] = f2bf(g);
     }
+    Ps1[lq][j] = sum;
   }
+  __syncthreads();
+  bp[tid] = ((Ps1[0][tid] + Ps1[1][tid]) + Ps1[2][tid]) + Ps1[3][tid];
 }
 
-// db[j] = sum_r dZ[r][j] (B rows, row stride ld) in two deterministic
-// passes: block (cb, rb) of 4 waves sums rows rb*CS_ROWS .. +CS_ROWS of
-// columns cb*64 .. +64 into part[rb][j] (wave w takes rows w, w+4, ...,
-// then the 4 wave sums are added in order); a second kernel adds the
-// row-block partials in order.
-constexpr int CS_ROWS = 128;
-__global__ void __launch_bounds__(256) colsum_part_kernel(const float *dZ, int B, int ncol,
-                                                          int64_t ld, float *part) {
-  __shared__ float ws[4][64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int j = blockIdx.x * 64 + lane;
-  const int r0 = blockIdx.y * CS_ROWS;
-  int r1 = r0 + CS_ROWS;
-  if (r1 > B) r1 = B;
-  float acc = 0.f;
-  if (j < ncol && r0 + w < r1)
-    acc = ordered_sum(0.f, dZ + (int64_t)(r0 + w) * ld + j, 4 * ld, (r1 - r0 - w + 3) / 4);
-  ws[w][lane] = acc;
+// Bias gradients from the blocks' column sums of train_rows_kernel:
+// column col of bpart[nblk][528] summed over the blocks; thread group g of
+// a block of 256 adds blocks g, g + 16, g + 32, ... in order, then the 16
+// group sums are added in order.  Columns 0..255 go to b1, 256..511 to b2,
+// 512..527 to b3.
+__global__ void __launch_bounds__(256) bias_grad_kernel(const float *bpart, int nblk,
+                                                        float *grad) {
+  __shared__ float red[16][17];
+  const int c = threadIdx.x & 15, g = threadIdx.x >> 4;
+  const int col = blockIdx.x * 16 + c;
+  const int cnt = g < nblk ? (nblk - g + 15) / 16 : 0;
+  red[g][c] = ordered_sum(0.f, bpart + (int64_t)g * MLP_BIAS_COLS + col,
+                          (int64_t)16 * MLP_BIAS_COLS, cnt);
   __syncthreads();
-  if (w == 0 && j < ncol)
-    part[(int64_t)blockIdx.y * ncol + j] = ((ws[0][lane] + ws[1][lane]) + ws[2][lane]) + ws[3][lane];
-}
-__global__ void colsum_final_kernel(const float *part, int nrb, int ncol, float *db) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= ncol) return;
-  db[j] = ordered_sum(0.f, part + j, ncol, nrb);
+  if (g == 0) {
+    float t = 0.f;
+    for (int q = 0; q < 16; ++q) t += red[q][c];
+    const int64_t dst = col < MLP_H ? MLP_B1 + col
+                                    : (col < 2 * MLP_H ? MLP_B2 + (col - MLP_H)
+                                                       : MLP_B3 + (col - 2 * MLP_H));
+    grad[dst] = t;
+  }
 }
 
 __global__ void fill_f32_kernel(float *p, int64_t n, float v) {
@@ -819,14 +831,10 @@ hipError_t mlp_train_rows(const MlpRowsArgs &r, int B, hipStream_t s) {
   hipLaunchKernelGGL(train_rows_kernel, dim3((unsigned)(B / 16)), dim3(256), 0, s, r);
   return hipGetLastError();
 }
-int mlp_colsum_blocks(int B) { return (B + CS_ROWS - 1) / CS_ROWS; }
-hipError_t mlp_colsum(const float *dZ, int B, int ncol, int64_t ld, float *db, float *part,
-                      hipStream_t s) {
-  const int nrb = mlp_colsum_blocks(B);
-  if (nrb == 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(colsum_part_kernel, dim3(nb(ncol, 64), nrb), dim3(256), 0, s, dZ, B, ncol,
-                     ld, part);
-  hipLaunchKernelGGL(colsum_final_kernel, dim3(nb(ncol)), dim3(256), 0, s, part, nrb, ncol, db);
+hipError_t mlp_bias_grad(const float *bpart, int nblk, float *grad, hipStream_t s) {
+  if (nblk <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(bias_grad_kernel, dim3(MLP_BIAS_COLS / 16), dim3(256), 0, s, bpart, nblk,
+                     grad);
   return hipGetLastError();
 }
 hipError_t mlp_fill(float *p, int64_t n, float v, hipStream_t s) {
