@@ -89,7 +89,7 @@ struct Acts {
   uint16_t *X, *A1b, *A2b, *dZ3b, *dZ2b, *dZ1b;
   float *Z1, *Z2, *Z3;
   float *bpart;  // per 16-row block: column sums of dZ1 | dZ2 | dZ3
-  float *work;   // split-K parts of the weight gradients
+  float *work1, *work2, *work3;  // split-K parts of the weight gradients
 };
 
 bool alloc_acts(Scratch &S, int64_t B, bool backward, Acts *a) {
@@ -106,7 +106,9 @@ bool alloc_acts(Scratch &S, int64_t B, bool backward, Acts *a) {
     a->dZ2b = S.get<uint16_t>(B * MLP_H);
     a->dZ1b = S.get<uint16_t>(B * MLP_H);
     a->bpart = S.get<float>((size_t)(B / 16) * MLP_BIAS_COLS);
-    a->work = S.get<float>(MLP_SPLITK_WORK);
+    a->work1 = S.get<float>(MLP_SPLITK_WORK_SMALL);
+    a->work2 = S.get<float>(MLP_SPLITK_WORK);
+    a->work3 = S.get<float>(MLP_SPLITK_WORK_SMALL);
   }
   return S.err == hipSuccess;
 }
@@ -128,7 +130,8 @@ hipError_t forward(const chx_gate *g, const Acts &a, int B, hipStream_t s) {
                   p + MLP_B3, 0, s);
 }
 
-// Loss and gradient of one batch of B rows (multiple of 16) into g->g: the
+// Loss and gradient of one batch of B rows (multiple of 16) into g->g and
+// the weight gradients' split-K parts (gp; mlp_grad_step adds them): the
 // rows at positions start .. start + B - 1 of the permutation
 // i -> (pa i + pc) mod n (padding at or past n) and their labels; inv = 1 /
 // (rows in the batch mean).  One launch does the rows' forward and
@@ -137,7 +140,7 @@ hipError_t forward(const chx_gate *g, const Acts &a, int B, hipStream_t s) {
 // blocks' column sums.
 hipError_t batch_grad(chx_gate *g, const Acts &a, int B, const float *feat, const int8_t *labels,
                       int64_t n, int64_t start, uint64_t pa, uint64_t pc, float inv,
-                      float *loss_sum, hipStream_t s) {
+                      float *loss_sum, GradParts *gp, hipStream_t s) {
   MlpRowsArgs r;
   r.n = n;
   r.start = start;
@@ -163,15 +166,21 @@ hipError_t batch_grad(chx_gate *g, const Acts &a, int B, const float *feat, cons
   hipError_t e;
   if ((e = mlp_train_rows(r, B, s))) return e;
   if ((e = mlp_bias_grad(a.bpart, B / 16, gr, s))) return e;
-  // weight gradients A^T dZ, layer 3, 2, 1
+  // weight gradients A^T dZ, layer 3, 2, 1, their parts left for mlp_grad_step
+  gp->w1 = a.work1;
+  gp->w2 = a.work2;
+  gp->w3 = a.work3;
   if ((e = mlp_gemm(a.A2b, 1, MLP_H, a.dZ3b, MLP_OUTP, 1, gr + MLP_W3, MLP_OUTP, MLP_H, MLP_OUTP,
-                    B, nullptr, 0, s, a.work, MLP_SPLITK_WORK)))
+                    B, nullptr, 0, s, a.work3, MLP_SPLITK_WORK_SMALL, EPI_NONE, nullptr, nullptr,
+                    &gp->s3)))
     return e;
   if ((e = mlp_gemm(a.A1b, 1, MLP_H, a.dZ2b, MLP_H, 1, gr + MLP_W2, MLP_H, MLP_H, MLP_H, B,
-                    nullptr, 0, s, a.work, MLP_SPLITK_WORK)))
+                    nullptr, 0, s, a.work2, MLP_SPLITK_WORK, EPI_NONE, nullptr, nullptr,
+                    &gp->s2)))
     return e;
   return mlp_gemm(a.X, 1, MLP_INP, a.dZ1b, MLP_H, 1, gr + MLP_W1, MLP_H, MLP_INP, MLP_H, B,
-                  nullptr, 0, s, a.work, MLP_SPLITK_WORK);
+                  nullptr, 0, s, a.work1, MLP_SPLITK_WORK_SMALL, EPI_NONE, nullptr, nullptr,
+                  &gp->s1);
 }
 
 // p(chaotic) and confidence of n rows of device features.
@@ -309,14 +318,15 @@ chx_status chx_gate_train(chx_gate *g, const float *features, const int8_t *labe
       const int64_t start = b * B;
       const int64_t rows = (n - start) < B ? (n - start) : B;
       const int Bp = (int)round16(rows);
-      GCHK(batch_grad(g, a, Bp, feat, lab, n, start, pa, pc, 1.0f / (float)rows, loss + ep, s),
+      GradParts gp;
+      GCHK(batch_grad(g, a, Bp, feat, lab, n, start, pa, pc, 1.0f / (float)rows, loss + ep, &gp,
+                      s),
            "batch gradient");
       g->t += 1;
       const double bc1 = 1.0 - pow((double)c.beta1, (double)g->t);
       const double bc2 = 1.0 - pow((double)c.beta2, (double)g->t);
-      GCHK(mlp_adamw(g->p, g->pb, g->pbT, g->g, g->m, g->v, g->mask, MLP_NPARAM, c.lr, c.beta1,
-                     c.beta2,
-                     c.eps, c.weight_decay, (float)bc1, (float)bc2, s),
+      GCHK(mlp_grad_step(gp, g->p, g->pb, g->pbT, g->g, g->m, g->v, g->mask, 1, c.lr, c.beta1,
+                         c.beta2, c.eps, c.weight_decay, (float)bc1, (float)bc2, s),
            "AdamW");
     }
   }
@@ -347,7 +357,11 @@ chx_status chx_gate_grad(chx_gate *g, const float *features, const int8_t *label
   if (!alloc_acts(S, Bp, true, &a)) return dev_fail(S.err, "allocate buffers");
   GCHK(mlp_fill(loss, 1, 0.f, s), "clear loss");
   GCHK(mlp_fill(g->g, MLP_NPARAM, 0.f, s), "clear gradient");
-  GCHK(batch_grad(g, a, Bp, feat, lab, n, 0, 1, 0, 1.0f / (float)n, loss, s), "gradient");
+  GradParts gp;
+  GCHK(batch_grad(g, a, Bp, feat, lab, n, 0, 1, 0, 1.0f / (float)n, loss, &gp, s), "gradient");
+  GCHK(mlp_grad_step(gp, g->p, g->pb, g->pbT, g->g, g->m, g->v, g->mask, 0, 0.f, 0.f, 0.f, 0.f,
+                     0.f, 1.f, 1.f, s),
+       "gradient parts");
   float hl = 0.f;
   GCHK(hipMemcpyAsync(&hl, loss, sizeof hl, hipMemcpyDeviceToHost, s), "read loss");
   if (grad_out)

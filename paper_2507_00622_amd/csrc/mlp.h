@@ -32,10 +32,15 @@ enum { EPI_NONE = 0, EPI_GELU = 1, EPI_GELU_BACK = 2 };
 hipError_t mlp_gemm(const uint16_t *A, int64_t a_r, int64_t a_c, const uint16_t *B, int64_t b_r,
                     int64_t b_c, float *C, int64_t ldc, int M, int N, int K, const float *bias,
                     int accumulate, hipStream_t s, float *work = nullptr, int64_t work_len = 0,
-                    int epi = EPI_NONE, uint16_t *Cb = nullptr, const float *Zaux = nullptr);
-// split-K workspace of the training pass (floats): up to 16 parts of the
-// 256 x 256 weight gradient
+                    int epi = EPI_NONE, uint16_t *Cb = nullptr, const float *Zaux = nullptr,
+                    int *parts = nullptr);
+// With parts given (no bias, no accumulate, ldc == N): a product split over
+// K leaves its parts in work[z][M][N] for the caller to add and *parts = S
+// (the number of parts); with *parts == 1 the product is in C.
+// Split-K workspaces of the training pass (floats): up to 16 parts of the
+// 256 x 256 weight gradient, 64 of the 16 x 256 and 256 x 16 ones
 constexpr int64_t MLP_SPLITK_WORK = (int64_t)16 * MLP_H * MLP_H;
+constexpr int64_t MLP_SPLITK_WORK_SMALL = (int64_t)64 * MLP_H * MLP_OUTP;
 // The row-local part of a training batch of B rows (multiple of 16): rows
 // (a i + c) mod n of the batch positions start + i (-1 at or past n), their
 // z-scored inputs, the forward pass, softmax cross-entropy against labels
@@ -66,11 +71,18 @@ hipError_t gate_select(int64_t n, const int *status, const int8_t *label1, const
                        hipStream_t s);
 hipError_t gate_scatter(int64_t n2, const int64_t *orbit, const int8_t *label2, int8_t *label,
                         hipStream_t s);
-// AdamW on the FP32 masters p (entries with mask set); pb receives their
-// BF16 copies and pbT the weights' transposed BF16 copies.
-hipError_t mlp_adamw(float *p, uint16_t *pb, uint16_t *pbT, const float *g, float *m, float *v,
-                     const uint8_t *mask, int64_t n, float lr, float b1, float b2, float eps,
-                     float wd, float bc1, float bc2, hipStream_t s);
+// Split-K parts of the three weight gradients (sN parts at wN; sN <= 1:
+// the gradient is already in g).
+struct GradParts {
+  const float *w1, *w2, *w3;
+  int s1, s2, s3;
+};
+// g = the batch's gradient (adding the weight gradients' parts); with step
+// set, AdamW on the FP32 masters p (entries with mask set), pb receiving
+// their BF16 copies and pbT the weights' transposed BF16 copies.
+hipError_t mlp_grad_step(const GradParts &gp, float *p, uint16_t *pb, uint16_t *pbT, float *g,
+                         float *m, float *v, const uint8_t *mask, int step, float lr, float b1,
+                         float b2, float eps, float wd, float bc1, float bc2, hipStream_t s);
 // pb = BF16 of all MLP_NPARAM parameters, pbT = BF16 of the weights
 // transposed (W1T[256][16], W2T[256][256], W3T[16][256] at the offsets of
 // W1, W2, W3)

@@ -600,13 +600,27 @@ __global__ void zero_u64_kernel(unsigned long long *p, int n) {
   if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
 }
 
-// AdamW on the FP32 masters; mask[i] = 0 keeps padded entries at zero.
-__global__ void adamw_kernel(float *p, uint16_t *pb, uint16_t *pbT, const float *g, float *m,
-                             float *v, const uint8_t *mask, int64_t n, float lr, float b1,
-                             float b2, float eps, float wd, float bc1, float bc2) {
+// The gradient of one batch, entry i of g: a weight whose product was split
+// over K is the sum of its parts in order of the part (as
+// gemm_splitk_sum_kernel adds them); the other entries (unsplit products,
+// biases) are already in g.  With step set, AdamW then updates the FP32
+// master (entries with mask set) and its BF16 copies pb and pbT.
+__global__ void grad_step_kernel(GradParts gp, float *p, uint16_t *pb, uint16_t *pbT, float *g,
+                                 float *m, float *v, const uint8_t *mask, int step, float lr,
+                                 float b1, float b2, float eps, float wd, float bc1, float bc2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || !mask[i]) return;
-  const float gi = g[i];
+  if (i >= MLP_NPARAM) return;
+  float gi;
+  if (i < MLP_B1 && gp.s1 > 1)
+    gi = ordered_sum(0.f, gp.w1 + (i - MLP_W1), MLP_B1 - MLP_W1, gp.s1);
+  else if (i >= MLP_W2 && i < MLP_B2 && gp.s2 > 1)
+    gi = ordered_sum(0.f, gp.w2 + (i - MLP_W2), MLP_B2 - MLP_W2, gp.s2);
+  else if (i >= MLP_W3 && i < MLP_B3 && gp.s3 > 1)
+    gi = ordered_sum(0.f, gp.w3 + (i - MLP_W3), MLP_B3 - MLP_W3, gp.s3);
+  else
+    gi = g[i];
+  g[i] = gi;
+  if (!step || !mask[i]) return;
   const float mi = b1 * m[i] + (1.f - b1) * gi;
   const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
   m[i] = mi;
@@ -771,7 +785,7 @@ inline unsigned nb(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t);
 hipError_t mlp_gemm(const uint16_t *A, int64_t a_r, int64_t a_c, const uint16_t *B, int64_t b_r,
                     int64_t b_c, float *C, int64_t ldc, int M, int N, int K, const float *bias,
                     int accumulate, hipStream_t s, float *work, int64_t work_len, int epi,
-                    uint16_t *Cb, const float *Zaux) {
+                    uint16_t *Cb, const float *Zaux, int *parts) {
   if (M <= 0 || N <= 0 || K <= 0 || M % 16 || N % 16 || K % 16) return hipErrorInvalidValue;
   // (64, 64) tiles where N allows, (16, 64) for a 16-row product, else
   // (64, 16)
@@ -783,7 +797,8 @@ hipError_t mlp_gemm(const uint16_t *A, int64_t a_r, int64_t a_c, const uint16_t 
   // two chunks
   const int chunks = (K + GBK - 1) / GBK;
   if (epi < EPI_NONE || epi > EPI_GELU_BACK ||
-      (epi != EPI_NONE && (!Cb || (epi == EPI_GELU_BACK && !Zaux) || accumulate)))
+      (epi != EPI_NONE && (!Cb || (epi == EPI_GELU_BACK && !Zaux) || accumulate)) ||
+      (parts && (bias || accumulate || ldc != N)))
     return hipErrorInvalidValue;
   int S = 1;
   while (epi == EPI_NONE && work && gm * gn * S < 256 && chunks >= 4 * S &&
@@ -820,7 +835,8 @@ hipError_t mlp_gemm(const uint16_t *A, int64_t a_r, int64_t a_c, const uint16_t 
   }
 #undef CHX_GEMM_LAUNCH
 #undef CHX_GEMM_GO
-  if (S > 1)
+  if (parts) *parts = S;
+  else if (S > 1)
     hipLaunchKernelGGL(gemm_splitk_sum_kernel, dim3(nb((int64_t)M * N)), dim3(256), 0, s, work, S,
                        M, N, C, ldc, bias, accumulate);
   return hipGetLastError();
@@ -858,11 +874,11 @@ hipError_t gate_scatter(int64_t n2, const int64_t *orbit, const int8_t *label2, 
   hipLaunchKernelGGL(gate_scatter_kernel, dim3(nb(n2)), dim3(256), 0, s, n2, orbit, label2, label);
   return hipGetLastError();
 }
-hipError_t mlp_adamw(float *p, uint16_t *pb, uint16_t *pbT, const float *g, float *m, float *v,
-                     const uint8_t *mask, int64_t n, float lr, float b1, float b2, float eps,
-                     float wd, float bc1, float bc2, hipStream_t s) {
-  hipLaunchKernelGGL(adamw_kernel, dim3(nb(n)), dim3(256), 0, s, p, pb, pbT, g, m, v, mask, n, lr,
-                     b1, b2, eps, wd, bc1, bc2);
+hipError_t mlp_grad_step(const GradParts &gp, float *p, uint16_t *pb, uint16_t *pbT, float *g,
+                         float *m, float *v, const uint8_t *mask, int step, float lr, float b1,
+                         float b2, float eps, float wd, float bc1, float bc2, hipStream_t s) {
+  hipLaunchKernelGGL(grad_step_kernel, dim3(nb(MLP_NPARAM)), dim3(256), 0, s, gp, p, pb, pbT, g, m,
+                     v, mask, step, lr, b1, b2, eps, wd, bc1, bc2);
   return hipGetLastError();
 }
 hipError_t mlp_weights_bf16(const float *p, uint16_t *pb, uint16_t *pbT, hipStream_t s) {
