@@ -854,7 +854,7 @@ def bench_gate(args, P, chx, torch, dev):
     roof_mlp = {"bound": "mfma", "achieved": mlp_fl / t_train / 1e12,
                 "peak": PEAK_BF16 / 1e12, "unit": "TFLOP/s",
                 "frac": mlp_fl / t_train / PEAK_BF16, "traffic": None,
-                "kernel": "chx::gemm_tile_kernel (training pass, all kernels)",
+                "kernel": "chx::train_rows_kernel + chx::gemm_tile_kernel (training pass, all kernels)",
                 "flops_per_row_epoch": mlp_train_flops_per_row(),
                 "executed_flops_per_row_epoch": mlp_train_flops_per_row(True),
                 "time_basis": "whole training call"}
