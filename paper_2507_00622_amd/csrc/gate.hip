@@ -19,7 +19,7 @@ struct chx_gate {
   float *p = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
   uint8_t *mask = nullptr;
   uint16_t *pb = nullptr;   // BF16 copy of p
-  uint16_t *pbT = nullptr;  // BF16 copy of the weights, transposed
+  uint16_t *pbF = nullptr;  // BF16 copy of the weights in MFMA operand order
   float *mean = nullptr;    // [16] z-score mean (first 6 used)
   float *istd = nullptr;    // [16] inverse standard deviation
   double *partials = nullptr;
@@ -153,7 +153,7 @@ hipError_t batch_grad(chx_gate *g, const Acts &a, int B, const float *feat, cons
   r.inv = inv;
   r.p = g->p;
   r.pb = g->pb;
-  r.pbT = g->pbT;
+  r.pbF = g->pbF;
   r.X = a.X;
   r.A1b = a.A1b;
   r.A2b = a.A2b;
@@ -237,7 +237,7 @@ chx_status chx_gate_create(uint64_t seed, chx_gate **out) {
   al(&g->g, sizeof(float) * MLP_NPARAM);
   al(&g->mask, MLP_NPARAM);
   al(&g->pb, sizeof(uint16_t) * MLP_NPARAM);
-  al(&g->pbT, sizeof(uint16_t) * MLP_NPARAM);
+  al(&g->pbF, sizeof(uint16_t) * MLP_NFRAG);
   al(&g->mean, sizeof(float) * 16);
   al(&g->istd, sizeof(float) * 16);
   al(&g->partials, sizeof(double) * MLP_STAT_BLOCKS * 2 * MLP_IN);
@@ -247,7 +247,7 @@ chx_status chx_gate_create(uint64_t seed, chx_gate **out) {
   if (e == hipSuccess) e = mlp_fill(g->g, MLP_NPARAM, 0.f, nullptr);
   if (e == hipSuccess) e = mlp_fill(g->mean, 16, 0.f, nullptr);
   if (e == hipSuccess) e = mlp_fill(g->istd, 16, 1.f, nullptr);
-  if (e == hipSuccess) e = mlp_weights_bf16(g->p, g->pb, g->pbT, nullptr);
+  if (e == hipSuccess) e = mlp_weights_bf16(g->p, g->pb, g->pbF, nullptr);
   if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
   if (e != hipSuccess) {
     chx_gate_destroy(g);
@@ -261,7 +261,7 @@ void chx_gate_destroy(chx_gate *g) {
   if (!g) return;
   (void)hipDeviceSynchronize();
   for (void *p : {(void *)g->p, (void *)g->m, (void *)g->v, (void *)g->g, (void *)g->mask,
-                  (void *)g->pb, (void *)g->pbT, (void *)g->mean, (void *)g->istd,
+                  (void *)g->pb, (void *)g->pbF, (void *)g->mean, (void *)g->istd,
                   (void *)g->partials})
     if (p) (void)hipFree(p);
   delete g;
@@ -307,7 +307,7 @@ chx_status chx_gate_train(chx_gate *g, const float *features, const int8_t *labe
   GCHK(mlp_fill(loss, c.epochs, 0.f, s), "clear loss");
   const int64_t nbatch = (n + B - 1) / B;
   // the BF16 copy of the weights; each AdamW step refreshes it
-  GCHK(mlp_weights_bf16(g->p, g->pb, g->pbT, s), "weights to bf16");
+  GCHK(mlp_weights_bf16(g->p, g->pb, g->pbF, s), "weights to bf16");
   for (int ep = 0; ep < c.epochs; ++ep) {
     // epoch permutation i -> (pa i + pc) mod n with pa coprime to n
     const uint64_t key = mix64(c.seed ^ mix64(0x6a7e0000ull + (uint64_t)ep));
@@ -325,7 +325,7 @@ chx_status chx_gate_train(chx_gate *g, const float *features, const int8_t *labe
       g->t += 1;
       const double bc1 = 1.0 - pow((double)c.beta1, (double)g->t);
       const double bc2 = 1.0 - pow((double)c.beta2, (double)g->t);
-      GCHK(mlp_grad_step(gp, g->p, g->pb, g->pbT, g->g, g->m, g->v, g->mask, 1, c.lr, c.beta1,
+      GCHK(mlp_grad_step(gp, g->p, g->pb, g->pbF, g->g, g->m, g->v, g->mask, 1, c.lr, c.beta1,
                          c.beta2, c.eps, c.weight_decay, (float)bc1, (float)bc2, s),
            "AdamW");
     }
@@ -359,7 +359,7 @@ chx_status chx_gate_grad(chx_gate *g, const float *features, const int8_t *label
   GCHK(mlp_fill(g->g, MLP_NPARAM, 0.f, s), "clear gradient");
   GradParts gp;
   GCHK(batch_grad(g, a, Bp, feat, lab, n, 0, 1, 0, 1.0f / (float)n, loss, &gp, s), "gradient");
-  GCHK(mlp_grad_step(gp, g->p, g->pb, g->pbT, g->g, g->m, g->v, g->mask, 0, 0.f, 0.f, 0.f, 0.f,
+  GCHK(mlp_grad_step(gp, g->p, g->pb, g->pbF, g->g, g->m, g->v, g->mask, 0, 0.f, 0.f, 0.f, 0.f,
                      0.f, 1.f, 1.f, s),
        "gradient parts");
   float hl = 0.f;
@@ -418,7 +418,7 @@ chx_status chx_gate_set(chx_gate *g, const float *params, const float *mean, con
     GCHK(mlp_apply_mask(g->p, g->mask, MLP_NPARAM, nullptr), "mask params");
     GCHK(mlp_fill(g->m, MLP_NPARAM, 0.f, nullptr), "clear moments");
     GCHK(mlp_fill(g->v, MLP_NPARAM, 0.f, nullptr), "clear moments");
-    GCHK(mlp_weights_bf16(g->p, g->pb, g->pbT, nullptr), "weights to bf16");
+    GCHK(mlp_weights_bf16(g->p, g->pb, g->pbF, nullptr), "weights to bf16");
     g->t = 0;
   }
   if ((mean == nullptr) != (istd == nullptr))

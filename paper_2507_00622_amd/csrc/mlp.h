@@ -22,6 +22,13 @@ constexpr int64_t MLP_B3 = MLP_W3 + (int64_t)MLP_H * MLP_OUTP;
 constexpr int64_t MLP_NPARAM = MLP_B3 + MLP_OUTP;
 // bias-gradient columns of a training block's partial sums (b1 | b2 | b3)
 constexpr int MLP_BIAS_COLS = 2 * MLP_H + MLP_OUTP;
+// regions of the training pass's BF16 weights in MFMA operand order (pbF)
+constexpr int64_t MLP_F_W1 = 0;                                      // W1, forward
+constexpr int64_t MLP_F_W2 = MLP_F_W1 + (int64_t)MLP_INP * MLP_H;    // W2, forward
+constexpr int64_t MLP_F_W2T = MLP_F_W2 + (int64_t)MLP_H * MLP_H;     // W2, backward
+constexpr int64_t MLP_F_W3 = MLP_F_W2T + (int64_t)MLP_H * MLP_H;     // W3, forward
+constexpr int64_t MLP_F_W3T = MLP_F_W3 + (int64_t)MLP_H * MLP_OUTP;  // W3, backward
+constexpr int64_t MLP_NFRAG = MLP_F_W3T + (int64_t)MLP_H * MLP_OUTP;
 
 // C = A B (+ bias) (+ C): BF16 operands at any strides, FP32 result.
 // work (work_len floats, may be null) holds split-K partial products.
@@ -47,8 +54,8 @@ constexpr int64_t MLP_SPLITK_WORK_SMALL = (int64_t)64 * MLP_H * MLP_OUTP;
 // (gradient scaled by inv, loss added to loss_sum) and the activation
 // gradients; X, A1, A2, dZ3, dZ2, dZ1 (BF16) are left for the weight
 // gradients and each 16-row block's column sums of dZ1 | dZ2 | dZ3 in
-// bpart[B / 16][MLP_BIAS_COLS] for mlp_bias_grad.  pbT: the weights'
-// transposed BF16 copy (mlp_weights_bf16).
+// bpart[B / 16][MLP_BIAS_COLS] for mlp_bias_grad.  pbF: the weights' BF16
+// copy in MFMA operand order (mlp_weights_bf16).
 struct MlpRowsArgs {
   int64_t n, start;
   uint64_t a, c;
@@ -56,7 +63,7 @@ struct MlpRowsArgs {
   const int8_t *labels;
   float inv;
   const float *p;
-  const uint16_t *pb, *pbT;
+  const uint16_t *pb, *pbF;
   uint16_t *X, *A1b, *A2b, *dZ3b, *dZ2b, *dZ1b;
   float *bpart, *loss_sum;
 };
@@ -79,14 +86,13 @@ struct GradParts {
 };
 // g = the batch's gradient (adding the weight gradients' parts); with step
 // set, AdamW on the FP32 masters p (entries with mask set), pb receiving
-// their BF16 copies and pbT the weights' transposed BF16 copies.
-hipError_t mlp_grad_step(const GradParts &gp, float *p, uint16_t *pb, uint16_t *pbT, float *g,
+// their BF16 copies and pbF the weights' operand-order BF16 copies.
+hipError_t mlp_grad_step(const GradParts &gp, float *p, uint16_t *pb, uint16_t *pbF, float *g,
                          float *m, float *v, const uint8_t *mask, int step, float lr, float b1,
                          float b2, float eps, float wd, float bc1, float bc2, hipStream_t s);
-// pb = BF16 of all MLP_NPARAM parameters, pbT = BF16 of the weights
-// transposed (W1T[256][16], W2T[256][256], W3T[16][256] at the offsets of
-// W1, W2, W3)
-hipError_t mlp_weights_bf16(const float *p, uint16_t *pb, uint16_t *pbT, hipStream_t s);
+// pb = BF16 of all MLP_NPARAM parameters; pbF (MLP_NFRAG entries) = BF16
+// of the weights in the training pass's MFMA operand order
+hipError_t mlp_weights_bf16(const float *p, uint16_t *pb, uint16_t *pbF, hipStream_t s);
 hipError_t mlp_batch_input(const float *feat, const int64_t *rows, int B, int64_t n_valid,
                            const float *mean, const float *istd, uint16_t *X, hipStream_t s);
 hipError_t mlp_init_params(float *p, uint8_t *mask, uint64_t seed, hipStream_t s);

@@ -282,19 +282,42 @@ __global__ void gemm_splitk_sum_kernel(const float *work, int S, int M, int N, f
 }
 
 
-// Position of weight entry i in the transposed BF16 weights (W1T[256][16],
-// W2T[256][256], W3T[16][256], at the offsets of W1, W2, W3); -1 for biases.
-__device__ __forceinline__ int64_t mlp_tpos(int64_t i) {
-  if (i < MLP_B1) return MLP_W1 + (i % MLP_H) * MLP_INP + i / MLP_H;
-  if (i >= MLP_W2 && i < MLP_B2) {
-    const int64_t o = i - MLP_W2;
-    return MLP_W2 + (o % MLP_H) * MLP_H + o / MLP_H;
+// Block barrier for LDS traffic only: waits for this wavefront's LDS
+// accesses, not for its global loads in flight (which __syncthreads would
+// drain); the memory clobber keeps the compiler from moving accesses across.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// The training pass's BF16 weights in MFMA operand order: the B operand of
+// 16-column tile jt and k-step ks of a product is 64 lanes x 4 consecutive k
+// (lane l: column 16 jt + l % 16, k = 16 ks + 4 (l / 16) + e), one
+// contiguous 512-byte run, so a wavefront's operand load is one coalesced
+// read.  Entry (jt, ks, l, e) of a product with KS k-steps lies at
+// ((jt KS + ks) 64 + l) 4 + e of its region.  Regions: layer 1 forward
+// (B = W1), layer 2 forward (W2) and backward (W2^T), layer 3 forward (W3)
+// and backward (W3^T).
+__device__ __forceinline__ int64_t frag_at(int64_t base, int ks_count, int jt, int ks, int k4,
+                                           int col16) {
+  // k4 = k mod 16 within the k-step, col16 = column mod 16
+  return base + ((int64_t)(jt * ks_count + ks) * 64 + (k4 >> 2) * 16 + col16) * 4 + (k4 & 3);
+}
+// Positions of weight entry i in the operand-order copy (second one for
+// the weights used by both passes; -1 where there is none).
+__device__ __forceinline__ void mlp_fpos(int64_t i, int64_t &f0, int64_t &f1) {
+  f0 = f1 = -1;
+  if (i < MLP_B1) {  // W1[k][j], k < 16
+    const int k = (int)(i / MLP_H), j = (int)(i % MLP_H);
+    f0 = frag_at(MLP_F_W1, 1, j >> 4, 0, k, j & 15);
+  } else if (i >= MLP_W2 && i < MLP_B2) {  // W2[k][j]
+    const int k = (int)((i - MLP_W2) / MLP_H), j = (int)((i - MLP_W2) % MLP_H);
+    f0 = frag_at(MLP_F_W2, MLP_H / 16, j >> 4, k >> 4, k & 15, j & 15);
+    f1 = frag_at(MLP_F_W2T, MLP_H / 16, k >> 4, j >> 4, j & 15, k & 15);
+  } else if (i >= MLP_W3 && i < MLP_B3) {  // W3[k][j], j < 16
+    const int k = (int)((i - MLP_W3) / MLP_OUTP), j = (int)((i - MLP_W3) % MLP_OUTP);
+    f0 = frag_at(MLP_F_W3, MLP_H / 16, 0, k >> 4, k & 15, j);
+    f1 = frag_at(MLP_F_W3T, 1, k >> 4, 0, j, k & 15);
   }
-  if (i >= MLP_W3 && i < MLP_B3) {
-    const int64_t o = i - MLP_W3;
-    return MLP_W3 + (o % MLP_OUTP) * MLP_H + o / MLP_OUTP;
-  }
-  return -1;
 }
 
 // The row-local part of one training batch, 16 rows per block of 4
@@ -338,14 +361,13 @@ __global__ void __launch_bounds__(256) train_rows_kernel(const MlpRowsArgs t) {
   short4_t wf[MLP_H / 16][4], w3f[MLP_H / 16], w3b[4];
 #pragma unroll
   for (int b = 0; b < 4; ++b)
-    w3b[b] = *(const short4_t *)&t.pb[MLP_W3 + (int64_t)(cw + 16 * b + li) * MLP_OUTP + 4 * lq];
+    w3b[b] = *(const short4_t *)&t.pbF[MLP_F_W3T + ((4 * wave + b) * 64 + lane) * 4];
 #pragma unroll
   for (int ks = 0; ks < MLP_H / 16; ++ks) {
 #pragma unroll
     for (int b = 0; b < 4; ++b)
-      wf[ks][b] = *(const short4_t *)&t.pbT[MLP_W2 + (int64_t)(cw + 16 * b + li) * MLP_H +
-                                            16 * ks + 4 * lq];
-    w3f[ks] = *(const short4_t *)&t.pbT[MLP_W3 + (int64_t)li * MLP_H + 16 * ks + 4 * lq];
+      wf[ks][b] = *(const short4_t *)&t.pbF[MLP_F_W2 + (((4 * wave + b) * 16 + ks) * 64 + lane) * 4];
+    w3f[ks] = *(const short4_t *)&t.pbF[MLP_F_W3 + (ks * 64 + lane) * 4];
   }
   {
     const int i = tid >> 4, k = tid & 15;
@@ -359,15 +381,15 @@ __global__ void __launch_bounds__(256) train_rows_kernel(const MlpRowsArgs t) {
     Xs[i][k] = h;
     t.X[(r0 + i) * MLP_INP + k] = h;
   }
-  __syncthreads();
+  lds_barrier();
   // layer 1 (one k-step)
   float4_t z1[4], z2[4];
   {
     const short4_t x = *(const short4_t *)&Xs[li][4 * lq];
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      const int j = cw + 16 * b + li;
-      const short4_t w = *(const short4_t *)&t.pbT[MLP_W1 + (int64_t)j * MLP_INP + 4 * lq];
+      const short4_t w =
+          *(const short4_t *)&t.pbF[MLP_F_W1 + ((4 * wave + b) * 64 + lane) * 4];
       z1[b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, w, zero, 0, 0, 0);
     }
   }
@@ -384,7 +406,7 @@ __global__ void __launch_bounds__(256) train_rows_kernel(const MlpRowsArgs t) {
       t.A1b[(r0 + i) * MLP_H + j] = h;
     }
   }
-  __syncthreads();
+  lds_barrier();
   // layer 2
 #pragma unroll
   for (int b = 0; b < 4; ++b) z2[b] = zero;
@@ -399,8 +421,8 @@ __global__ void __launch_bounds__(256) train_rows_kernel(const MlpRowsArgs t) {
   for (int ks = 0; ks < MLP_H / 16; ++ks)
 #pragma unroll
     for (int b = 0; b < 4; ++b)
-      wf[ks][b] = *(const short4_t *)&t.pb[MLP_W2 + (int64_t)(cw + 16 * b + li) * MLP_H +
-                                           16 * ks + 4 * lq];
+      wf[ks][b] =
+          *(const short4_t *)&t.pbF[MLP_F_W2T + (((4 * wave + b) * 16 + ks) * 64 + lane) * 4];
   uint16_t h2[4][4];
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
@@ -413,12 +435,12 @@ __global__ void __launch_bounds__(256) train_rows_kernel(const MlpRowsArgs t) {
       t.A2b[(r0 + 4 * lq + r) * MLP_H + j] = h2[b][r];
     }
   }
-  __syncthreads();  // every wavefront has read A1
+  lds_barrier();  // every wavefront has read A1
 #pragma unroll
   for (int b = 0; b < 4; ++b)
 #pragma unroll
     for (int r = 0; r < 4; ++r) As[4 * lq + r][cw + 16 * b + li] = h2[b][r];
-  __syncthreads();
+  lds_barrier();
   // logits (first wavefront)
   if (wave == 0) {
     float4_t z3 = zero;
@@ -431,7 +453,7 @@ __global__ void __launch_bounds__(256) train_rows_kernel(const MlpRowsArgs t) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) Zs[4 * lq + r][li] = z3[r] + bj;
   }
-  __syncthreads();
+  lds_barrier();
   // softmax cross-entropy, one lane per row (first wavefront)
   if (wave == 0) {
     float l = 0.f;
@@ -461,7 +483,7 @@ __global__ void __launch_bounds__(256) train_rows_kernel(const MlpRowsArgs t) {
     for (int off = 8; off > 0; off >>= 1) l += __shfl_down(l, off, 64);
     if (lane == 0 && t.loss_sum) atomicAdd(t.loss_sum, l);
   }
-  __syncthreads();
+  lds_barrier();
   if (tid < MLP_OUTP) {
     float sum = 0.f;
     for (int i = 0; i < 16; ++i) sum += Zs[i][tid];
@@ -487,7 +509,7 @@ __global__ void __launch_bounds__(256) train_rows_kernel(const MlpRowsArgs t) {
       Ps2[lq][j] = sum;
     }
   }
-  __syncthreads();
+  lds_barrier();
   bp[MLP_H + tid] = ((Ps2[0][tid] + Ps2[1][tid]) + Ps2[2][tid]) + Ps2[3][tid];
   // dZ1 = (dZ2 W2^T) GELU'(Z1)
   float4_t d1[4];
@@ -513,7 +535,7 @@ __global__ void __launch_bounds__(256) train_rows_kernel(const MlpRowsArgs t) {
     }
     Ps1[lq][j] = sum;
   }
-  __syncthreads();
+  lds_barrier();
   bp[tid] = ((Ps1[0][tid] + Ps1[1][tid]) + Ps1[2][tid]) + Ps1[3][tid];
 }
 
@@ -604,8 +626,8 @@ __global__ void zero_u64_kernel(unsigned long long *p, int n) {
 // over K is the sum of its parts in order of the part (as
 // gemm_splitk_sum_kernel adds them); the other entries (unsplit products,
 // biases) are already in g.  With step set, AdamW then updates the FP32
-// master (entries with mask set) and its BF16 copies pb and pbT.
-__global__ void grad_step_kernel(GradParts gp, float *p, uint16_t *pb, uint16_t *pbT, float *g,
+// master (entries with mask set) and its BF16 copies pb and pbF.
+__global__ void grad_step_kernel(GradParts gp, float *p, uint16_t *pb, uint16_t *pbF, float *g,
                                  float *m, float *v, const uint8_t *mask, int step, float lr,
                                  float b1, float b2, float eps, float wd, float bc1, float bc2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -630,19 +652,23 @@ __global__ void grad_step_kernel(GradParts gp, float *p, uint16_t *pb, uint16_t 
   p[i] = pn;
   const uint16_t h = f2bf(pn);
   pb[i] = h;
-  const int64_t ti = mlp_tpos(i);
-  if (ti >= 0) pbT[ti] = h;
+  int64_t f0, f1;
+  mlp_fpos(i, f0, f1);
+  if (f0 >= 0) pbF[f0] = h;
+  if (f1 >= 0) pbF[f1] = h;
 }
 
-// BF16 copies of the parameters: pb in their own layout, pbT the weights
-// transposed
-__global__ void weights_bf16_kernel(const float *p, uint16_t *pb, uint16_t *pbT) {
+// BF16 copies of the parameters: pb in their own layout, pbF the weights in
+// the training pass's operand order
+__global__ void weights_bf16_kernel(const float *p, uint16_t *pb, uint16_t *pbF) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= MLP_NPARAM) return;
   const uint16_t h = f2bf(p[i]);
   pb[i] = h;
-  const int64_t ti = mlp_tpos(i);
-  if (ti >= 0) pbT[ti] = h;
+  int64_t f0, f1;
+  mlp_fpos(i, f0, f1);
+  if (f0 >= 0) pbF[f0] = h;
+  if (f1 >= 0) pbF[f1] = h;
 }
 
 // X[r][0..15] = BF16 of the z-scored features of row rows[r] (zero pad;
@@ -874,15 +900,15 @@ hipError_t gate_scatter(int64_t n2, const int64_t *orbit, const int8_t *label2, 
   hipLaunchKernelGGL(gate_scatter_kernel, dim3(nb(n2)), dim3(256), 0, s, n2, orbit, label2, label);
   return hipGetLastError();
 }
-hipError_t mlp_grad_step(const GradParts &gp, float *p, uint16_t *pb, uint16_t *pbT, float *g,
+hipError_t mlp_grad_step(const GradParts &gp, float *p, uint16_t *pb, uint16_t *pbF, float *g,
                          float *m, float *v, const uint8_t *mask, int step, float lr, float b1,
                          float b2, float eps, float wd, float bc1, float bc2, hipStream_t s) {
-  hipLaunchKernelGGL(grad_step_kernel, dim3(nb(MLP_NPARAM)), dim3(256), 0, s, gp, p, pb, pbT, g, m,
+  hipLaunchKernelGGL(grad_step_kernel, dim3(nb(MLP_NPARAM)), dim3(256), 0, s, gp, p, pb, pbF, g, m,
                      v, mask, step, lr, b1, b2, eps, wd, bc1, bc2);
   return hipGetLastError();
 }
-hipError_t mlp_weights_bf16(const float *p, uint16_t *pb, uint16_t *pbT, hipStream_t s) {
-  hipLaunchKernelGGL(weights_bf16_kernel, dim3(nb(MLP_NPARAM)), dim3(256), 0, s, p, pb, pbT);
+hipError_t mlp_weights_bf16(const float *p, uint16_t *pb, uint16_t *pbF, hipStream_t s) {
+  hipLaunchKernelGGL(weights_bf16_kernel, dim3(nb(MLP_NPARAM)), dim3(256), 0, s, p, pb, pbF);
   return hipGetLastError();
 }
 hipError_t mlp_batch_input(const float *feat, const int64_t *rows, int B, int64_t n_valid,

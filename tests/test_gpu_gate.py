@@ -6,6 +6,8 @@
     (oracle/mlp.py) on the same BF16-rounded operands: |p| within 2e-3,
     gradient normwise relative 2e-2 per parameter block;
   - one AdamW step against the oracle update applied to the device gradient;
+  - the gradient after several AdamW steps against the oracle's at the
+    trained parameters (the steps keep the weights' BF16 copies current);
   - training learns a separable rule;
   - chx_gate_classify: with a gate that is never confident every label is
     the plain integrator's (bit for bit); with a mixed gate, resumed orbits
@@ -171,6 +173,37 @@ def test_adamw_step_matches_oracle(env):
     assert d[firm].max() <= 2e-6
     assert d.max() <= 2 * lr * (1.0 + wd * np.abs(p).max())
     assert np.all(p1[M.mask() == 0] == 0.0)
+    g.close()
+
+
+def test_gradient_after_training_steps(env):
+    """The training pass reads a transposed BF16 copy of the weights that every
+    AdamW step rewrites: a gradient taken after training matches the oracle's
+    at the trained parameters."""
+    torch, P, M, O = env
+    say("case: gate gradient after AdamW steps")
+    g = P.Gate(1)
+    p = random_params(M, 14, scale=0.7)
+    F = random_features(15, 3000)
+    y = (np.random.default_rng(16).random(len(F)) < 0.5).astype(np.int8)
+    mu, istd = M.zscore_stats(F.astype(np.float64))
+    g.set(p, mu.astype(np.float32), istd.astype(np.float32))
+    g.train(F, y, epochs=2, batch=512, lr=3e-2, seed=17)  # 12 steps
+    p1, mu32, is32 = g.get()
+    moved = np.abs(p1 - p).max()
+    say(f"  largest parameter change {moved:.3e}")
+    assert moved > 1e-2
+    n = 1000
+    loss, gg = g.grad(F[:n], y[:n])
+    X = M.inputs(F[:n], mu32, is32, rounding=True)
+    lr, gr = M.loss_and_grad(p1.astype(np.float64), X, y[:n], rounding=True)
+    say(f"  loss gpu {loss:.7f} oracle {lr:.7f}")
+    assert abs(loss - lr) <= 1e-4 * max(1.0, abs(lr))
+    for name, a, b in (("W1", M.W1, M.B1), ("b1", M.B1, M.W2), ("W2", M.W2, M.B2),
+                       ("b2", M.B2, M.W3), ("W3", M.W3, M.B3), ("b3", M.B3, M.NPARAM)):
+        rel = np.linalg.norm(gg[a:b] - gr[a:b]) / max(np.linalg.norm(gr[a:b]), 1e-30)
+        say(f"  {name}: normwise rel {rel:.3e}")
+        assert rel <= 2e-2, name
     g.close()
 
 
