@@ -144,6 +144,7 @@ hipError_t batch_grad(chx_gate *g, const Acts &a, int B, const float *feat, cons
   MlpRowsArgs r;
   r.n = n;
   r.start = start;
+  r.ld = B;
   r.a = pa;
   r.c = pc;
   r.feat = feat;
@@ -170,17 +171,16 @@ hipError_t batch_grad(chx_gate *g, const Acts &a, int B, const float *feat, cons
   gp->w1 = a.work1;
   gp->w2 = a.work2;
   gp->w3 = a.work3;
-  if ((e = mlp_gemm(a.A2b, 1, MLP_H, a.dZ3b, MLP_OUTP, 1, gr + MLP_W3, MLP_OUTP, MLP_H, MLP_OUTP,
-                    B, nullptr, 0, s, a.work3, MLP_SPLITK_WORK_SMALL, EPI_NONE, nullptr, nullptr,
-                    &gp->s3)))
+  // (the row kernel's outputs are feature-major with row stride B, so both
+  // operands run along K = rows)
+  if ((e = mlp_gemm(a.A2b, B, 1, a.dZ3b, 1, B, gr + MLP_W3, MLP_OUTP, MLP_H, MLP_OUTP, B, nullptr,
+                    0, s, a.work3, MLP_SPLITK_WORK_SMALL, EPI_NONE, nullptr, nullptr, &gp->s3)))
     return e;
-  if ((e = mlp_gemm(a.A1b, 1, MLP_H, a.dZ2b, MLP_H, 1, gr + MLP_W2, MLP_H, MLP_H, MLP_H, B,
-                    nullptr, 0, s, a.work2, MLP_SPLITK_WORK, EPI_NONE, nullptr, nullptr,
-                    &gp->s2)))
+  if ((e = mlp_gemm(a.A1b, B, 1, a.dZ2b, 1, B, gr + MLP_W2, MLP_H, MLP_H, MLP_H, B, nullptr, 0, s,
+                    a.work2, MLP_SPLITK_WORK, EPI_NONE, nullptr, nullptr, &gp->s2)))
     return e;
-  return mlp_gemm(a.X, 1, MLP_INP, a.dZ1b, MLP_H, 1, gr + MLP_W1, MLP_H, MLP_INP, MLP_H, B,
-                  nullptr, 0, s, a.work1, MLP_SPLITK_WORK_SMALL, EPI_NONE, nullptr, nullptr,
-                  &gp->s1);
+  return mlp_gemm(a.X, B, 1, a.dZ1b, 1, B, gr + MLP_W1, MLP_H, MLP_INP, MLP_H, B, nullptr, 0, s,
+                  a.work1, MLP_SPLITK_WORK_SMALL, EPI_NONE, nullptr, nullptr, &gp->s1);
 }
 
 // p(chaotic) and confidence of n rows of device features.

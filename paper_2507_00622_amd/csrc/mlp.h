@@ -52,12 +52,13 @@ constexpr int64_t MLP_SPLITK_WORK_SMALL = (int64_t)64 * MLP_H * MLP_OUTP;
 // (a i + c) mod n of the batch positions start + i (-1 at or past n), their
 // z-scored inputs, the forward pass, softmax cross-entropy against labels
 // (gradient scaled by inv, loss added to loss_sum) and the activation
-// gradients; X, A1, A2, dZ3, dZ2, dZ1 (BF16) are left for the weight
+// gradients; X, A1, A2, dZ3, dZ2, dZ1 (BF16, feature-major: row r of
+// feature j at j ld + r, ld >= B a multiple of 16) are left for the weight
 // gradients and each 16-row block's column sums of dZ1 | dZ2 | dZ3 in
 // bpart[B / 16][MLP_BIAS_COLS] for mlp_bias_grad.  pbF: the weights' BF16
 // copy in MFMA operand order (mlp_weights_bf16).
 struct MlpRowsArgs {
-  int64_t n, start;
+  int64_t n, start, ld;
   uint64_t a, c;
   const float *feat, *mean, *istd;
   const int8_t *labels;

@@ -282,6 +282,12 @@ __global__ void gemm_splitk_sum_kernel(const float *work, int S, int M, int N, f
 }
 
 
+// four consecutive BF16 values as one 8-byte store (p 8-byte aligned)
+__device__ __forceinline__ void store4(uint16_t *p, const uint16_t (&h)[4]) {
+  *(uint2 *)p = make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16),
+                           (uint32_t)h[2] | ((uint32_t)h[3] << 16));
+}
+
 // Block barrier for LDS traffic only: waits for this wavefront's LDS
 // accesses, not for its global loads in flight (which __syncthreads would
 // drain); the memory clobber keeps the compiler from moving accesses across.
@@ -337,7 +343,9 @@ __device__ __forceinline__ void mlp_fpos(int64_t i, int64_t &f0, int64_t &f1) {
 // load; the MFMAs run over k in ascending order as in gemm_tile_kernel, so
 // the products equal those of separate gemm_tile_kernel launches bit for
 // bit.  The logits and the softmax are the first wavefront's.  Outputs for
-// the weight gradients: X, A1, A2, dZ3, dZ2, dZ1 (BF16, row-major); for the
+// the weight gradients: X, A1, A2, dZ3, dZ2, dZ1 (BF16) feature-major,
+// element (row r, feature j) at j ld + r, so that the weight-gradient
+// products A^T dZ read both operands along K (the rows); for the
 // bias gradients the block's column sums of dZ1, dZ2, dZ3 (FP32: per lane
 // its 4 rows in order, then the 4 lane groups in order; dZ3's 16 rows in
 // order) to bpart[block][b1 256 | b2 256 | b3 16].
@@ -379,7 +387,7 @@ __global__ void __launch_bounds__(256) train_rows_kernel(const MlpRowsArgs t) {
         (src >= 0 && k < MLP_IN) ? (t.feat[src * MLP_IN + k] - t.mean[k]) * t.istd[k] : 0.f;
     const uint16_t h = f2bf(v);
     Xs[i][k] = h;
-    t.X[(r0 + i) * MLP_INP + k] = h;
+    t.X[(int64_t)k * t.ld + r0 + i] = h;
   }
   lds_barrier();
   // layer 1 (one k-step)
@@ -397,14 +405,14 @@ __global__ void __launch_bounds__(256) train_rows_kernel(const MlpRowsArgs t) {
   for (int b = 0; b < 4; ++b) {
     const int j = cw + 16 * b + li;
     const float bj = t.p[MLP_B1 + j];
+    uint16_t h[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int i = 4 * lq + r;
       z1[b][r] += bj;
-      const uint16_t h = f2bf(gelu(z1[b][r]));
-      As[i][j] = h;
-      t.A1b[(r0 + i) * MLP_H + j] = h;
+      h[r] = f2bf(gelu(z1[b][r]));
+      As[4 * lq + r][j] = h[r];
     }
+    store4(t.A1b + (int64_t)j * t.ld + r0 + 4 * lq, h);
   }
   lds_barrier();
   // layer 2
@@ -432,8 +440,8 @@ __global__ void __launch_bounds__(256) train_rows_kernel(const MlpRowsArgs t) {
     for (int r = 0; r < 4; ++r) {
       z2[b][r] += bj;
       h2[b][r] = f2bf(gelu(z2[b][r]));
-      t.A2b[(r0 + 4 * lq + r) * MLP_H + j] = h2[b][r];
     }
+    store4(t.A2b + (int64_t)j * t.ld + r0 + 4 * lq, h2[b]);
   }
   lds_barrier();  // every wavefront has read A1
 #pragma unroll
@@ -475,7 +483,7 @@ __global__ void __launch_bounds__(256) train_rows_kernel(const MlpRowsArgs t) {
       for (int c = 0; c < MLP_OUTP; ++c) {
         const float g = c == 0 ? g0 : (c == 1 ? g1 : 0.f);
         const uint16_t h = f2bf(g);
-        t.dZ3b[(r0 + i) * MLP_OUTP + c] = h;
+        t.dZ3b[(int64_t)c * t.ld + r0 + i] = h;
         Gs[i][c] = h;
         Zs[i][c] = g;
       }
@@ -497,15 +505,15 @@ __global__ void __launch_bounds__(256) train_rows_kernel(const MlpRowsArgs t) {
       const int j = cw + 16 * b + li;
       const float4_t d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, w3b[b], zero, 0, 0, 0);
       float sum = 0.f;
+      uint16_t h[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = 4 * lq + r;
         const float g = d[r] * gelu_grad(z2[b][r]);
-        const uint16_t h = f2bf(g);
+        h[r] = f2bf(g);
         sum += g;
-        t.dZ2b[(r0 + i) * MLP_H + j] = h;
-        As[i][j] = h;
+        As[4 * lq + r][j] = h[r];
       }
+      store4(t.dZ2b + (int64_t)j * t.ld + r0 + 4 * lq, h);
       Ps2[lq][j] = sum;
     }
   }
@@ -526,13 +534,14 @@ __global__ void __launch_bounds__(256) train_rows_kernel(const MlpRowsArgs t) {
   for (int b = 0; b < 4; ++b) {
     const int j = cw + 16 * b + li;
     float sum = 0.f;
+    uint16_t h[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int i = 4 * lq + r;
       const float g = d1[b][r] * gelu_grad(z1[b][r]);
       sum += g;
-      t.dZ1b[(r0 + i) * MLP_H + j] = f2bf(g);
+      h[r] = f2bf(g);
     }
+    store4(t.dZ1b + (int64_t)j * t.ld + r0 + 4 * lq, h);
     Ps1[lq][j] = sum;
   }
   lds_barrier();
