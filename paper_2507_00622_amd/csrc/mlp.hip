@@ -53,9 +53,9 @@ __device__ __forceinline__ float gelu_grad(float z) {
 // A(i,k) = A[i*a_r + k*a_c], B(k,j) = B[k*b_r + j*b_c], both BF16; M, N, K
 // multiples of 16.  A block of 4 wavefronts computes a BM x BN tile of C,
 // (64, 64), (16, 64) or (64, 16) (rows past M are not stored).  K goes in
-// chunks of 64: the block stages the chunk of A (BM x 64) and of B
-// (64 x BN) in LDS with k contiguous (As[i][k], Bs[j][k], rows padded to
-// 72 elements against bank conflicts), reading global memory along
+// chunks of 32: the block stages the chunk of A (BM x 32) and of B
+// (32 x BN) in LDS with k contiguous (As[i][k], Bs[j][k], rows padded to
+// 40 elements against bank conflicts), reading global memory along
 // whichever index has unit stride, 8 elements (16 bytes) per load where VEC
 // says the addresses allow it, the next chunk's loads in flight during this
 // chunk's products; rows past M are staged as zeros, k past the end of the
@@ -70,7 +70,7 @@ __device__ __forceinline__ float gelu_grad(float z) {
 // split): EPI_GELU stores Z = AB + bias and its activation GELU(Z) in BF16
 // to Cb; EPI_GELU_BACK takes the product as dA and stores
 // dZ = dA GELU'(Zaux) and its BF16 copy to Cb (Zaux, Cb with C's row stride).
-constexpr int GBK = 64, GPAD = GBK + 8;
+constexpr int GBK = 32, GPAD = GBK + 8;
 
 template <int BM, int BN, bool VEC, int EPI>
 __global__ void __launch_bounds__(256) gemm_tile_kernel(const uint16_t *A, int64_t a_r,
