@@ -162,11 +162,10 @@ hipError_t batch_grad(chx_gate *g, const Acts &a, int B, const float *feat, cons
   r.dZ2b = a.dZ2b;
   r.dZ1b = a.dZ1b;
   r.bpart = a.bpart;
-  r.loss_sum = loss_sum;
   float *gr = g->g;
   hipError_t e;
   if ((e = mlp_train_rows(r, B, s))) return e;
-  if ((e = mlp_bias_grad(a.bpart, B / 16, gr, s))) return e;
+  if ((e = mlp_bias_grad(a.bpart, B / 16, gr, loss_sum, s))) return e;
   // weight gradients A^T dZ, layer 3, 2, 1, their parts left for mlp_grad_step
   gp->w1 = a.work1;
   gp->w2 = a.work2;

@@ -20,8 +20,10 @@ constexpr int64_t MLP_B2 = MLP_W2 + (int64_t)MLP_H * MLP_H;
 constexpr int64_t MLP_W3 = MLP_B2 + MLP_H;
 constexpr int64_t MLP_B3 = MLP_W3 + (int64_t)MLP_H * MLP_OUTP;
 constexpr int64_t MLP_NPARAM = MLP_B3 + MLP_OUTP;
-// bias-gradient columns of a training block's partial sums (b1 | b2 | b3)
-constexpr int MLP_BIAS_COLS = 2 * MLP_H + MLP_OUTP;
+// columns of a training block's partial sums: b1 | b2 | b3 | loss, padded
+// to a multiple of 16
+constexpr int MLP_BIAS_LOSS = 2 * MLP_H + MLP_OUTP;
+constexpr int MLP_BIAS_COLS = MLP_BIAS_LOSS + 16;
 // regions of the training pass's BF16 weights in MFMA operand order (pbF)
 constexpr int64_t MLP_F_W1 = 0;                                      // W1, forward
 constexpr int64_t MLP_F_W2 = MLP_F_W1 + (int64_t)MLP_INP * MLP_H;    // W2, forward
@@ -51,11 +53,11 @@ constexpr int64_t MLP_SPLITK_WORK_SMALL = (int64_t)64 * MLP_H * MLP_OUTP;
 // The row-local part of a training batch of B rows (multiple of 16): rows
 // (a i + c) mod n of the batch positions start + i (-1 at or past n), their
 // z-scored inputs, the forward pass, softmax cross-entropy against labels
-// (gradient scaled by inv, loss added to loss_sum) and the activation
+// (gradient scaled by inv) and the activation
 // gradients; X, A1, A2, dZ3, dZ2, dZ1 (BF16, feature-major: row r of
 // feature j at j ld + r, ld >= B a multiple of 16) are left for the weight
-// gradients and each 16-row block's column sums of dZ1 | dZ2 | dZ3 in
-// bpart[B / 16][MLP_BIAS_COLS] for mlp_bias_grad.  pbF: the weights' BF16
+// gradients and each 16-row block's column sums of dZ1 | dZ2 | dZ3 and its
+// loss in bpart[B / 16][MLP_BIAS_COLS] for mlp_bias_grad.  pbF: the weights' BF16
 // copy in MFMA operand order (mlp_weights_bf16).
 struct MlpRowsArgs {
   int64_t n, start, ld;
@@ -66,11 +68,13 @@ struct MlpRowsArgs {
   const float *p;
   const uint16_t *pb, *pbF;
   uint16_t *X, *A1b, *A2b, *dZ3b, *dZ2b, *dZ1b;
-  float *bpart, *loss_sum;
+  float *bpart;
 };
 hipError_t mlp_train_rows(const MlpRowsArgs &r, int B, hipStream_t s);
-// grad's b1, b2, b3 = the sums of the nblk blocks' partials (in order)
-hipError_t mlp_bias_grad(const float *bpart, int nblk, float *grad, hipStream_t s);
+// grad's b1, b2, b3 = the sums of the nblk blocks' partials (in order);
+// their loss sum is added to *loss_sum (if not null)
+hipError_t mlp_bias_grad(const float *bpart, int nblk, float *grad, float *loss_sum,
+                         hipStream_t s);
 hipError_t mlp_apply_mask(float *p, const uint8_t *mask, int64_t n, hipStream_t s);
 hipError_t mlp_fill(float *p, int64_t n, float v, hipStream_t s);
 hipError_t gate_select(int64_t n, const int *status, const int8_t *label1, const float *pc,

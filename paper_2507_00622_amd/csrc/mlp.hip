@@ -332,8 +332,8 @@ __device__ __forceinline__ void mlp_fpos(int64_t i, int64_t &f0, int64_t &f1) {
 //     BF16 inputs X;
 //   Z1 = X W1 + b1, A1 = GELU(Z1); Z2 = A1 W2 + b2, A2 = GELU(Z2);
 //   Z3 = A2 W3 + b3; softmax cross-entropy on the two logits: dZ3 =
-//     (softmax - onehot(label)) inv, the loss summed into loss_sum (rows
-//     without a label 0 or 1 contribute nothing);
+//     (softmax - onehot(label)) inv, the block's loss (rows without a
+//     label 0 or 1 contribute nothing);
 //   dZ2 = (dZ3 W3^T) GELU'(Z2); dZ1 = (dZ2 W2^T) GELU'(Z1).
 // Wavefront w computes columns 64w .. 64w + 63 of the 256-wide layers (four
 // 16 x 16 tiles) and keeps Z1, Z2 in registers; the activation entering
@@ -348,7 +348,7 @@ __device__ __forceinline__ void mlp_fpos(int64_t i, int64_t &f0, int64_t &f1) {
 // products A^T dZ read both operands along K (the rows); for the
 // bias gradients the block's column sums of dZ1, dZ2, dZ3 (FP32: per lane
 // its 4 rows in order, then the 4 lane groups in order; dZ3's 16 rows in
-// order) to bpart[block][b1 256 | b2 256 | b3 16].
+// order) and its loss to bpart[block][b1 256 | b2 256 | b3 16 | loss 1].
 constexpr int TR_LD = MLP_H + 8;  // LDS row of a 256-wide BF16 activation
 __global__ void __launch_bounds__(256) train_rows_kernel(const MlpRowsArgs t) {
   __shared__ __align__(16) uint16_t Xs[16][24];
@@ -489,7 +489,7 @@ __global__ void __launch_bounds__(256) train_rows_kernel(const MlpRowsArgs t) {
       }
     }
     for (int off = 8; off > 0; off >>= 1) l += __shfl_down(l, off, 64);
-    if (lane == 0 && t.loss_sum) atomicAdd(t.loss_sum, l);
+    if (lane == 0) bp[MLP_BIAS_LOSS] = l;
   }
   lds_barrier();
   if (tid < MLP_OUTP) {
@@ -548,13 +548,13 @@ __global__ void __launch_bounds__(256) train_rows_kernel(const MlpRowsArgs t) {
   bp[tid] = ((Ps1[0][tid] + Ps1[1][tid]) + Ps1[2][tid]) + Ps1[3][tid];
 }
 
-// Bias gradients from the blocks' column sums of train_rows_kernel:
-// column col of bpart[nblk][528] summed over the blocks; thread group g of
-// a block of 256 adds blocks g, g + 16, g + 32, ... in order, then the 16
-// group sums are added in order.  Columns 0..255 go to b1, 256..511 to b2,
-// 512..527 to b3.
+// Bias gradients and loss from the blocks' sums of train_rows_kernel:
+// column col of bpart[nblk][MLP_BIAS_COLS] summed over the blocks; thread
+// group g of a block of 256 adds blocks g, g + 16, g + 32, ... in order,
+// then the 16 group sums are added in order.  Columns 0..255 go to b1,
+// 256..511 to b2, 512..527 to b3, the loss column is added to *loss_sum.
 __global__ void __launch_bounds__(256) bias_grad_kernel(const float *bpart, int nblk,
-                                                        float *grad) {
+                                                        float *grad, float *loss_sum) {
   __shared__ float red[16][17];
   const int c = threadIdx.x & 15, g = threadIdx.x >> 4;
   const int col = blockIdx.x * 16 + c;
@@ -565,10 +565,14 @@ __global__ void __launch_bounds__(256) bias_grad_kernel(const float *bpart, int 
   if (g == 0) {
     float t = 0.f;
     for (int q = 0; q < 16; ++q) t += red[q][c];
-    const int64_t dst = col < MLP_H ? MLP_B1 + col
-                                    : (col < 2 * MLP_H ? MLP_B2 + (col - MLP_H)
-                                                       : MLP_B3 + (col - 2 * MLP_H));
-    grad[dst] = t;
+    if (col < 2 * MLP_H + MLP_OUTP) {
+      const int64_t dst = col < MLP_H ? MLP_B1 + col
+                                      : (col < 2 * MLP_H ? MLP_B2 + (col - MLP_H)
+                                                         : MLP_B3 + (col - 2 * MLP_H));
+      grad[dst] = t;
+    } else if (col == MLP_BIAS_LOSS && loss_sum) {
+      *loss_sum += t;
+    }
   }
 }
 
@@ -882,10 +886,11 @@ hipError_t mlp_train_rows(const MlpRowsArgs &r, int B, hipStream_t s) {
   hipLaunchKernelGGL(train_rows_kernel, dim3((unsigned)(B / 16)), dim3(256), 0, s, r);
   return hipGetLastError();
 }
-hipError_t mlp_bias_grad(const float *bpart, int nblk, float *grad, hipStream_t s) {
+hipError_t mlp_bias_grad(const float *bpart, int nblk, float *grad, float *loss_sum,
+                         hipStream_t s) {
   if (nblk <= 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(bias_grad_kernel, dim3(MLP_BIAS_COLS / 16), dim3(256), 0, s, bpart, nblk,
-                     grad);
+                     grad, loss_sum);
   return hipGetLastError();
 }
 hipError_t mlp_fill(float *p, int64_t n, float v, hipStream_t s) {

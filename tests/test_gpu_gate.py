@@ -8,7 +8,7 @@
   - one AdamW step against the oracle update applied to the device gradient;
   - the gradient after several AdamW steps against the oracle's at the
     trained parameters (the steps keep the weights' BF16 copies current);
-  - training learns a separable rule;
+  - training learns a separable rule, and is reproducible bit for bit;
   - chx_gate_classify: with a gate that is never confident every label is
     the plain integrator's (bit for bit); with a mixed gate, resumed orbits
     carry the plain label and gated ones the gate's label.
@@ -205,6 +205,23 @@ def test_gradient_after_training_steps(env):
         say(f"  {name}: normwise rel {rel:.3e}")
         assert rel <= 2e-2, name
     g.close()
+
+
+def test_training_is_reproducible(env):
+    """Every sum of the training pass runs in a fixed order (split-K parts,
+    bias and loss sums), so two runs from the same state agree bit for bit."""
+    torch, P, M, O = env
+    say("case: training twice from the same state")
+    F = random_features(18, 5000)
+    y = (np.random.default_rng(19).random(len(F)) < 0.5).astype(np.int8)
+    out = []
+    for _ in range(2):
+        g = P.Gate(20)
+        losses = g.train(F, y, epochs=2, batch=1024, lr=1e-2, seed=21)
+        out.append((np.asarray(losses), g.get()[0]))
+        g.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
 
 
 def test_training_learns_a_rule(env):
