@@ -326,7 +326,7 @@ __device__ __forceinline__ void mlp_fpos(int64_t i, int64_t &f0, int64_t &f1) {
   }
 }
 
-// The row-local part of one training batch, 16 rows per block of 4
+// The row-local part of one training batch, 16 rows per block of TR_W
 // wavefronts (the weight gradients, sums over all rows, follow as products):
 //   rows: batch position i -> (a i + c) mod n (-1 at or past n), z-scored
 //     BF16 inputs X;
@@ -335,8 +335,8 @@ __device__ __forceinline__ void mlp_fpos(int64_t i, int64_t &f0, int64_t &f1) {
 //     (softmax - onehot(label)) inv, the block's loss (rows without a
 //     label 0 or 1 contribute nothing);
 //   dZ2 = (dZ3 W3^T) GELU'(Z2); dZ1 = (dZ2 W2^T) GELU'(Z1).
-// Wavefront w computes columns 64w .. 64w + 63 of the 256-wide layers (four
-// 16 x 16 tiles) and keeps Z1, Z2 in registers; the activation entering
+// Wavefront w of TR_W computes columns 16 TR_T w .. 16 TR_T (w + 1) - 1 of
+// the 256-wide layers (TR_T 16 x 16 tiles) and keeps Z1, Z2 in registers; the activation entering
 // each product waits in LDS (16 x 256 BF16).  The forward products read
 // the transposed BF16 weights WT, the backward ones the weights W, so that
 // each lane's MFMA operand (4 consecutive k of one column) is one 8-byte
@@ -350,7 +350,10 @@ __device__ __forceinline__ void mlp_fpos(int64_t i, int64_t &f0, int64_t &f1) {
 // its 4 rows in order, then the 4 lane groups in order; dZ3's 16 rows in
 // order) and its loss to bpart[block][b1 256 | b2 256 | b3 16 | loss 1].
 constexpr int TR_LD = MLP_H + 8;  // LDS row of a 256-wide BF16 activation
-__global__ void __launch_bounds__(256) train_rows_kernel(const MlpRowsArgs t) {
+// wavefronts per block and 16-column tiles per wavefront of the 256-wide
+// layers
+constexpr int TR_W = 8, TR_T = 16 / TR_W;
+__global__ void __launch_bounds__(64 * TR_W) train_rows_kernel(const MlpRowsArgs t) {
   __shared__ __align__(16) uint16_t Xs[16][24];
   __shared__ __align__(16) uint16_t Gs[16][24];
   __shared__ __align__(16) uint16_t As[16][TR_LD];
@@ -361,23 +364,23 @@ __global__ void __launch_bounds__(256) train_rows_kernel(const MlpRowsArgs t) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lq = lane >> 4;
   const int64_t r0 = (int64_t)blockIdx.x * 16;
-  const int cw = wave * 64;
+  const int cw = wave * 16 * TR_T;
   const float4_t zero = {0.f, 0.f, 0.f, 0.f};
   // the weight operands do not depend on the rows: W2's and W3's go out
   // first, W2's backward ones once the forward product is done, each in
   // flight under the work before its product
-  short4_t wf[MLP_H / 16][4], w3f[MLP_H / 16], w3b[4];
+  short4_t wf[MLP_H / 16][TR_T], w3f[MLP_H / 16], w3b[TR_T];
 #pragma unroll
-  for (int b = 0; b < 4; ++b)
-    w3b[b] = *(const short4_t *)&t.pbF[MLP_F_W3T + ((4 * wave + b) * 64 + lane) * 4];
+  for (int b = 0; b < TR_T; ++b)
+    w3b[b] = *(const short4_t *)&t.pbF[MLP_F_W3T + ((TR_T * wave + b) * 64 + lane) * 4];
 #pragma unroll
   for (int ks = 0; ks < MLP_H / 16; ++ks) {
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
-      wf[ks][b] = *(const short4_t *)&t.pbF[MLP_F_W2 + (((4 * wave + b) * 16 + ks) * 64 + lane) * 4];
+    for (int b = 0; b < TR_T; ++b)
+      wf[ks][b] = *(const short4_t *)&t.pbF[MLP_F_W2 + (((TR_T * wave + b) * 16 + ks) * 64 + lane) * 4];
     w3f[ks] = *(const short4_t *)&t.pbF[MLP_F_W3 + (ks * 64 + lane) * 4];
   }
-  {
+  if (tid < 256) {
     const int i = tid >> 4, k = tid & 15;
     const int64_t pos = t.start + r0 + i;
     const int64_t src =
@@ -391,18 +394,18 @@ __global__ void __launch_bounds__(256) train_rows_kernel(const MlpRowsArgs t) {
   }
   lds_barrier();
   // layer 1 (one k-step)
-  float4_t z1[4], z2[4];
+  float4_t z1[TR_T], z2[TR_T];
   {
     const short4_t x = *(const short4_t *)&Xs[li][4 * lq];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < TR_T; ++b) {
       const short4_t w =
-          *(const short4_t *)&t.pbF[MLP_F_W1 + ((4 * wave + b) * 64 + lane) * 4];
+          *(const short4_t *)&t.pbF[MLP_F_W1 + ((TR_T * wave + b) * 64 + lane) * 4];
       z1[b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, w, zero, 0, 0, 0);
     }
   }
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
+  for (int b = 0; b < TR_T; ++b) {
     const int j = cw + 16 * b + li;
     const float bj = t.p[MLP_B1 + j];
     uint16_t h[4];
@@ -417,23 +420,23 @@ __global__ void __launch_bounds__(256) train_rows_kernel(const MlpRowsArgs t) {
   lds_barrier();
   // layer 2
 #pragma unroll
-  for (int b = 0; b < 4; ++b) z2[b] = zero;
+  for (int b = 0; b < TR_T; ++b) z2[b] = zero;
 #pragma unroll
   for (int ks = 0; ks < MLP_H / 16; ++ks) {
     const short4_t x = *(const short4_t *)&As[li][16 * ks + 4 * lq];
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < TR_T; ++b)
       z2[b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, wf[ks][b], z2[b], 0, 0, 0);
   }
 #pragma unroll
   for (int ks = 0; ks < MLP_H / 16; ++ks)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < TR_T; ++b)
       wf[ks][b] =
-          *(const short4_t *)&t.pbF[MLP_F_W2T + (((4 * wave + b) * 16 + ks) * 64 + lane) * 4];
-  uint16_t h2[4][4];
+          *(const short4_t *)&t.pbF[MLP_F_W2T + (((TR_T * wave + b) * 16 + ks) * 64 + lane) * 4];
+  uint16_t h2[TR_T][4];
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
+  for (int b = 0; b < TR_T; ++b) {
     const int j = cw + 16 * b + li;
     const float bj = t.p[MLP_B2 + j];
 #pragma unroll
@@ -445,7 +448,7 @@ __global__ void __launch_bounds__(256) train_rows_kernel(const MlpRowsArgs t) {
   }
   lds_barrier();  // every wavefront has read A1
 #pragma unroll
-  for (int b = 0; b < 4; ++b)
+  for (int b = 0; b < TR_T; ++b)
 #pragma unroll
     for (int r = 0; r < 4; ++r) As[4 * lq + r][cw + 16 * b + li] = h2[b][r];
   lds_barrier();
@@ -501,7 +504,7 @@ __global__ void __launch_bounds__(256) train_rows_kernel(const MlpRowsArgs t) {
   {
     const short4_t x = *(const short4_t *)&Gs[li][4 * lq];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < TR_T; ++b) {
       const int j = cw + 16 * b + li;
       const float4_t d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, w3b[b], zero, 0, 0, 0);
       float sum = 0.f;
@@ -518,20 +521,21 @@ __global__ void __launch_bounds__(256) train_rows_kernel(const MlpRowsArgs t) {
     }
   }
   lds_barrier();
-  bp[MLP_H + tid] = ((Ps2[0][tid] + Ps2[1][tid]) + Ps2[2][tid]) + Ps2[3][tid];
+  if (tid < MLP_H)
+    bp[MLP_H + tid] = ((Ps2[0][tid] + Ps2[1][tid]) + Ps2[2][tid]) + Ps2[3][tid];
   // dZ1 = (dZ2 W2^T) GELU'(Z1)
-  float4_t d1[4];
+  float4_t d1[TR_T];
 #pragma unroll
-  for (int b = 0; b < 4; ++b) d1[b] = zero;
+  for (int b = 0; b < TR_T; ++b) d1[b] = zero;
 #pragma unroll
   for (int ks = 0; ks < MLP_H / 16; ++ks) {
     const short4_t x = *(const short4_t *)&As[li][16 * ks + 4 * lq];
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < TR_T; ++b)
       d1[b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, wf[ks][b], d1[b], 0, 0, 0);
   }
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
+  for (int b = 0; b < TR_T; ++b) {
     const int j = cw + 16 * b + li;
     float sum = 0.f;
     uint16_t h[4];
@@ -545,7 +549,7 @@ __global__ void __launch_bounds__(256) train_rows_kernel(const MlpRowsArgs t) {
     Ps1[lq][j] = sum;
   }
   lds_barrier();
-  bp[tid] = ((Ps1[0][tid] + Ps1[1][tid]) + Ps1[2][tid]) + Ps1[3][tid];
+  if (tid < MLP_H) bp[tid] = ((Ps1[0][tid] + Ps1[1][tid]) + Ps1[2][tid]) + Ps1[3][tid];
 }
 
 // Bias gradients and loss from the blocks' sums of train_rows_kernel:
@@ -883,7 +887,7 @@ hipError_t mlp_gemm(const uint16_t *A, int64_t a_r, int64_t a_c, const uint16_t 
 
 hipError_t mlp_train_rows(const MlpRowsArgs &r, int B, hipStream_t s) {
   if (B <= 0 || B % 16) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(train_rows_kernel, dim3((unsigned)(B / 16)), dim3(256), 0, s, r);
+  hipLaunchKernelGGL(train_rows_kernel, dim3((unsigned)(B / 16)), dim3(64 * TR_W), 0, s, r);
   return hipGetLastError();
 }
 hipError_t mlp_bias_grad(const float *bpart, int nblk, float *grad, float *loss_sum,
