@@ -12,7 +12,8 @@ integrates both energies as one ensemble.
 
 value = orbit-steps per second over the timed passes (inputs resident in
 HBM).  roofline: the integration kernel's algorithmic FP64 flops per launch
-(flop model in the design doc) divided by its mean launch duration measured with
+(model_flops_hh: state, tangent vectors, LD and checkpoint work per
+orbit-step, FMA = 2) divided by its mean launch duration measured with
 HIP events on the stream it runs on.  cpu_baseline: the oracle on this
 host's cores on a bounded sample of the same workload.
 """
@@ -1457,8 +1458,9 @@ def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this path has no multi-GPU form "
-              "(orbits are independent; the sharding design is in DESIGN.md).",
-              file=sys.stderr)
+              "(orbits are independent: each GPU would integrate its own contiguous "
+              "share of the orbit list and the results would be gathered once at the "
+              "end).", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
