@@ -336,13 +336,13 @@ __device__ __forceinline__ void mlp_fpos(int64_t i, int64_t &f0, int64_t &f1) {
 //     label 0 or 1 contribute nothing);
 //   dZ2 = (dZ3 W3^T) GELU'(Z2); dZ1 = (dZ2 W2^T) GELU'(Z1).
 // Wavefront w of TR_W computes columns 16 TR_T w .. 16 TR_T (w + 1) - 1 of
-// the 256-wide layers (TR_T 16 x 16 tiles) and keeps Z1, Z2 in registers; the activation entering
-// each product waits in LDS (16 x 256 BF16).  The forward products read
-// the transposed BF16 weights WT, the backward ones the weights W, so that
-// each lane's MFMA operand (4 consecutive k of one column) is one 8-byte
-// load; the MFMAs run over k in ascending order as in gemm_tile_kernel, so
-// the products equal those of separate gemm_tile_kernel launches bit for
-// bit.  The logits and the softmax are the first wavefront's.  Outputs for
+// the 256-wide layers (TR_T 16 x 16 tiles) and keeps Z1, Z2 in registers;
+// the activation entering each product waits in LDS (16 x 256 BF16).  The
+// weights come from the operand-order BF16 copy pbF, one coalesced 8-byte
+// load per lane and operand; the MFMAs run over k in ascending order as in
+// gemm_tile_kernel, so the products equal those of separate
+// gemm_tile_kernel launches bit for bit.  Block barriers wait for LDS only.
+// The logits and the softmax are the first wavefront's.  Outputs for
 // the weight gradients: X, A1, A2, dZ3, dZ2, dZ1 (BF16) feature-major,
 // element (row r, feature j) at j ld + r, so that the weight-gradient
 // products A^T dZ read both operands along K (the rows); for the
@@ -377,7 +377,8 @@ __global__ void __launch_bounds__(64 * TR_W) train_rows_kernel(const MlpRowsArgs
   for (int ks = 0; ks < MLP_H / 16; ++ks) {
 #pragma unroll
     for (int b = 0; b < TR_T; ++b)
-      wf[ks][b] = *(const short4_t *)&t.pbF[MLP_F_W2 + (((TR_T * wave + b) * 16 + ks) * 64 + lane) * 4];
+      wf[ks][b] =
+          *(const short4_t *)&t.pbF[MLP_F_W2 + (((TR_T * wave + b) * 16 + ks) * 64 + lane) * 4];
     w3f[ks] = *(const short4_t *)&t.pbF[MLP_F_W3 + (ks * 64 + lane) * 4];
   }
   if (tid < 256) {
