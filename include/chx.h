@@ -504,6 +504,18 @@ chx_status chx_gate_classify(const chx_gate *g, const chx_system *sys, const dou
                              uint8_t *source_out, float *confidence_out,
                              chx_gate_stats *stats);
 
+/* Releases what the library keeps on the devices between calls: the code
+ * objects of user-supplied systems (CHX_SYS_CUSTOM, CHX_SYS_CUSTOM_GENERAL),
+ * loaded on each device that ran one.  Each such device is synchronised
+ * first; the compiled code stays cached in host memory and is loaded again
+ * on its next use, so ensembles and calls made afterwards work as before.
+ * Everything else the library allocates lives for one call (or for an
+ * ensemble or gate, which its owner destroys), so there is nothing else to
+ * release.  Library housekeeping, not an operation of the paper.  No other
+ * call of the library may run concurrently.  CHX_ERR_DEVICE if a device
+ * call fails (the remaining code objects are still unloaded). */
+chx_status chx_shutdown(void);
+
 /* Message for the last non-OK status on this thread ("" if none). */
 const char *chx_last_error(void);
 /* Library version string. */

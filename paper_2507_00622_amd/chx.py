@@ -36,7 +36,7 @@ EXPORTS = [
     "chx_last_error", "chx_version", "chx_struct_size", "chx_integrate_batched",
     "chx_ensemble_subset", "chx_gate_create", "chx_gate_destroy", "chx_gate_train",
     "chx_gate_grad", "chx_gate_infer", "chx_gate_get", "chx_gate_set", "chx_gate_features",
-    "chx_gate_classify", "chx_ld_indicators", "chx_integrate_ensemble_noalloc",
+    "chx_gate_classify", "chx_ld_indicators", "chx_integrate_ensemble_noalloc", "chx_shutdown",
 ]
 GATE_NFEAT, GATE_NPARAM = 6, 74256
 
@@ -131,6 +131,7 @@ def lib():
         L.chx_ic_quartic.argtypes = [S, P, i64, P, u32, P]
         L.chx_last_error.restype = C.c_char_p
         L.chx_version.restype = C.c_char_p
+        L.chx_shutdown.argtypes = []
         L.chx_integrate_batched.argtypes = [C.POINTER(_BatchItem), i32, O, R,
                                             C.POINTER(_BatchStats)]
         L.chx_struct_size.argtypes = [i32]
@@ -713,3 +714,9 @@ class Gate:
 
 def version():
     return lib().chx_version().decode()
+
+
+def shutdown():
+    """Unloads the user-system code objects from the devices (chx_shutdown);
+    later calls load them again."""
+    _check(lib().chx_shutdown())

@@ -673,6 +673,13 @@ void chx_options_default(chx_options *o) {
 const char *chx_last_error(void) { return g_err.c_str(); }
 const char *chx_version(void) { return "libchx 0.1 (gfx950)"; }
 
+chx_status chx_shutdown(void) {
+  g_err.clear();
+  const hipError_t e = custom_unload_all();
+  if (e != hipSuccess) return dev_fail(e, "unload user-system code objects");
+  return CHX_OK;
+}
+
 size_t chx_struct_size(int32_t which) {
   switch (which) {
   case 0: return sizeof(chx_system);

@@ -324,14 +324,43 @@ hipError_t load(Program *pg, Loaded **out) {
   if (e != hipSuccess) return e;
   Loaded &l = pg->dev[d];
   if (!l.mod) {
-    if ((e = hipModuleLoadData(&l.mod, pg->code.data())) != hipSuccess) return e;
-    if ((e = hipModuleGetFunction(&l.kernel, l.mod, pg->lowered.c_str())) != hipSuccess) return e;
-    if ((e = hipModuleGetFunction(&l.init, l.mod, "chx_custom_init")) != hipSuccess) return e;
+    if ((e = hipModuleLoadData(&l.mod, pg->code.data())) != hipSuccess) {
+      l = Loaded();
+      return e;
+    }
+    if ((e = hipModuleGetFunction(&l.kernel, l.mod, pg->lowered.c_str())) != hipSuccess ||
+        (e = hipModuleGetFunction(&l.init, l.mod, "chx_custom_init")) != hipSuccess) {
+      (void)hipModuleUnload(l.mod);
+      l = Loaded();
+      return e;
+    }
   }
   *out = &l;
   return hipSuccess;
 }
 }  // namespace
+
+// Unloads every user-system code object from each device it was loaded on,
+// after that device's work has finished; the compiled code stays cached
+// and is loaded again on its next use.
+hipError_t custom_unload_all() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  int cur = 0;
+  hipError_t e = hipGetDevice(&cur), first = hipSuccess;
+  if (e != hipSuccess) return e;
+  for (auto &kv : g_progs) {
+    for (auto &dl : kv.second->dev) {
+      if (!dl.second.mod) continue;
+      hipError_t u = hipSetDevice(dl.first);
+      if (u == hipSuccess) u = hipDeviceSynchronize();
+      if (u == hipSuccess) u = hipModuleUnload(dl.second.mod);
+      if (u != hipSuccess && first == hipSuccess) first = u;
+    }
+    kv.second->dev.clear();
+  }
+  e = hipSetDevice(cur);
+  return first != hipSuccess ? first : e;
+}
 
 // H(0) and the LD integrand at t = 0 of every active orbit (after the
 // built-in set-up kernel).

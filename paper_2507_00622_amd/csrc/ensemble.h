@@ -80,5 +80,6 @@ chx_status custom_prepare(const std::string &src, int ndof, bool general, const 
 hipError_t custom_init(void *handle, const chx::StepArgs &a, hipStream_t s);
 hipError_t custom_launch(void *handle, bool general, const Plan &pl, const chx::StepArgs &a,
                          int block, hipStream_t s);
+hipError_t custom_unload_all();
 }  // namespace host
 }  // namespace chx

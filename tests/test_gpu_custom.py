@@ -164,6 +164,34 @@ def test_custom_henon_heiles(env, integ):
     compare(g, o, sel, 1e-3 if integ == "dop853_adaptive" else 1e-9, integ)
 
 
+def test_shutdown_unloads_and_next_call_reloads(env):
+    """chx_shutdown unloads the user-system code objects; an ensemble created
+    before it and a new call after it still run, with the same results."""
+    torch, P, O = env
+    say("case: chx_shutdown between calls of a custom Henon-Heiles system")
+    x0, mask = O.hh_grid(0.125, 12, 12)
+    w0 = S.deviation_vectors(72, len(x0), 2, 4)
+    kw = dict(dt=0.01, T=20.0, indicators=ALL, gali_kmax=2, n_lyap=4)
+    sysc = P.custom(2, HH)
+    a = run_gpu(env, sysc, x0, mask, w0, **kw)
+    xd = torch.as_tensor(x0, device="cuda")
+    md = torch.as_tensor(mask, device="cuda")
+    wd = torch.as_tensor(w0, device="cuda")
+    e = P.Ensemble(sysc, xd, mask=md, w0=wd, steps_per_launch=500, **kw)
+    e.advance(1000)
+    torch.cuda.synchronize()
+    P.shutdown()
+    e.advance()
+    r = {k: v.cpu().numpy() for k, v in e.results().items()}
+    e.close()
+    P.shutdown()
+    b = run_gpu(env, sysc, x0, mask, w0, **kw)
+    for k in a:
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+        if k in r:
+            assert np.array_equal(a[k], r[k], equal_nan=True), k
+
+
 def test_custom_quartic_with_parameter(env):
     torch, P, O = env
     say("case: custom quartic N=3, eps=0.1 as a parameter, Lyapunov spectrum + GALI, T=50")
