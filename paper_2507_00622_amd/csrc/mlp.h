@@ -46,9 +46,9 @@ hipError_t mlp_gemm(const uint16_t *A, int64_t a_r, int64_t a_c, const uint16_t 
 // With parts given (no bias, no accumulate, ldc == N): a product split over
 // K leaves its parts in work[z][M][N] for the caller to add and *parts = S
 // (the number of parts); with *parts == 1 the product is in C.
-// Split-K workspaces of the training pass (floats): up to 16 parts of the
+// Split-K workspaces of the training pass (floats): up to 32 parts of the
 // 256 x 256 weight gradient, 64 of the 16 x 256 and 256 x 16 ones
-constexpr int64_t MLP_SPLITK_WORK = (int64_t)16 * MLP_H * MLP_H;
+constexpr int64_t MLP_SPLITK_WORK = (int64_t)32 * MLP_H * MLP_H;
 constexpr int64_t MLP_SPLITK_WORK_SMALL = (int64_t)64 * MLP_H * MLP_OUTP;
 // The row-local part of a training batch of B rows (multiple of 16): rows
 // (a i + c) mod n of the batch positions start + i (-1 at or past n), their

@@ -837,15 +837,15 @@ hipError_t mlp_gemm(const uint16_t *A, int64_t a_r, int64_t a_c, const uint16_t 
   const int BM = BN == 64 && M == 16 ? 16 : 64;
   const int64_t gm = (M + BM - 1) / BM, gn = N / BN;
   if (gm > 65535) return hipErrorInvalidValue;
-  // split K (a workspace given) until about 256 blocks, each part at least
-  // two chunks
+  // split K (a workspace given) until about 512 blocks (two per CU), each
+  // part at least two chunks
   const int chunks = (K + GBK - 1) / GBK;
   if (epi < EPI_NONE || epi > EPI_GELU_BACK ||
       (epi != EPI_NONE && (!Cb || (epi == EPI_GELU_BACK && !Zaux) || accumulate)) ||
       (parts && (bias || accumulate || ldc != N)))
     return hipErrorInvalidValue;
   int S = 1;
-  while (epi == EPI_NONE && work && gm * gn * S < 256 && chunks >= 4 * S &&
+  while (epi == EPI_NONE && work && gm * gn * S < 512 && chunks >= 4 * S &&
          (int64_t)2 * S * M * N <= work_len)
     S *= 2;
   const int cpc = (chunks + S - 1) / S;
