@@ -255,17 +255,17 @@ __global__ void __launch_bounds__(256) gemm_tile_kernel(const uint16_t *A, int64
 }
 
 // t = t + p[0] + p[stride] + ... + p[(count - 1) stride], added in that
-// order; the loads go out 8 at a time ahead of the additions.
+// order; the loads go out G at a time ahead of the additions.
+template <int G = 8>
 __device__ __forceinline__ float ordered_sum(float t, const float *p, int64_t stride, int count) {
-  int c = 0;
-  for (; c + 8 <= count; c += 8) {
-    float v[8];
+  for (int c = 0; c < count; c += G) {
+    float v[G];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = p[(int64_t)(c + e) * stride];
+    for (int e = 0; e < G; ++e) v[e] = c + e < count ? p[(int64_t)(c + e) * stride] : 0.f;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) t += v[e];
+    for (int e = 0; e < G; ++e)
+      if (c + e < count) t += v[e];
   }
-  for (; c < count; ++c) t += p[(int64_t)c * stride];
   return t;
 }
 
@@ -275,7 +275,7 @@ __global__ void gemm_splitk_sum_kernel(const float *work, int S, int M, int N, f
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)M * N) return;
   const int i = (int)(t / N), j = (int)(t % N);
-  float v = ordered_sum(0.f, work + t, (int64_t)M * N, S);
+  float v = ordered_sum<>(0.f, work + t, (int64_t)M * N, S);
   if (bias) v += bias[j];
   float *dst = C + (int64_t)i * ldc + j;
   *dst = accumulate ? *dst + v : v;
@@ -564,7 +564,7 @@ __global__ void __launch_bounds__(256) bias_grad_kernel(const float *bpart, int 
   const int c = threadIdx.x & 15, g = threadIdx.x >> 4;
   const int col = blockIdx.x * 16 + c;
   const int cnt = g < nblk ? (nblk - g + 15) / 16 : 0;
-  red[g][c] = ordered_sum(0.f, bpart + (int64_t)g * MLP_BIAS_COLS + col,
+  red[g][c] = ordered_sum<>(0.f, bpart + (int64_t)g * MLP_BIAS_COLS + col,
                           (int64_t)16 * MLP_BIAS_COLS, cnt);
   __syncthreads();
   if (g == 0) {
@@ -651,12 +651,13 @@ __global__ void grad_step_kernel(GradParts gp, float *p, uint16_t *pb, uint16_t 
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= MLP_NPARAM) return;
   float gi;
+  // (up to 32 parts: all loads in flight at once)
   if (i < MLP_B1 && gp.s1 > 1)
-    gi = ordered_sum(0.f, gp.w1 + (i - MLP_W1), MLP_B1 - MLP_W1, gp.s1);
+    gi = ordered_sum<32>(0.f, gp.w1 + (i - MLP_W1), MLP_B1 - MLP_W1, gp.s1);
   else if (i >= MLP_W2 && i < MLP_B2 && gp.s2 > 1)
-    gi = ordered_sum(0.f, gp.w2 + (i - MLP_W2), MLP_B2 - MLP_W2, gp.s2);
+    gi = ordered_sum<32>(0.f, gp.w2 + (i - MLP_W2), MLP_B2 - MLP_W2, gp.s2);
   else if (i >= MLP_W3 && i < MLP_B3 && gp.s3 > 1)
-    gi = ordered_sum(0.f, gp.w3 + (i - MLP_W3), MLP_B3 - MLP_W3, gp.s3);
+    gi = ordered_sum<32>(0.f, gp.w3 + (i - MLP_W3), MLP_B3 - MLP_W3, gp.s3);
   else
     gi = g[i];
   g[i] = gi;
