@@ -651,7 +651,8 @@ __global__ void grad_step_kernel(GradParts gp, float *p, uint16_t *pb, uint16_t 
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= MLP_NPARAM) return;
   float gi;
-  // (up to 32 parts: all loads in flight at once)
+  // (32 parts' loads in flight at a time: the 256 x 256 gradient has up to
+  // 32 parts, the 16-wide ones up to 64)
   if (i < MLP_B1 && gp.s1 > 1)
     gi = ordered_sum<32>(0.f, gp.w1 + (i - MLP_W1), MLP_B1 - MLP_W1, gp.s1);
   else if (i >= MLP_W2 && i < MLP_B2 && gp.s2 > 1)
