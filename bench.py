@@ -1446,7 +1446,7 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=2048,
                     help="orbits in the oracle sample (strided over the workload)")
     ap.add_argument("--cpu-T", type=float, default=1e4)
-    ap.add_argument("--gate-epochs", type=int, default=6,
+    ap.add_argument("--gate-epochs", type=int, default=24,
                     help="training epochs of the gate workload")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes (calibrates "
