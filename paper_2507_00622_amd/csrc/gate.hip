@@ -173,13 +173,13 @@ hipError_t batch_grad(chx_gate *g, const Acts &a, int B, const float *feat, cons
   // (the row kernel's outputs are feature-major with row stride B, so both
   // operands run along K = rows)
   if ((e = mlp_gemm(a.A2b, B, 1, a.dZ3b, 1, B, gr + MLP_W3, MLP_OUTP, MLP_H, MLP_OUTP, B, nullptr,
-                    0, s, a.work3, MLP_SPLITK_WORK_SMALL, EPI_NONE, nullptr, nullptr, &gp->s3)))
+                    0, s, a.work3, MLP_SPLITK_WORK_SMALL, EPI_NONE, nullptr, &gp->s3)))
     return e;
   if ((e = mlp_gemm(a.A1b, B, 1, a.dZ2b, 1, B, gr + MLP_W2, MLP_H, MLP_H, MLP_H, B, nullptr, 0, s,
-                    a.work2, MLP_SPLITK_WORK, EPI_NONE, nullptr, nullptr, &gp->s2)))
+                    a.work2, MLP_SPLITK_WORK, EPI_NONE, nullptr, &gp->s2)))
     return e;
   return mlp_gemm(a.X, B, 1, a.dZ1b, 1, B, gr + MLP_W1, MLP_H, MLP_INP, MLP_H, B, nullptr, 0, s,
-                  a.work1, MLP_SPLITK_WORK_SMALL, EPI_NONE, nullptr, nullptr, &gp->s1);
+                  a.work1, MLP_SPLITK_WORK_SMALL, EPI_NONE, nullptr, &gp->s1);
 }
 
 // p(chaotic) and confidence of n rows of device features.

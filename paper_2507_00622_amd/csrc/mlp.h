@@ -34,15 +34,13 @@ constexpr int64_t MLP_NFRAG = MLP_F_W3T + (int64_t)MLP_H * MLP_OUTP;
 
 // C = A B (+ bias) (+ C): BF16 operands at any strides, FP32 result.
 // work (work_len floats, may be null) holds split-K partial products.
-// Epilogues (no accumulate): EPI_GELU also stores GELU(C) in BF16 to Cb;
-// EPI_GELU_BACK turns the product dA into dZ = dA GELU'(Zaux) in C and
-// stores its BF16 copy to Cb (Cb, Zaux with C's row stride).
-enum { EPI_NONE = 0, EPI_GELU = 1, EPI_GELU_BACK = 2 };
+// Epilogue EPI_GELU (no accumulate): also stores GELU(C) in BF16 to Cb
+// (C's row stride).
+enum { EPI_NONE = 0, EPI_GELU = 1 };
 hipError_t mlp_gemm(const uint16_t *A, int64_t a_r, int64_t a_c, const uint16_t *B, int64_t b_r,
                     int64_t b_c, float *C, int64_t ldc, int M, int N, int K, const float *bias,
                     int accumulate, hipStream_t s, float *work = nullptr, int64_t work_len = 0,
-                    int epi = EPI_NONE, uint16_t *Cb = nullptr, const float *Zaux = nullptr,
-                    int *parts = nullptr);
+                    int epi = EPI_NONE, uint16_t *Cb = nullptr, int *parts = nullptr);
 // With parts given (no bias, no accumulate, ldc == N): a product split over
 // K leaves its parts in work[z][M][N] for the caller to add and *parts = S
 // (the number of parts); with *parts == 1 the product is in C.

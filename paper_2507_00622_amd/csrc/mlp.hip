@@ -66,10 +66,9 @@ __device__ __forceinline__ float gelu_grad(float z) {
 // and, after, D[4 (l / 16) + r][l % 16].  Split K: block z of gridDim.z
 // takes chunks [z cpc, (z + 1) cpc) and, when gridDim.z > 1, writes its
 // partial tile to work[z][M][N]; a second kernel adds the parts in order of
-// z (deterministic) with the bias and the accumulation.  Epilogues (no
-// split): EPI_GELU stores Z = AB + bias and its activation GELU(Z) in BF16
-// to Cb; EPI_GELU_BACK takes the product as dA and stores
-// dZ = dA GELU'(Zaux) and its BF16 copy to Cb (Zaux, Cb with C's row stride).
+// z (deterministic) with the bias and the accumulation.  Epilogue EPI_GELU
+// (no split): Z = AB + bias to C and its activation GELU(Z) in BF16 to Cb
+// (C's row stride).
 constexpr int GBK = 32, GPAD = GBK + 8;
 
 template <int BM, int BN, bool VEC, int EPI>
@@ -79,7 +78,7 @@ __global__ void __launch_bounds__(256) gemm_tile_kernel(const uint16_t *A, int64
                                                         int64_t ldc, int M, int N, int K,
                                                         int cpc, const float *bias,
                                                         int accumulate, float *work,
-                                                        uint16_t *Cb, const float *Zaux) {
+                                                        uint16_t *Cb) {
   // wavefronts: (64, 64) 2 x 2 of 2 x 2 tiles; (64, 16) 4 x 1 and (16, 64)
   // 1 x 4 of one tile
   constexpr int WGM = BM == 64 && BN == 64 ? 2 : (BM == 64 ? 4 : 1);
@@ -213,8 +212,8 @@ __global__ void __launch_bounds__(256) gemm_tile_kernel(const uint16_t *A, int64
         }
     return;
   }
-  // every load of the epilogue (bias, Zaux or the C accumulated onto) goes
-  // out before its first store, so one wait covers them all
+  // every load of the epilogue (bias, the C accumulated onto) goes out
+  // before its first store, so one wait covers them all
   float x[TM][TN][4];
 #pragma unroll
   for (int a = 0; a < TM; ++a)
@@ -227,8 +226,7 @@ __global__ void __launch_bounds__(256) gemm_tile_kernel(const uint16_t *A, int64
         const int i = row0 + (wm * TM + a) * 16 + lk + r;
         const int64_t e = (int64_t)i * ldc + j;
         if (bias) acc[a][b][r] += bj;
-        if constexpr (EPI == EPI_GELU_BACK) x[a][b][r] = i < M ? Zaux[e] : 0.f;
-        else if constexpr (EPI == EPI_NONE) x[a][b][r] = (accumulate && i < M) ? C[e] : 0.f;
+        if constexpr (EPI == EPI_NONE) x[a][b][r] = (accumulate && i < M) ? C[e] : 0.f;
       }
     }
 #pragma unroll
@@ -244,10 +242,6 @@ __global__ void __launch_bounds__(256) gemm_tile_kernel(const uint16_t *A, int64
         if constexpr (EPI == EPI_GELU) {
           C[e] = v;
           Cb[e] = f2bf(gelu(v));
-        } else if constexpr (EPI == EPI_GELU_BACK) {
-          const float g = v * gelu_grad(x[a][b][r]);
-          C[e] = g;
-          Cb[e] = f2bf(g);
         } else {
           C[e] = accumulate ? x[a][b][r] + v : v;
         }
@@ -831,7 +825,7 @@ inline unsigned nb(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t);
 hipError_t mlp_gemm(const uint16_t *A, int64_t a_r, int64_t a_c, const uint16_t *B, int64_t b_r,
                     int64_t b_c, float *C, int64_t ldc, int M, int N, int K, const float *bias,
                     int accumulate, hipStream_t s, float *work, int64_t work_len, int epi,
-                    uint16_t *Cb, const float *Zaux, int *parts) {
+                    uint16_t *Cb, int *parts) {
   if (M <= 0 || N <= 0 || K <= 0 || M % 16 || N % 16 || K % 16) return hipErrorInvalidValue;
   // (64, 64) tiles where N allows, (16, 64) for a 16-row product, else
   // (64, 16)
@@ -842,8 +836,7 @@ hipError_t mlp_gemm(const uint16_t *A, int64_t a_r, int64_t a_c, const uint16_t 
   // split K (a workspace given) until about 512 blocks (two per CU), each
   // part at least two chunks
   const int chunks = (K + GBK - 1) / GBK;
-  if (epi < EPI_NONE || epi > EPI_GELU_BACK ||
-      (epi != EPI_NONE && (!Cb || (epi == EPI_GELU_BACK && !Zaux) || accumulate)) ||
+  if (epi < EPI_NONE || epi > EPI_GELU || (epi == EPI_GELU && (!Cb || accumulate)) ||
       (parts && (bias || accumulate || ldc != N)))
     return hipErrorInvalidValue;
   int S = 1;
@@ -860,7 +853,7 @@ hipError_t mlp_gemm(const uint16_t *A, int64_t a_r, int64_t a_c, const uint16_t 
   const dim3 grid((unsigned)gn, (unsigned)gm, (unsigned)S);
 #define CHX_GEMM_GO(bm, bn, v, ep)                                                               \
   hipLaunchKernelGGL((gemm_tile_kernel<bm, bn, v, ep>), grid, dim3(256), 0, s, A, a_r, a_c, B,   \
-                     b_r, b_c, C, ldc, M, N, K, cpc, bias, accumulate, work, Cb, Zaux)
+                     b_r, b_c, C, ldc, M, N, K, cpc, bias, accumulate, work, Cb)
 #define CHX_GEMM_LAUNCH(bm, bn, ep)                                                              \
   do {                                                                                          \
     if (vec) CHX_GEMM_GO(bm, bn, true, ep);                                                     \
@@ -872,11 +865,9 @@ hipError_t mlp_gemm(const uint16_t *A, int64_t a_r, int64_t a_c, const uint16_t 
     CHX_GEMM_LAUNCH(64, 16, EPI_NONE);
   } else if (BM == 16) {
     if (epi == EPI_GELU) CHX_GEMM_LAUNCH(16, 64, EPI_GELU);
-    else if (epi == EPI_GELU_BACK) CHX_GEMM_LAUNCH(16, 64, EPI_GELU_BACK);
     else CHX_GEMM_LAUNCH(16, 64, EPI_NONE);
   } else {
     if (epi == EPI_GELU) CHX_GEMM_LAUNCH(64, 64, EPI_GELU);
-    else if (epi == EPI_GELU_BACK) CHX_GEMM_LAUNCH(64, 64, EPI_GELU_BACK);
     else CHX_GEMM_LAUNCH(64, 64, EPI_NONE);
   }
 #undef CHX_GEMM_LAUNCH
