@@ -33,7 +33,8 @@ constexpr int64_t MLP_F_W3T = MLP_F_W3 + (int64_t)MLP_H * MLP_OUTP;  // W3, back
 constexpr int64_t MLP_NFRAG = MLP_F_W3T + (int64_t)MLP_H * MLP_OUTP;
 
 // C = A B (+ bias) (+ C): BF16 operands at any strides, FP32 result.
-// work (work_len floats, may be null) holds split-K partial products.
+// work (work_len floats, may be null; needs parts) holds split-K partial
+// products.
 // Epilogue EPI_GELU (no accumulate): also stores GELU(C) in BF16 to Cb
 // (C's row stride).
 enum { EPI_NONE = 0, EPI_GELU = 1 };

@@ -65,8 +65,7 @@ __device__ __forceinline__ float gelu_grad(float z) {
 // and 16 k: lane l holds A[l % 16][4 (l / 16) + e], B[4 (l / 16) + e][l % 16]
 // and, after, D[4 (l / 16) + r][l % 16].  Split K: block z of gridDim.z
 // takes chunks [z cpc, (z + 1) cpc) and, when gridDim.z > 1, writes its
-// partial tile to work[z][M][N]; a second kernel adds the parts in order of
-// z (deterministic) with the bias and the accumulation.  Epilogue EPI_GELU
+// partial tile to work[z][M][N] for the caller to add in order of z.  Epilogue EPI_GELU
 // (no split): Z = AB + bias to C and its activation GELU(Z) in BF16 to Cb
 // (C's row stride).
 constexpr int GBK = 32, GPAD = GBK + 8;
@@ -262,19 +261,6 @@ __device__ __forceinline__ float ordered_sum(float t, const float *p, int64_t st
   }
   return t;
 }
-
-// C[i][j] (+)= sum_z work[z][i][j] (+ bias[j]), the parts added in order.
-__global__ void gemm_splitk_sum_kernel(const float *work, int S, int M, int N, float *C,
-                                       int64_t ldc, const float *bias, int accumulate) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)M * N) return;
-  const int i = (int)(t / N), j = (int)(t % N);
-  float v = ordered_sum<>(0.f, work + t, (int64_t)M * N, S);
-  if (bias) v += bias[j];
-  float *dst = C + (int64_t)i * ldc + j;
-  *dst = accumulate ? *dst + v : v;
-}
-
 
 // four consecutive BF16 values as one 8-byte store (p 8-byte aligned)
 __device__ __forceinline__ void store4(uint16_t *p, const uint16_t (&h)[4]) {
@@ -635,9 +621,8 @@ __global__ void zero_u64_kernel(unsigned long long *p, int n) {
 }
 
 // The gradient of one batch, entry i of g: a weight whose product was split
-// over K is the sum of its parts in order of the part (as
-// gemm_splitk_sum_kernel adds them); the other entries (unsplit products,
-// biases) are already in g.  With step set, AdamW then updates the FP32
+// over K is the sum of its parts in order of the part (deterministic); the
+// other entries (unsplit products, biases) are already in g.  With step set, AdamW then updates the FP32
 // master (entries with mask set) and its BF16 copies pb and pbF.
 __global__ void grad_step_kernel(GradParts gp, float *p, uint16_t *pb, uint16_t *pbF, float *g,
                                  float *m, float *v, const uint8_t *mask, int step, float lr,
@@ -837,7 +822,7 @@ hipError_t mlp_gemm(const uint16_t *A, int64_t a_r, int64_t a_c, const uint16_t 
   // part at least two chunks
   const int chunks = (K + GBK - 1) / GBK;
   if (epi < EPI_NONE || epi > EPI_GELU || (epi == EPI_GELU && (!Cb || accumulate)) ||
-      (parts && (bias || accumulate || ldc != N)))
+      (work && !parts) || (parts && (bias || accumulate || ldc != N)))
     return hipErrorInvalidValue;
   int S = 1;
   while (epi == EPI_NONE && work && gm * gn * S < 512 && chunks >= 4 * S &&
@@ -873,9 +858,6 @@ hipError_t mlp_gemm(const uint16_t *A, int64_t a_r, int64_t a_c, const uint16_t 
 #undef CHX_GEMM_LAUNCH
 #undef CHX_GEMM_GO
   if (parts) *parts = S;
-  else if (S > 1)
-    hipLaunchKernelGGL(gemm_splitk_sum_kernel, dim3(nb((int64_t)M * N)), dim3(256), 0, s, work, S,
-                       M, N, C, ldc, bias, accumulate);
   return hipGetLastError();
 }
 
